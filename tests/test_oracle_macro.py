@@ -1,0 +1,105 @@
+"""Pins of the oracle's macro FE-HMM driver."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import fe_ref
+
+LAME = oracle.two_phase_lame(10.0)
+
+
+def single_scale_fe(nx, ny, lam, mu, stretch, nsteps, bc):
+    """Independent dense single-scale Q1 neo-Hookean FE with the same BCs."""
+    hx, hy = 1.0 / nx, 1.0 / ny
+    nn = (nx + 1) * (ny + 1)
+    xy = np.array([[i * hx, j * hy] for j in range(ny + 1) for i in range(nx + 1)])
+    conn = np.array([[j * (nx + 1) + i, j * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i]
+                     for j in range(ny) for i in range(nx)])
+    g = 1 / np.sqrt(3)
+    sx, sy = np.array([-1, 1, 1, -1]), np.array([-1, -1, 1, 1])
+    dN = np.zeros((4, 4, 2))
+    for p, (xi, eta) in enumerate([(-g, -g), (g, -g), (g, g), (-g, g)]):
+        dN[p, :, 0] = 0.25 * sx * (1 + sy * eta) * 2 / hx
+        dN[p, :, 1] = 0.25 * sy * (1 + sx * xi) * 2 / hy
+    wdet = hx * hy / 4
+    fixed = np.zeros(2 * nn, bool)
+    for v, (x, y) in enumerate(xy):
+        if x == 0:
+            fixed[2 * v] = True
+            if bc == 0 or y == 0:
+                fixed[2 * v + 1] = True
+        if abs(x - 1) < 1e-12:
+            fixed[2 * v] = True
+    u = np.zeros(2 * nn)
+    for k in range(1, nsteps + 1):
+        u[0::2][np.abs(xy[:, 0] - 1) < 1e-12] = (stretch - 1) * k / nsteps
+        r0 = None
+        for it in range(30):
+            R = np.zeros(2 * nn); K = np.zeros((2 * nn, 2 * nn))
+            for e in conn:
+                dofs = np.ravel([[2 * a, 2 * a + 1] for a in e])
+                for p in range(4):
+                    F = np.eye(2) + np.einsum("ai,aJ->iJ", u[dofs].reshape(4, 2), dN[p])
+                    P = fe_ref.P_closed(F, lam, mu)
+                    A = fe_ref.A_closed(F, lam, mu).reshape(2, 2, 2, 2)
+                    R[dofs] += np.einsum("iJ,aJ->ai", P, dN[p]).ravel() * wdet
+                    K[np.ix_(dofs, dofs)] += np.einsum("aJ,iJkL,bL->aibk", dN[p], A, dN[p]).reshape(8, 8) * wdet
+            rn = np.linalg.norm(R[~fixed])
+            r0 = rn if r0 is None else r0
+            if rn <= 1e-12 * r0:
+                break
+            free = ~fixed
+            u[free] -= np.linalg.solve(K[np.ix_(free, free)], R[free])
+    return xy, u
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_homogeneous_rve_fe_hmm_equals_single_scale_fe(bc):
+    """e_mod = 0 for periodic coupling (Sec. 4): with a one-phase RVE the FE-HMM
+    macro solution is the single-scale FE solution of the same law."""
+    nx = ny = 3
+    n = 2
+    ph = np.zeros(n * n, np.uint8)
+    m = oracle.Macro(nx, ny, n, ph, LAME, bc=bc, stretch=1.1, nsteps=2, rtol_macro=1e-12)
+    for k in (1, 2):
+        st = m.step(k)
+        assert st["status"] == 0
+    xy_ref, u_ref = single_scale_fe(nx, ny, *LAME[0], 1.1, 2, bc)
+    xy = m.nodes()
+    u = m.u()
+    order = [int(np.argmin(np.abs(xy_ref - p).sum(axis=1))) for p in xy]
+    u_ref = u_ref.reshape(-1, 2)[order].reshape(-1)
+    assert np.abs(u - u_ref).max() < 1e-10 * np.abs(u_ref).max()
+
+
+def test_uniaxial_stretch_gives_uniform_macro_state():
+    """Roller BCs (bc 1) with free top/bottom: the homogeneous macro state is an
+    equilibrium, so every quadrature point sees the same Fbar, Pbar."""
+    n = 4
+    ph = oracle.phase_by_centroid(2, n, 0.3)
+    m = oracle.Macro(2, 2, n, ph, LAME, bc=1, stretch=1.08, nsteps=1)
+    st = m.step(1)
+    assert st["status"] == 0
+    F, P, A = m.qp()
+    assert np.abs(F - F[0]).max() < 1e-10
+    assert F[0, 0, 0] == pytest.approx(1.08, abs=1e-12)
+    # traction-free top/bottom: P_21 = P_22 = 0 on average state; P_12 = 0 by symmetry
+    assert np.abs(P[0, 1, :]).max() < 1e-10 * abs(P[0, 0, 0])
+
+
+def test_nested_newton_is_quadratic_and_alternating_agrees():
+    """Algorithm 1 (nested) converges quadratically in the macro residual; the
+    alternating Algorithm 2 reaches the same macro solution (Sec. 5)."""
+    n = 4
+    ph = oracle.phase_by_centroid(2, n, 0.25)
+    kw = dict(bc=0, stretch=1.1, nsteps=2, rtol_macro=1e-10)
+    mn = oracle.Macro(3, 3, n, ph, LAME, scheme=0, **kw)
+    ma = oracle.Macro(3, 3, n, ph, LAME, scheme=1, **kw)
+    for k in (1, 2):
+        sn = mn.step(k)
+        sa = ma.step(k)
+        assert sn["status"] == 0 and sa["status"] == 0
+        h = sn["res_hist"]
+        assert h[-1] <= 1e-10
+        assert h[-2] < 1e-3 and h[-1] <= 10 * h[-2] ** 2
+    assert np.abs(mn.u() - ma.u()).max() < 1e-7 * np.abs(mn.u()).max()
