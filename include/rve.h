@@ -1,0 +1,167 @@
+/*
+ * rve.h -- C ABI of the MI355X (gfx950) batched periodic-RVE solver of the
+ * nonlinear FE-HMM (Eidel, Fischer, Gote, arXiv:1908.08292).
+ *
+ * Problem solved per RVE (micro problem of Sec. 3.3 under periodic coupling,
+ * Sec. 3.2 eq. ConstraintCondition): on the unit cell [0,1]^d meshed by n^d
+ * bilinear quadrilaterals (d = 2, plane strain) or trilinear hexahedra (d = 3)
+ * with 2^d Gauss points each, find the periodic fluctuation w (one node pinned
+ * against rigid translation) such that the first-order coupled deformation
+ * F = Fbar + grad w (eq. linearization-uH) is in equilibrium,
+ *     R(w) = sum_e int P(F) . grad N dV = 0,
+ * with the compressible neo-Hookean law of Sec. 6 (eq. NH-free-energy).  The
+ * outputs are the volume average Pbar = <P> (eq. Average-of-P-and-F) and the
+ * consistent tangent Abar = dPbar/dFbar at the converged state, i.e. the
+ * micro-to-macro stiffness transfer T^T K T / |K_delta| of eqs.
+ * (k-mac-element-5..7) written for the d^2 unit macro-gradient states.
+ *
+ * Conventions.
+ *   - Node (i,j[,k]) of the periodic grid has id i + n j [+ n^2 k]; element
+ *     (i,j[,k]) has the same id and its centroid at ((i+1/2)/n, ...).
+ *   - F and P are row-major d x d: F[i*d + J] = F_iJ (i spatial, J material).
+ *   - A is the d^2 x d^2 row-major matrix A[(i*d+J)*d*d + (k*d+L)] = dP_iJ/dF_kL.
+ *   - Fluctuations are node-major: w[node*d + i]; node 0 is pinned (w = 0).
+ *
+ * Errors.  Every call returns an int: RVE_OK (0), a negative RVE_E* code for
+ * API/usage/device failures (nothing was computed; rve_last_error() explains),
+ * or RVE_EPARTIAL (1) from rve_solve_batch when some RVEs failed.  Per-RVE
+ * codes (RVE_S_*) go to the status array; failed RVEs get NaN P and A and their
+ * w_state is left unchanged, the rest of the batch is unaffected.
+ *
+ * Ownership.  The library owns meshes, batches and their device workspaces
+ * (freed by the *_destroy calls).  The caller owns every input/output buffer.
+ * Calls on one handle are not thread-safe.
+ */
+#ifndef FEHMM_RVE_H
+#define FEHMM_RVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------------- */
+#define RVE_OK 0
+#define RVE_EPARTIAL 1        /* some RVEs of the batch failed (see status[]) */
+#define RVE_EINVAL (-1)       /* bad argument (NULL, size, range, destroyed handle) */
+#define RVE_ENOMEM (-2)       /* host or device allocation failed */
+#define RVE_EHIP (-3)         /* a HIP runtime call failed */
+#define RVE_EUNSUPPORTED (-4) /* valid request this build does not support */
+
+/* ---- per-RVE status -------------------------------------------------------- */
+#define RVE_S_CONVERGED 0
+#define RVE_S_NOCONV 1    /* Newton did not reach the tolerance in max_iter updates */
+#define RVE_S_DETF 2      /* det F <= 0 at a Gauss point survived all step halvings */
+#define RVE_S_SINGULAR 3  /* a pivot of the LDL^T factorization vanished */
+#define RVE_S_NONFINITE 4 /* non-finite input or residual */
+
+typedef struct rve_mesh_s* rve_mesh;
+typedef struct rve_batch_s* rve_batch;
+
+/* Lame parameters from Young's modulus and Poisson's ratio (the 3D relations,
+ * also used for plane strain; the paper's material table, Sec. 6). */
+int rve_lame(double E, double nu, double* lambda_out, double* mu_out);
+
+/* ---- meshes ------------------------------------------------------------------
+ * rve_mesh_create: one periodic RVE discretisation (Sec. 3.1 micro triangulation,
+ * here a structured grid) with its phase field and material table.
+ *   ndim       2 or 3
+ *   n          elements per edge, 2 <= n <= 64 (2D) or 2 <= n <= 24 (3D)
+ *   nphase     1..255; lame: host array [nphase][2] = (lambda, mu), mu > 0
+ *   phase      host array [n^d] of phase ids (x-fastest), or NULL: then an
+ *              element is in incl_phase iff |centroid - incl_center| < incl_radius
+ *              (strict), else in phase 0.  The data are copied.
+ * The symbolic factorization plan for (ndim, n) is built on first use and shared
+ * by every mesh of that size. */
+typedef struct {
+    int32_t ndim;
+    int32_t n;
+    int32_t nphase;
+    const double* lame;
+    const uint8_t* phase;
+    double incl_center[3];
+    double incl_radius;
+    int32_t incl_phase;
+} rve_mesh_desc;
+
+int rve_mesh_create(const rve_mesh_desc* desc, rve_mesh* out);
+int rve_mesh_destroy(rve_mesh m);
+/* Copies the element phases (n^d bytes) to host memory. */
+int rve_mesh_get_phase(rve_mesh m, uint8_t* host_phase);
+
+/* ---- batches -----------------------------------------------------------------
+ * rve_batch_create: B RVEs (host array of mesh handles, sizes may differ).  The
+ * meshes must outlive the batch.  Allocates the device workspaces of the
+ * persistent solver; the device pointers are fixed for the life of the handle, so
+ * rve_solve_batch can be captured in a HIP graph.  w_state of RVE r occupies
+ * doubles [off[r], off[r+1]) with off[r+1]-off[r] = d * n_r^d. */
+int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out);
+int rve_batch_destroy(rve_batch b);
+int rve_batch_state_offsets(rve_batch b, int64_t* host_off /* [B+1] */);
+
+#define RVE_PREC_FP64 0
+#define RVE_PREC_FP32_IR 1 /* FP32 factorization, FP64 residuals + refinement */
+
+typedef struct {
+    double rtol;           /* Newton: stop when ||R_f||_2 <= rtol ||R_f^0||_2 + atol */
+    double atol;           /* < 0: per-RVE default 1e-12 * mu_max * h^(d-1) */
+    int32_t max_iter;      /* Newton updates before RVE_S_NOCONV */
+    int32_t precision;     /* RVE_PREC_* */
+    int32_t det_backtrack; /* halvings of a Newton step while some J <= 0 */
+    int32_t reserved;
+} rve_opts;
+
+/* rtol 1e-10, atol -1 (default), max_iter 25, FP64, det_backtrack 8 */
+void rve_opts_default(rve_opts* o);
+
+/* ---- the hot path ------------------------------------------------------------
+ * rve_solve_batch: solve every RVE of the batch for its macro deformation.
+ * All array arguments are DEVICE pointers owned by the caller:
+ *   F        [B][d*d]   in   macro deformation gradient per RVE (det F > 0)
+ *   P        [B][d*d]   out  Pbar
+ *   A        [B][d^4]   out  Abar = dPbar/dFbar (may be NULL: tangent skipped)
+ *   w_state  ragged     in/out warm start and converged fluctuation per RVE
+ *                       (layout from rve_batch_state_offsets); NULL: zero start,
+ *                       nothing stored
+ *   status   [B] int32  out  RVE_S_* per RVE (may be NULL)
+ *   iters    [B] int32  out  Newton updates per RVE (may be NULL)
+ * All meshes of a batch share d (rve_batch_create rejects a mix).  The call is
+ * asynchronous on hip_stream (a hipStream_t; NULL = default stream); results are
+ * valid after the stream synchronizes.  Returns RVE_OK once the work is
+ * enqueued; per-RVE failures are only visible in status[] (RVE_EPARTIAL is
+ * returned by rve_solve_batch_sync). */
+int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
+                    int32_t* iters, const rve_opts* opts, void* hip_stream);
+
+/* As rve_solve_batch, then synchronizes the stream and returns RVE_EPARTIAL if
+ * any RVE failed (status must then be non-NULL). */
+int rve_solve_batch_sync(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
+                         int32_t* iters, const rve_opts* opts, void* hip_stream);
+
+/* Algorithmic work of the last plan for (ndim, n): floating-point operations of
+ * one LDL^T factorization, nonzeros of L, front count and largest front. */
+int rve_plan_info(int32_t ndim, int32_t n, double* factor_flops, int64_t* nnz_L, int32_t* nfronts,
+                  int32_t* max_front);
+
+/* Introspection of the (ndim, n) plan, for tooling and tests (host only).
+ * sizes[6] receives the counts (fronts, rows, relind, children, kpair,
+ * kcontrib); each non-NULL array receives: fronts [nf][8] = (m, p, parent,
+ * rows_off, relind_off, child_begin, child_end, kmap_begin) in elimination
+ * (post)order, rows (global dof = node*d+comp of every front row, pivots
+ * first), relind (positions of a front's update rows in its parent front),
+ * children, kpair [.][4] = (row node, pivot node, contrib begin, count) in
+ * front-local node indices, kcontrib [.][3] = (element, local a, local b). */
+int rve_plan_export(int32_t ndim, int32_t n, int64_t* sizes, int32_t* fronts, int32_t* rows, int32_t* relind,
+                    int32_t* children, int32_t* kpair, int32_t* kcontrib);
+
+/* ---- errors ------------------------------------------------------------------ */
+const char* rve_strerror(int code);
+/* Copies the calling thread's last error message (NUL-terminated) into buf. */
+int rve_last_error(char* buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEHMM_RVE_H */

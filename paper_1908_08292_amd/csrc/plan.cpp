@@ -1,0 +1,321 @@
+// plan.cpp -- symbolic analysis shared by all RVEs of one (d, n).
+#include "plan.h"
+
+#include <algorithm>
+#include <map>
+#include <set>
+#include <stdexcept>
+
+#include "mesh_common.h"
+
+namespace fehmm {
+namespace {
+
+struct Box {
+    int lo[3], hi[3];
+    bool per[3];
+};
+
+struct NDBuilder {
+    int d, n, leaf;
+    std::vector<std::vector<int>> sup;  // supernodes in postorder
+
+    int node_id(const int* c) const {
+        int id = 0, s = 1;
+        for (int k = 0; k < d; ++k) {
+            id += (((c[k] % n) + n) % n) * s;
+            s *= n;
+        }
+        return id;
+    }
+
+    std::vector<int> nodes_of(const Box& b) const {
+        std::vector<int> out;
+        int c[3] = {0, 0, 0};
+        int lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+        for (int k = 0; k < d; ++k) { lo[k] = b.lo[k]; hi[k] = b.hi[k]; }
+        for (c[2] = lo[2]; c[2] < hi[2]; ++c[2])
+            for (c[1] = lo[1]; c[1] < hi[1]; ++c[1])
+                for (c[0] = lo[0]; c[0] < hi[0]; ++c[0]) out.push_back(node_id(c));
+        return out;
+    }
+
+    static int64_t volume(const Box& b, int d) {
+        int64_t v = 1;
+        for (int k = 0; k < d; ++k) v *= std::max(0, b.hi[k] - b.lo[k]);
+        return v;
+    }
+
+    void rec(const Box& b) {
+        int64_t vol = volume(b, d);
+        if (vol == 0) return;
+        if (vol <= leaf) {
+            sup.push_back(nodes_of(b));
+            return;
+        }
+        // cut direction: a periodic direction first, then the longest
+        int k = 0;
+        auto key = [&](int q) { return std::make_pair(b.per[q] ? 1 : 0, b.hi[q] - b.lo[q]); };
+        for (int q = 1; q < d; ++q)
+            if (key(q) > key(k)) k = q;
+        int size = b.hi[k] - b.lo[k];
+        if (b.per[k]) {
+            int a = b.lo[k], c = b.lo[k] + size / 2;
+            Box b1 = b, b2 = b;
+            b1.lo[k] = a + 1; b1.hi[k] = c; b1.per[k] = false;
+            b2.lo[k] = c + 1; b2.hi[k] = b.hi[k]; b2.per[k] = false;
+            rec(b1);
+            rec(b2);
+            Box s1 = b, s2 = b;
+            s1.lo[k] = a; s1.hi[k] = a + 1; s1.per[k] = false;
+            s2.lo[k] = c; s2.hi[k] = c + 1; s2.per[k] = false;
+            std::vector<int> sep = nodes_of(s1);
+            if (c != a) {
+                std::vector<int> t = nodes_of(s2);
+                sep.insert(sep.end(), t.begin(), t.end());
+            }
+            sup.push_back(sep);
+        } else {
+            int mid = b.lo[k] + size / 2;
+            Box b1 = b, b2 = b, s = b;
+            b1.hi[k] = mid;
+            b2.lo[k] = mid + 1;
+            s.lo[k] = mid; s.hi[k] = mid + 1;
+            rec(b1);
+            rec(b2);
+            sup.push_back(nodes_of(s));
+        }
+    }
+};
+
+std::vector<int> periodic_neighbours(int d, int n, int v) {
+    int nb = 1;
+    for (int k = 0; k < d; ++k) nb *= 3;
+    int c[3] = {0, 0, 0}, t = v;
+    for (int k = 0; k < d; ++k) { c[k] = t % n; t /= n; }
+    std::vector<int> out;
+    for (int o = 0; o < nb; ++o) {
+        int oo = o, id = 0, s = 1;
+        for (int k = 0; k < d; ++k) {
+            int dk = oo % 3 - 1;
+            oo /= 3;
+            id += ((c[k] + dk + n) % n) * s;
+            s *= n;
+        }
+        out.push_back(id);
+    }
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+    return out;
+}
+
+// parent of every supernode (owner of the earliest node of its structure)
+std::vector<int> supernode_parents(int d, int n, const std::vector<std::vector<int>>& sup) {
+    int nn = 1;
+    for (int k = 0; k < d; ++k) nn *= n;
+    const int ns = (int)sup.size();
+    std::vector<int> pos(nn, -1), owner(nn, -1), endp(ns);
+    int cur = 0;
+    for (int s = 0; s < ns; ++s) {
+        for (int v : sup[s]) { pos[v] = cur++; owner[v] = s; }
+        endp[s] = cur;
+    }
+    std::vector<std::set<int>> st(ns);
+    std::vector<int> parent(ns, -1);
+    std::vector<int> node_at(cur);
+    for (int v = 0; v < nn; ++v) if (pos[v] >= 0) node_at[pos[v]] = v;
+    for (int s = 0; s < ns; ++s) {
+        for (int v : sup[s])
+            for (int u : periodic_neighbours(d, n, v))
+                if (pos[u] >= endp[s]) st[s].insert(pos[u]);
+        if (!st[s].empty()) {
+            int par = owner[node_at[*st[s].begin()]];
+            parent[s] = par;
+            for (int q : st[s])
+                if (q >= endp[par]) st[par].insert(q);
+        }
+    }
+    return parent;
+}
+
+std::vector<std::vector<int>> postorder(const std::vector<std::vector<int>>& sup, const std::vector<int>& parent) {
+    const int ns = (int)sup.size();
+    std::vector<std::vector<int>> kids(ns);
+    std::vector<int> roots;
+    for (int s = 0; s < ns; ++s) {
+        if (parent[s] < 0) roots.push_back(s);
+        else kids[parent[s]].push_back(s);
+    }
+    std::vector<std::vector<int>> out;
+    // iterative DFS: children in their original order, node after its children
+    std::vector<std::pair<int, size_t>> stk;
+    for (int r : roots) {
+        stk.push_back({r, 0});
+        while (!stk.empty()) {
+            auto& top = stk.back();
+            if (top.second < kids[top.first].size()) {
+                int c = kids[top.first][top.second++];
+                stk.push_back({c, 0});
+            } else {
+                out.push_back(sup[top.first]);
+                stk.pop_back();
+            }
+        }
+    }
+    return out;
+}
+
+}  // namespace
+
+PlanHost build_plan(int d, int n) {
+    if (!(d == 2 || d == 3) || n < 2) throw std::runtime_error("unsupported mesh size");
+    PlanHost P;
+    P.d = d;
+    P.n = n;
+    int nn = 1;
+    for (int k = 0; k < d; ++k) nn *= n;
+    P.nnode = nn;
+    P.nelem = nn;
+    P.nfree = d * (nn - 1);
+
+    NDBuilder nd{d, n, d == 2 ? 16 : 27, {}};
+    Box root;
+    for (int k = 0; k < 3; ++k) { root.lo[k] = 0; root.hi[k] = (k < d) ? n : 1; root.per[k] = k < d; }
+    nd.rec(root);
+
+    // drop the pinned node 0
+    std::vector<std::vector<int>> sup0;
+    for (auto& s : nd.sup) {
+        std::vector<int> t;
+        for (int v : s) if (v != 0) t.push_back(v);
+        if (!t.empty()) sup0.push_back(t);
+    }
+    // the supernodal tree of the dissection order, then a depth-first postorder
+    // of it, so that each front's children sit on top of the update stack
+    std::vector<int> par0 = supernode_parents(d, n, sup0);
+    std::vector<std::vector<int>> sup = postorder(sup0, par0);
+    const int ns = (int)sup.size();
+    std::vector<int> pos(nn, -1), owner(nn, -1), first(ns), endp(ns);
+    int cur = 0;
+    for (int s = 0; s < ns; ++s) {
+        first[s] = cur;
+        for (int v : sup[s]) { pos[v] = cur++; owner[v] = s; }
+        endp[s] = cur;
+    }
+    if (cur != nn - 1) throw std::runtime_error("nested dissection lost nodes");
+
+    auto neighbours = [&](int v) { return periodic_neighbours(d, n, v); };
+
+    std::vector<int> node_at(nn - 1);
+    for (int v = 1; v < nn; ++v) node_at[pos[v]] = v;
+    auto node_at_pos = [&](int q) { return node_at[q]; };
+
+    // symbolic factorization over supernodes (structures kept as sorted positions)
+    std::vector<std::set<int>> st(ns);
+    std::vector<int> parent(ns, -1);
+    std::vector<std::vector<int>> kids(ns);
+    for (int s = 0; s < ns; ++s) {
+        for (int v : sup[s])
+            for (int u : neighbours(v))
+                if (u != 0 && pos[u] >= endp[s]) st[s].insert(pos[u]);
+        for (int c : kids[s])
+            for (int q : st[c])
+                if (q >= endp[s]) st[s].insert(q);
+        if (!st[s].empty()) {
+            int par = owner[node_at_pos(*st[s].begin())];
+            parent[s] = par;
+            kids[par].push_back(s);
+        }
+    }
+    P.fronts.resize(ns);
+    int64_t Loff = 0, top = 0, maxtop = 0, scratch = 0;
+    for (int s = 0; s < ns; ++s) {
+        FrontHost& F = P.fronts[s];
+        int pn = (int)sup[s].size();
+        std::vector<int> fnodes(sup[s].begin(), sup[s].end());
+        std::sort(fnodes.begin(), fnodes.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+        for (int q : st[s]) fnodes.push_back(node_at[q]);
+        F.m = (int)fnodes.size() * d;
+        F.p = pn * d;
+        F.parent = parent[s];
+        F.rows_off = (int64_t)P.rows.size();
+        for (int v : fnodes)
+            for (int k = 0; k < d; ++k) P.rows.push_back(v * d + k);
+        // front-local node index
+        std::map<int, int> loc;
+        for (int i = 0; i < (int)fnodes.size(); ++i) loc[fnodes[i]] = i;
+        // children and their relind into this front
+        F.child_begin = (int)P.children.size();
+        for (int c : kids[s]) P.children.push_back(c);
+        F.child_end = (int)P.children.size();
+        for (int c : kids[s]) {
+            FrontHost& C = P.fronts[c];
+            C.relind_off = (int64_t)P.relind.size();
+            for (int q : st[c]) {
+                auto it = loc.find(node_at[q]);
+                if (it == loc.end()) throw std::runtime_error("child structure not in parent front");
+                for (int k = 0; k < d; ++k) P.relind.push_back(it->second * d + k);
+            }
+        }
+        // original entries: pivot node a, neighbour b eliminated no earlier than a
+        F.kmap_begin = (int)P.kpair.size();
+        for (int ia = 0; ia < pn; ++ia) {
+            int a = fnodes[ia];
+            for (int b : neighbours(a)) {
+                if (b == 0 || pos[b] < pos[a]) continue;
+                KPair kp;
+                kp.row_node = loc.at(b);
+                kp.col_node = ia;
+                kp.c_begin = (int)P.kcontrib.size();
+                // elements containing a: a is local node la of element (a - offset(la))
+                for (int la = 0; la < (1 << d); ++la) {
+                    int e = element_of_node(d, n, a, la);
+                    int en[8];
+                    element_nodes(d, n, e, en);
+                    for (int lb = 0; lb < (1 << d); ++lb)
+                        if (en[lb] == b) P.kcontrib.push_back(KContrib{e, la, lb, 0});
+                }
+                kp.c_count = (int)P.kcontrib.size() - kp.c_begin;
+                P.kpair.push_back(kp);
+            }
+        }
+        F.kmap_end = (int)P.kpair.size();
+        // storage
+        F.L_off = Loff;
+        Loff += (int64_t)F.m * F.p;
+        F.D_off = Loff;
+        Loff += F.p;
+        F.y_off = Loff;
+        Loff += (int64_t)F.p * kMaxNrhs;
+        int64_t usz = (int64_t)(F.m - F.p) * (F.m - F.p) + (int64_t)(F.m - F.p) * kMaxNrhs;
+        scratch = std::max(scratch, usz);
+        // update-matrix stack: children are the top entries; U_s replaces them
+        if (F.child_end > F.child_begin) {
+            int64_t expect = P.fronts[P.children[F.child_begin]].U_off;
+            for (int q = F.child_begin; q < F.child_end; ++q) {
+                const FrontHost& C = P.fronts[P.children[q]];
+                if (C.U_off != expect) throw std::runtime_error("children are not on top of the update stack");
+                expect += (int64_t)(C.m - C.p) * (C.m - C.p) + (int64_t)(C.m - C.p) * kMaxNrhs;
+            }
+            if (expect != top) throw std::runtime_error("update stack out of order");
+            top = P.fronts[P.children[F.child_begin]].U_off;
+        }
+        F.U_off = top;
+        top += usz;
+        maxtop = std::max(maxtop, top);
+        P.max_m = std::max(P.max_m, F.m);
+        P.max_p = std::max(P.max_p, F.p);
+        for (int j = 0; j < F.p; ++j) {
+            double r = F.m - j - 1;
+            P.factor_flops += r * (r + 2.0);
+            P.nnz_L += F.m - j;
+        }
+    }
+    if (P.fronts.back().parent != -1) throw std::runtime_error("plan root is not last");
+    P.L_size = Loff;
+    P.U_stack = maxtop;
+    P.U_scratch = scratch;
+    return P;
+}
+
+}  // namespace fehmm

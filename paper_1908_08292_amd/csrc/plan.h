@@ -1,0 +1,64 @@
+// plan.h -- symbolic factorization plan of the periodic RVE stiffness matrix.
+//
+// The sparsity of the free-free tangent K_ff depends only on (d, n): every node
+// couples to its 3^d periodic neighbours and node 0 is pinned.  One plan per
+// (d, n) therefore serves every RVE of that size.  The plan holds a geometric
+// nested-dissection ordering of the periodic grid (two parallel planes cut a
+// periodic direction, one plane cuts an open one), the supernodal elimination
+// tree with one dense front per separator / leaf box, the maps that assemble
+// element matrices and children's update matrices into each front, and the
+// per-slot workspace layout of the batched multifrontal LDL^T.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace fehmm {
+
+constexpr int kMaxNrhs = 9;  // d^2 right-hand sides of the tangent condensation (3D)
+
+struct FrontHost {
+    int m = 0, p = 0;           // dofs in the front, pivot dofs (leading)
+    int parent = -1;
+    int64_t rows_off = 0;       // into rows[]: m global dof ids (node*d + comp)
+    int64_t relind_off = 0;     // into relind[]: (m-p) positions in the parent front
+    int64_t L_off = 0;          // panel m x p, column-major, leading dimension m
+    int64_t D_off = 0;          // p pivots
+    int64_t y_off = 0;          // p x kMaxNrhs forward-substituted right-hand sides
+    int64_t U_off = 0;          // update matrix (m-p)^2 + (m-p)*kMaxNrhs on the stack
+    int child_begin = 0, child_end = 0;  // into children[]
+    int kmap_begin = 0, kmap_end = 0;    // into kpair[]
+};
+
+// original-matrix block K(b, a) of a pivot node a: d x d block at front rows of
+// node b (row_node) and pivot node a (col_node), sum over contributions
+struct KPair {
+    int32_t row_node;  // front-local node index of b (row block = row_node*d)
+    int32_t col_node;  // front-local node index of a (< p/d)
+    int32_t c_begin, c_count;  // into kcontrib[]
+};
+
+struct KContrib {
+    int32_t elem;      // element id
+    int32_t la, lb;    // local node numbers of a and b in that element
+    int32_t pad;
+};
+
+struct PlanHost {
+    int d = 0, n = 0;
+    int nnode = 0, nelem = 0, nfree = 0;
+    std::vector<FrontHost> fronts;     // postorder (children before parents)
+    std::vector<int32_t> rows, relind, children;
+    std::vector<KPair> kpair;
+    std::vector<KContrib> kcontrib;
+    int64_t L_size = 0;        // doubles of L + D + y storage
+    int64_t U_stack = 0;       // doubles of the update-matrix stack
+    int64_t U_scratch = 0;     // doubles of the largest update matrix (+ rhs)
+    int max_m = 0, max_p = 0;
+    double factor_flops = 0;   // LDL^T flops of one factorization (fronts, exact)
+    int64_t nnz_L = 0;
+};
+
+// Builds the plan; throws std::runtime_error on unsupported (d, n).
+PlanHost build_plan(int d, int n);
+
+}  // namespace fehmm

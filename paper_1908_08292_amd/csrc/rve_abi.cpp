@@ -1,0 +1,478 @@
+// rve_abi.cpp -- C ABI of the batched RVE solver (include/rve.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/rve.h"
+#include "plan.h"
+#include "solver_dev.h"
+
+namespace fehmm {
+hipError_t launch_rve_solve(const SolveArgs& a, int nslots, hipStream_t stream);
+}
+
+using namespace fehmm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_OR(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return fail(RVE_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- plan cache
+struct PlanEntry {
+    PlanHost host;
+    DevPlan dev{};          // device pointers inside
+    DevFront* d_fronts = nullptr;
+    int32_t* d_rows = nullptr;
+    int32_t* d_relind = nullptr;
+    int32_t* d_children = nullptr;
+    KPair* d_kpair = nullptr;
+    KContrib* d_kcontrib = nullptr;
+    int refs = 0;
+    int device = -1;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, int>, std::unique_ptr<PlanEntry>> g_plans;
+
+template <typename T>
+int upload(const std::vector<T>& v, T** out) {
+    size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+    HIP_OR(hipMalloc((void**)out, bytes));
+    if (!v.empty()) HIP_OR(hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return RVE_OK;
+}
+
+void free_plan_dev(PlanEntry& e) {
+    (void)hipFree(e.d_fronts); (void)hipFree(e.d_rows); (void)hipFree(e.d_relind);
+    (void)hipFree(e.d_children); (void)hipFree(e.d_kpair); (void)hipFree(e.d_kcontrib);
+    e.d_fronts = nullptr;
+}
+
+int get_plan(int d, int n, PlanEntry** out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(d, n);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        *out = it->second.get();
+        return RVE_OK;
+    }
+    auto e = std::make_unique<PlanEntry>();
+    try {
+        e->host = build_plan(d, n);
+    } catch (const std::exception& ex) {
+        return fail(RVE_EINVAL, std::string("plan: ") + ex.what());
+    }
+    *out = e.get();
+    g_plans[key] = std::move(e);
+    return RVE_OK;
+}
+
+int plan_device(PlanEntry* e) {
+    if (e->d_fronts) return RVE_OK;
+    const PlanHost& P = e->host;
+    std::vector<DevFront> fr(P.fronts.size());
+    for (size_t s = 0; s < fr.size(); ++s) {
+        const FrontHost& f = P.fronts[s];
+        fr[s] = DevFront{f.m, f.p, f.parent, f.child_begin, f.child_end, f.kmap_begin, f.kmap_end, 0,
+                         f.rows_off, f.relind_off, f.L_off, f.D_off, f.y_off, f.U_off};
+    }
+    int st;
+    if ((st = upload(fr, &e->d_fronts)) || (st = upload(P.rows, &e->d_rows)) || (st = upload(P.relind, &e->d_relind)) ||
+        (st = upload(P.children, &e->d_children)) || (st = upload(P.kpair, &e->d_kpair)) ||
+        (st = upload(P.kcontrib, &e->d_kcontrib))) {
+        free_plan_dev(*e);
+        return st;
+    }
+    e->dev = DevPlan{P.d, P.n, P.nnode, P.nelem, (int32_t)P.fronts.size(), 0,
+                     e->d_fronts, e->d_rows, e->d_relind, e->d_children, e->d_kpair, e->d_kcontrib};
+    return RVE_OK;
+}
+
+}  // namespace
+
+struct rve_mesh_s {
+    int d = 0, n = 0, nphase = 0;
+    std::vector<double> lame;
+    std::vector<uint8_t> phase;
+    PlanEntry* plan = nullptr;
+    double mu_max = 0;
+    bool alive = true;
+};
+
+struct rve_batch_s {
+    int d = 0;
+    int64_t B = 0;
+    int nslots = 0;
+    SlotLayout lay{};
+    std::vector<int64_t> state_off;
+    // device
+    DevPlan* d_plans = nullptr;
+    int32_t* d_rve_plan = nullptr;
+    int64_t* d_rve_phase = nullptr;
+    uint8_t* d_phase_pool = nullptr;
+    int32_t* d_rve_lame = nullptr;
+    double* d_lame_pool = nullptr;
+    int64_t* d_state_off = nullptr;
+    double* d_atol = nullptr;
+    int32_t* d_order = nullptr;
+    double* d_ws = nullptr;
+    unsigned int* d_counter = nullptr;
+    bool alive = true;
+};
+
+extern "C" {
+
+int rve_lame(double E, double nu, double* lam, double* mu) {
+    if (!lam || !mu) return fail(RVE_EINVAL, "rve_lame: NULL output");
+    if (!(E > 0) || !(nu > -1.0 && nu < 0.5)) return fail(RVE_EINVAL, "rve_lame: need E > 0 and -1 < nu < 0.5");
+    *lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    *mu = E / (2.0 * (1.0 + nu));
+    return RVE_OK;
+}
+
+void rve_opts_default(rve_opts* o) {
+    if (!o) return;
+    o->rtol = 1e-10;
+    o->atol = -1.0;
+    o->max_iter = 25;
+    o->precision = RVE_PREC_FP64;
+    o->det_backtrack = 8;
+    o->reserved = 0;
+}
+
+const char* rve_strerror(int code) {
+    switch (code) {
+        case RVE_OK: return "ok";
+        case RVE_EPARTIAL: return "some RVEs failed (see status)";
+        case RVE_EINVAL: return "invalid argument";
+        case RVE_ENOMEM: return "out of memory";
+        case RVE_EHIP: return "HIP runtime error";
+        case RVE_EUNSUPPORTED: return "unsupported";
+        default: return "unknown error";
+    }
+}
+
+int rve_last_error(char* buf, size_t n) {
+    if (!buf || n == 0) return RVE_EINVAL;
+    std::snprintf(buf, n, "%s", g_err.c_str());
+    return RVE_OK;
+}
+
+int rve_plan_info(int32_t ndim, int32_t n, double* flops, int64_t* nnz, int32_t* nfronts, int32_t* max_front) {
+    PlanEntry* e = nullptr;
+    int st = get_plan(ndim, n, &e);
+    if (st) return st;
+    if (flops) *flops = e->host.factor_flops;
+    if (nnz) *nnz = e->host.nnz_L;
+    if (nfronts) *nfronts = (int32_t)e->host.fronts.size();
+    if (max_front) *max_front = e->host.max_m;
+    return RVE_OK;
+}
+
+int rve_mesh_create(const rve_mesh_desc* d, rve_mesh* out) {
+    if (!d || !out) return fail(RVE_EINVAL, "rve_mesh_create: NULL argument");
+    *out = nullptr;
+    if (!(d->ndim == 2 || d->ndim == 3)) return fail(RVE_EINVAL, "rve_mesh_create: ndim must be 2 or 3");
+    const int nmax = d->ndim == 2 ? 64 : 24;
+    if (d->n < 2 || d->n > nmax) return fail(RVE_EINVAL, "rve_mesh_create: n out of range");
+    if (d->nphase < 1 || d->nphase > 255 || !d->lame) return fail(RVE_EINVAL, "rve_mesh_create: bad phase table");
+    for (int q = 0; q < d->nphase; ++q) {
+        double lam = d->lame[2 * q], mu = d->lame[2 * q + 1];
+        if (!std::isfinite(lam) || !std::isfinite(mu) || !(mu > 0))
+            return fail(RVE_EINVAL, "rve_mesh_create: lame parameters must be finite with mu > 0");
+    }
+    auto m = std::make_unique<rve_mesh_s>();
+    m->d = d->ndim;
+    m->n = d->n;
+    m->nphase = d->nphase;
+    m->lame.assign(d->lame, d->lame + 2 * d->nphase);
+    int ne = 1;
+    for (int k = 0; k < m->d; ++k) ne *= m->n;
+    m->phase.resize(ne);
+    if (d->phase) {
+        for (int e = 0; e < ne; ++e) {
+            if (d->phase[e] >= d->nphase) return fail(RVE_EINVAL, "rve_mesh_create: phase id >= nphase");
+            m->phase[e] = d->phase[e];
+        }
+    } else {
+        if (d->incl_phase < 0 || d->incl_phase >= d->nphase)
+            return fail(RVE_EINVAL, "rve_mesh_create: incl_phase out of range");
+        const double h = 1.0 / m->n;
+        for (int e = 0; e < ne; ++e) {
+            int t = e;
+            double r2 = 0;
+            for (int k = 0; k < m->d; ++k) {
+                double x = ((t % m->n) + 0.5) * h - d->incl_center[k];
+                r2 += x * x;
+                t /= m->n;
+            }
+            m->phase[e] = (std::sqrt(r2) < d->incl_radius) ? (uint8_t)d->incl_phase : 0;
+        }
+    }
+    for (int q = 0; q < m->nphase; ++q) m->mu_max = std::max(m->mu_max, m->lame[2 * q + 1]);
+    int st = get_plan(m->d, m->n, &m->plan);
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        m->plan->refs++;
+    }
+    *out = m.release();
+    return RVE_OK;
+}
+
+int rve_mesh_destroy(rve_mesh m) {
+    if (!m || !m->alive) return fail(RVE_EINVAL, "rve_mesh_destroy: invalid handle");
+    m->alive = false;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (--m->plan->refs == 0) {
+            free_plan_dev(*m->plan);
+            g_plans.erase(std::make_pair(m->d, m->n));
+        }
+    }
+    // the husk stays allocated so that a second destroy is detected
+    m->lame.clear();
+    m->phase.clear();
+    return RVE_OK;
+}
+
+int rve_mesh_get_phase(rve_mesh m, uint8_t* host_phase) {
+    if (!m || !m->alive || !host_phase) return fail(RVE_EINVAL, "rve_mesh_get_phase: invalid argument");
+    std::memcpy(host_phase, m->phase.data(), m->phase.size());
+    return RVE_OK;
+}
+
+static void free_batch(rve_batch_s* b) {
+    (void)hipFree(b->d_plans); (void)hipFree(b->d_rve_plan); (void)hipFree(b->d_rve_phase); (void)hipFree(b->d_phase_pool);
+    (void)hipFree(b->d_rve_lame); (void)hipFree(b->d_lame_pool); (void)hipFree(b->d_state_off); (void)hipFree(b->d_atol);
+    (void)hipFree(b->d_order); (void)hipFree(b->d_ws); (void)hipFree(b->d_counter);
+    b->d_ws = nullptr;
+}
+
+int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
+    if (!meshes || !out || B <= 0) return fail(RVE_EINVAL, "rve_batch_create: invalid argument");
+    *out = nullptr;
+    for (int64_t r = 0; r < B; ++r)
+        if (!meshes[r] || !meshes[r]->alive) return fail(RVE_EINVAL, "rve_batch_create: invalid mesh handle");
+    const int d = meshes[0]->d;
+    for (int64_t r = 0; r < B; ++r)
+        if (meshes[r]->d != d) return fail(RVE_EUNSUPPORTED, "rve_batch_create: all meshes of a batch must share ndim");
+    auto b = std::make_unique<rve_batch_s>();
+    b->d = d;
+    b->B = B;
+    // distinct plans and meshes
+    std::vector<PlanEntry*> plans;
+    std::map<PlanEntry*, int> plan_id;
+    std::map<rve_mesh, std::pair<int64_t, int32_t>> mesh_off;  // phase offset, lame offset
+    std::vector<uint8_t> phase_pool;
+    std::vector<double> lame_pool;
+    std::vector<int32_t> rve_plan(B), rve_lame(B);
+    std::vector<int64_t> rve_phase(B);
+    std::vector<double> atol(B);
+    b->state_off.resize(B + 1);
+    b->state_off[0] = 0;
+    std::vector<double> cost(B);
+    for (int64_t r = 0; r < B; ++r) {
+        rve_mesh m = meshes[r];
+        if (!plan_id.count(m->plan)) {
+            plan_id[m->plan] = (int)plans.size();
+            plans.push_back(m->plan);
+        }
+        auto it = mesh_off.find(m);
+        if (it == mesh_off.end()) {
+            std::pair<int64_t, int32_t> off((int64_t)phase_pool.size(), (int32_t)lame_pool.size());
+            phase_pool.insert(phase_pool.end(), m->phase.begin(), m->phase.end());
+            lame_pool.insert(lame_pool.end(), m->lame.begin(), m->lame.end());
+            it = mesh_off.emplace(m, off).first;
+        }
+        rve_plan[r] = plan_id[m->plan];
+        rve_phase[r] = it->second.first;
+        rve_lame[r] = it->second.second;
+        atol[r] = 1e-12 * m->mu_max * std::pow(1.0 / m->n, d - 1);
+        b->state_off[r + 1] = b->state_off[r] + (int64_t)d * m->plan->host.nnode;
+        cost[r] = m->plan->host.factor_flops;
+    }
+    std::vector<int32_t> order(B);
+    for (int64_t r = 0; r < B; ++r) order[r] = (int32_t)r;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+    // workspace layout: max over the distinct plans
+    int64_t nn = 0, ne = 0, Lsz = 0, Ust = 0, Usc = 0;
+    const int nen = 1 << d, nd = nen * d, d2 = d * d;
+    for (PlanEntry* p : plans) {
+        int st = plan_device(p);
+        if (st) return st;
+        nn = std::max<int64_t>(nn, p->host.nnode);
+        ne = std::max<int64_t>(ne, p->host.nelem);
+        Lsz = std::max(Lsz, p->host.L_size);
+        Ust = std::max(Ust, p->host.U_stack);
+        Usc = std::max(Usc, p->host.U_scratch);
+    }
+    auto rnd = [](int64_t x) { return (x + 31) / 32 * 32; };
+    SlotLayout& L = b->lay;
+    int64_t o = 0;
+    L.w = o; o += rnd(nn * d);
+    L.wt = o; o += rnd(nn * d);
+    L.R = o; o += rnd(nn * d);
+    L.rhs = o; o += rnd(nn * d * d2);
+    L.x = o; o += rnd(nn * d);
+    L.fe = o; o += rnd(ne * nd);
+    L.ke = o; o += rnd(ne * nd * nd);
+    L.re = o; o += rnd(ne * nd * d2);
+    L.L = o; o += rnd(Lsz);
+    L.U = o; o += rnd(std::max<int64_t>(Ust, 1));
+    L.S = o; o += rnd(std::max<int64_t>(Usc, 1));
+    L.stride = o;
+    size_t free_b = 0, total_b = 0;
+    HIP_OR(hipMemGetInfo(&free_b, &total_b));
+    const double slot_bytes = (double)L.stride * sizeof(double);
+    int64_t cap = (int64_t)(0.5 * (double)free_b / slot_bytes);
+    int64_t nslots = std::min<int64_t>({B, (int64_t)1024, cap});
+    if (nslots < 1) return fail(RVE_ENOMEM, "rve_batch_create: not enough device memory for one workspace slot");
+    b->nslots = (int)nslots;
+    std::vector<DevPlan> dplans;
+    for (PlanEntry* p : plans) dplans.push_back(p->dev);
+    int st;
+    if ((st = upload(dplans, &b->d_plans)) || (st = upload(rve_plan, &b->d_rve_plan)) ||
+        (st = upload(rve_phase, &b->d_rve_phase)) || (st = upload(phase_pool, &b->d_phase_pool)) ||
+        (st = upload(rve_lame, &b->d_rve_lame)) || (st = upload(lame_pool, &b->d_lame_pool)) ||
+        (st = upload(b->state_off, &b->d_state_off)) || (st = upload(atol, &b->d_atol)) ||
+        (st = upload(order, &b->d_order))) {
+        free_batch(b.get());
+        return st;
+    }
+    hipError_t e1 = hipMalloc((void**)&b->d_ws, (size_t)L.stride * nslots * sizeof(double));
+    hipError_t e2 = hipMalloc((void**)&b->d_counter, 256);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        free_batch(b.get());
+        return fail(RVE_ENOMEM, "rve_batch_create: workspace allocation failed");
+    }
+    *out = b.release();
+    return RVE_OK;
+}
+
+int rve_batch_destroy(rve_batch b) {
+    if (!b || !b->alive) return fail(RVE_EINVAL, "rve_batch_destroy: invalid handle");
+    free_batch(b);
+    b->alive = false;
+    return RVE_OK;
+}
+
+int rve_batch_state_offsets(rve_batch b, int64_t* host_off) {
+    if (!b || !b->alive || !host_off) return fail(RVE_EINVAL, "rve_batch_state_offsets: invalid argument");
+    std::memcpy(host_off, b->state_off.data(), sizeof(int64_t) * (b->B + 1));
+    return RVE_OK;
+}
+
+int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
+                    int32_t* iters, const rve_opts* opts, void* hip_stream) {
+    if (!b || !b->alive) return fail(RVE_EINVAL, "rve_solve_batch: invalid batch handle");
+    if (!F || !P) return fail(RVE_EINVAL, "rve_solve_batch: F and P are required");
+    rve_opts o;
+    rve_opts_default(&o);
+    if (opts) o = *opts;
+    if (!(o.rtol >= 0) || o.max_iter < 0 || o.max_iter > 1000 || o.det_backtrack < 0 || o.det_backtrack > 60)
+        return fail(RVE_EINVAL, "rve_solve_batch: options out of range");
+    if (o.precision != RVE_PREC_FP64 && o.precision != RVE_PREC_FP32_IR)
+        return fail(RVE_EINVAL, "rve_solve_batch: unknown precision");
+    if (o.precision != RVE_PREC_FP64) return fail(RVE_EUNSUPPORTED, "rve_solve_batch: FP32_IR not built yet");
+    SolveArgs a{};
+    a.plans = b->d_plans;
+    a.rve_plan = b->d_rve_plan;
+    a.rve_phase = b->d_rve_phase;
+    a.phase_pool = b->d_phase_pool;
+    a.rve_lame = b->d_rve_lame;
+    a.lame_pool = b->d_lame_pool;
+    a.state_off = b->d_state_off;
+    a.rve_atol = b->d_atol;
+    a.order = b->d_order;
+    a.B = b->B;
+    a.ws = b->d_ws;
+    a.lay = b->lay;
+    a.counter = b->d_counter;
+    a.F = F;
+    a.P = P;
+    a.A = A;
+    a.wstate = w_state;
+    a.status = status;
+    a.iters = iters;
+    a.rtol = o.rtol;
+    a.atol = o.atol;
+    a.max_iter = o.max_iter;
+    a.backtrack = o.det_backtrack;
+    a.want_A = A != nullptr;
+    a.dim = b->d;
+    hipError_t e = launch_rve_solve(a, b->nslots, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(RVE_EHIP, std::string("rve_solve_batch launch: ") + hipGetErrorString(e));
+    return RVE_OK;
+}
+
+int rve_solve_batch_sync(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
+                         int32_t* iters, const rve_opts* opts, void* hip_stream) {
+    if (!status) return fail(RVE_EINVAL, "rve_solve_batch_sync: status is required");
+    int st = rve_solve_batch(b, F, P, A, w_state, status, iters, opts, hip_stream);
+    if (st) return st;
+    HIP_OR(hipStreamSynchronize((hipStream_t)hip_stream));
+    std::vector<int32_t> h(b->B);
+    HIP_OR(hipMemcpy(h.data(), status, sizeof(int32_t) * b->B, hipMemcpyDeviceToHost));
+    for (int32_t s : h)
+        if (s != RVE_S_CONVERGED) return RVE_EPARTIAL;
+    return RVE_OK;
+}
+
+}  // extern "C"
+
+extern "C" int rve_plan_export(int32_t ndim, int32_t n, int64_t* sizes, int32_t* fronts, int32_t* rows,
+                               int32_t* relind, int32_t* children, int32_t* kpair, int32_t* kcontrib) {
+    PlanEntry* e = nullptr;
+    int st = get_plan(ndim, n, &e);
+    if (st) return st;
+    const PlanHost& P = e->host;
+    if (!sizes) return fail(RVE_EINVAL, "rve_plan_export: sizes is required");
+    sizes[0] = (int64_t)P.fronts.size();
+    sizes[1] = (int64_t)P.rows.size();
+    sizes[2] = (int64_t)P.relind.size();
+    sizes[3] = (int64_t)P.children.size();
+    sizes[4] = (int64_t)P.kpair.size();
+    sizes[5] = (int64_t)P.kcontrib.size();
+    if (fronts)
+        for (size_t s = 0; s < P.fronts.size(); ++s) {
+            const FrontHost& f = P.fronts[s];
+            int32_t* o = fronts + 8 * s;
+            o[0] = f.m; o[1] = f.p; o[2] = f.parent; o[3] = (int32_t)f.rows_off; o[4] = (int32_t)f.relind_off;
+            o[5] = f.child_begin; o[6] = f.child_end; o[7] = f.kmap_begin;
+        }
+    if (rows) std::memcpy(rows, P.rows.data(), P.rows.size() * sizeof(int32_t));
+    if (relind) std::memcpy(relind, P.relind.data(), P.relind.size() * sizeof(int32_t));
+    if (children) std::memcpy(children, P.children.data(), P.children.size() * sizeof(int32_t));
+    if (kpair)
+        for (size_t q = 0; q < P.kpair.size(); ++q) {
+            kpair[4 * q] = P.kpair[q].row_node; kpair[4 * q + 1] = P.kpair[q].col_node;
+            kpair[4 * q + 2] = P.kpair[q].c_begin; kpair[4 * q + 3] = P.kpair[q].c_count;
+        }
+    if (kcontrib)
+        for (size_t q = 0; q < P.kcontrib.size(); ++q) {
+            kcontrib[3 * q] = P.kcontrib[q].elem; kcontrib[3 * q + 1] = P.kcontrib[q].la;
+            kcontrib[3 * q + 2] = P.kcontrib[q].lb;
+        }
+    return RVE_OK;
+}

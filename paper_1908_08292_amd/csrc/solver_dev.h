@@ -1,0 +1,53 @@
+// solver_dev.h -- device-side data structures of the batched RVE solver.
+#pragma once
+#include <cstdint>
+
+#include "plan.h"
+
+namespace fehmm {
+
+struct DevFront {
+    int32_t m, p, parent, child_begin, child_end, kmap_begin, kmap_end, pad;
+    int64_t rows_off, relind_off, L_off, D_off, y_off, U_off;
+};
+
+struct DevPlan {
+    int32_t d, n, nnode, nelem, nfront, pad;
+    const DevFront* fronts;
+    const int32_t* rows;
+    const int32_t* relind;
+    const int32_t* children;
+    const KPair* kpair;
+    const KContrib* kcontrib;
+};
+
+// offsets (in doubles) of the per-slot workspace regions
+struct SlotLayout {
+    int64_t w, wt, R, rhs, x, fe, ke, re, L, U, S, stride;
+};
+
+struct SolveArgs {
+    const DevPlan* plans;        // [nplan]
+    const int32_t* rve_plan;     // [B]
+    const int64_t* rve_phase;    // [B] offset into phase_pool
+    const uint8_t* phase_pool;
+    const int32_t* rve_lame;     // [B] offset (in doubles) into lame_pool
+    const double* lame_pool;
+    const int64_t* state_off;    // [B+1]
+    const double* rve_atol;      // [B] default absolute tolerance
+    const int32_t* order;        // [B] queue order (longest first)
+    int64_t B;
+    double* ws;
+    SlotLayout lay;
+    unsigned int* counter;
+    const double* F;
+    double* P;
+    double* A;
+    double* wstate;
+    int32_t* status;
+    int32_t* iters;
+    double rtol, atol;
+    int32_t max_iter, backtrack, want_A, dim;
+};
+
+}  // namespace fehmm
