@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <map>
 #include <set>
+#include <climits>
+#include <cstdint>
 #include <stdexcept>
 
 #include "mesh_common.h"
@@ -280,6 +282,31 @@ PlanHost build_plan(int d, int n) {
             }
         }
         F.kmap_end = (int)P.kpair.size();
+        F.asm_begin = (int)P.asm_rc.size();
+        {
+            const int nen = 1 << d, ndl = nen * d;
+            for (int q = F.kmap_begin; q < F.kmap_end; ++q) {
+                const KPair& kp = P.kpair[q];
+                for (int k = 0; k < d; ++k)
+                    for (int l = 0; l < d; ++l) {
+                        int r = kp.row_node * d + k, col = kp.col_node * d + l;
+                        if (r < col) continue;
+                        if (r >= 32768 || col >= 32768) throw std::runtime_error("front too large for the gather list");
+                        P.asm_rc.push_back((r << 16) | col);
+                        for (int t = 0; t < nen; ++t) {
+                            int src = -1;
+                            if (t < kp.c_count) {
+                                const KContrib& cb = P.kcontrib[kp.c_begin + t];
+                                int64_t flat = ((int64_t)cb.elem * ndl + cb.lb * d + k) * ndl + cb.la * d + l;
+                                if (flat > INT32_MAX) throw std::runtime_error("element matrix index overflow");
+                                src = (int)flat;
+                            }
+                            P.asm_src.push_back(src);
+                        }
+                    }
+            }
+        }
+        F.asm_end = (int)P.asm_rc.size();
         // storage
         F.L_off = Loff;
         Loff += (int64_t)F.m * F.p;
@@ -312,9 +339,61 @@ PlanHost build_plan(int d, int n) {
         }
     }
     if (P.fronts.back().parent != -1) throw std::runtime_error("plan root is not last");
+    for (int s = 0; s < ns; ++s) {
+        FrontHost& F = P.fronts[s];
+        F.ea_off = (int64_t)P.ea_dst.size();
+        if (F.parent < 0) continue;
+        const int mc = F.m - F.p, mp = P.fronts[F.parent].m;
+        const int32_t* rel = &P.relind[F.relind_off];
+        for (int k = 0; k < mc; ++k)
+            for (int i = k; i < mc; ++i) {
+                const int64_t R = rel[i], C = rel[k];
+                const int64_t off = C * mp - (C * (C - 1)) / 2 + R - C;
+                if (off > INT32_MAX) throw std::runtime_error("extend-add offset overflow");
+                P.ea_dst.push_back((int32_t)off);
+            }
+    }
     P.L_size = Loff;
     P.U_stack = maxtop;
     P.U_scratch = scratch;
+    // LDS path: whole fronts fit the LDS buffer; then update matrices get static
+    // slots (any processing order) and small subtrees run wave-per-front
+    {
+        const int64_t mm = P.max_m;
+        P.lds_path = mm <= 256 && (mm * (mm + 1) / 2 + mm * d * d) * 8 <= kLdsFrontBytes;
+    }
+    if (P.lds_path) {
+        int64_t off = 0;
+        for (int s = 0; s < ns; ++s) {
+            FrontHost& F = P.fronts[s];
+            const int64_t mu = F.m - F.p;
+            F.U_off = off;
+            off += mu * mu + mu * kMaxNrhs;  // room for either update-matrix format
+        }
+        P.U_stack = std::max<int64_t>(off, 1);
+        int maxh = 0;
+        for (int s = 0; s < ns; ++s) {
+            FrontHost& F = P.fronts[s];
+            F.wave = F.m <= kWaveFrontMaxM ? 1 : 0;
+            F.height = 0;
+            for (int q = F.child_begin; q < F.child_end; ++q) {
+                const FrontHost& C = P.fronts[P.children[q]];
+                if (!C.wave) F.wave = 0;
+                F.height = std::max(F.height, C.height + 1);
+            }
+            if (F.wave) {
+                maxh = std::max(maxh, F.height);
+                P.wave_slice = std::max<int64_t>(P.wave_slice, (int64_t)F.m * (F.m + 1) / 2 + (int64_t)F.m * d * d + 256);
+            }
+        }
+        for (int h = 0; h <= maxh; ++h) {
+            P.wave_hbeg.push_back((int32_t)P.wave_list.size());
+            for (int s = 0; s < ns; ++s)
+                if (P.fronts[s].wave && P.fronts[s].height == h) P.wave_list.push_back(s);
+        }
+        P.wave_hbeg.push_back((int32_t)P.wave_list.size());
+        P.wave_slice = (P.wave_slice + 31) / 32 * 32;
+    }
     return P;
 }
 

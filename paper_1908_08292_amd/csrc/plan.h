@@ -27,6 +27,10 @@ struct FrontHost {
     int64_t U_off = 0;          // update matrix (m-p)^2 + (m-p)*kMaxNrhs on the stack
     int child_begin = 0, child_end = 0;  // into children[]
     int kmap_begin = 0, kmap_end = 0;    // into kpair[]
+    int asm_begin = 0, asm_end = 0;      // into asm_rc[] (lower-triangle targets of original entries)
+    int64_t ea_off = 0;                  // into ea_dst[]: this front's packed update entries -> packed parent offsets
+    int wave = 0;                        // 1: small front (m <= 64, subtree small) processed by one wave
+    int height = 0;                      // 0 for leaves, 1 + max over children
 };
 
 // original-matrix block K(b, a) of a pivot node a: d x d block at front rows of
@@ -50,6 +54,19 @@ struct PlanHost {
     std::vector<int32_t> rows, relind, children;
     std::vector<KPair> kpair;
     std::vector<KContrib> kcontrib;
+    // flat gather list of the original entries: target (row << 16 | col) in the
+    // front and up to 2^d element-matrix sources (flat index into the element
+    // matrices [elem][2^d d][2^d d], -1 = none), asm_src[t * 2^d + q]
+    std::vector<int32_t> asm_rc, asm_src;
+    // extend-add map: for every entry t of a front's packed update matrix
+    // (column-major lower, (m-p)(m-p+1)/2 entries) the offset of its target in
+    // the parent's packed front, cpk(C, m_par) + R - C
+    std::vector<int32_t> ea_dst;
+    // fronts processed wave-per-front before the workgroup fronts, grouped by
+    // height (all fronts of one height are independent)
+    std::vector<int32_t> wave_list, wave_hbeg;
+    int64_t wave_slice = 0;    // doubles of one wave's LDS slice (packed front + rhs rows)
+    bool lds_path = false;     // every front fits the LDS front buffer
     int64_t L_size = 0;        // doubles of L + D + y storage
     int64_t U_stack = 0;       // doubles of the update-matrix stack
     int64_t U_scratch = 0;     // doubles of the largest update matrix (+ rhs)
@@ -57,6 +74,10 @@ struct PlanHost {
     double factor_flops = 0;   // LDL^T flops of one factorization (fronts, exact)
     int64_t nnz_L = 0;
 };
+
+// LDS budget of the front buffer (packed front + its m x d^2 rhs rows)
+constexpr int64_t kLdsFrontBytes = 148 * 1024;
+constexpr int kWaveFrontMaxM = 64;
 
 // Builds the plan; throws std::runtime_error on unsupported (d, n).
 PlanHost build_plan(int d, int n);

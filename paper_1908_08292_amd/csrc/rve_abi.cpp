@@ -17,7 +17,9 @@
 #include "solver_dev.h"
 
 namespace fehmm {
-hipError_t launch_rve_solve(const SolveArgs& a, int nslots, hipStream_t stream);
+hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, hipStream_t stream);
+int lds_static_bytes();
+constexpr int NWAVE_ = 4;  // waves per workgroup of the solve kernel
 }
 
 using namespace fehmm;
@@ -47,8 +49,14 @@ struct PlanEntry {
     int32_t* d_children = nullptr;
     KPair* d_kpair = nullptr;
     KContrib* d_kcontrib = nullptr;
+    int32_t* d_asm_rc = nullptr;
+    int32_t* d_asm_src = nullptr;
+    int32_t* d_ea_dst = nullptr;
+    int32_t* d_wave_list = nullptr;
+    int32_t* d_wave_hbeg = nullptr;
     int refs = 0;
     int device = -1;
+    int64_t lds_bytes = 0;
 };
 
 std::mutex g_mu;
@@ -65,6 +73,8 @@ int upload(const std::vector<T>& v, T** out) {
 void free_plan_dev(PlanEntry& e) {
     (void)hipFree(e.d_fronts); (void)hipFree(e.d_rows); (void)hipFree(e.d_relind);
     (void)hipFree(e.d_children); (void)hipFree(e.d_kpair); (void)hipFree(e.d_kcontrib);
+    (void)hipFree(e.d_asm_rc); (void)hipFree(e.d_asm_src); (void)hipFree(e.d_ea_dst);
+    (void)hipFree(e.d_wave_list); (void)hipFree(e.d_wave_hbeg);
     e.d_fronts = nullptr;
 }
 
@@ -93,18 +103,30 @@ int plan_device(PlanEntry* e) {
     std::vector<DevFront> fr(P.fronts.size());
     for (size_t s = 0; s < fr.size(); ++s) {
         const FrontHost& f = P.fronts[s];
-        fr[s] = DevFront{f.m, f.p, f.parent, f.child_begin, f.child_end, f.kmap_begin, f.kmap_end, 0,
-                         f.rows_off, f.relind_off, f.L_off, f.D_off, f.y_off, f.U_off};
+        fr[s] = DevFront{f.m, f.p, f.parent, f.child_begin, f.child_end, f.kmap_begin, f.kmap_end, f.asm_begin,
+                         f.asm_end, f.wave, f.rows_off, f.relind_off, f.L_off, f.D_off, f.y_off, f.U_off, f.ea_off};
     }
     int st;
     if ((st = upload(fr, &e->d_fronts)) || (st = upload(P.rows, &e->d_rows)) || (st = upload(P.relind, &e->d_relind)) ||
         (st = upload(P.children, &e->d_children)) || (st = upload(P.kpair, &e->d_kpair)) ||
-        (st = upload(P.kcontrib, &e->d_kcontrib))) {
+        (st = upload(P.kcontrib, &e->d_kcontrib)) || (st = upload(P.asm_rc, &e->d_asm_rc)) ||
+        (st = upload(P.asm_src, &e->d_asm_src)) || (st = upload(P.ea_dst, &e->d_ea_dst)) ||
+        (st = upload(P.wave_list, &e->d_wave_list)) || (st = upload(P.wave_hbeg, &e->d_wave_hbeg))) {
         free_plan_dev(*e);
         return st;
     }
     e->dev = DevPlan{P.d, P.n, P.nnode, P.nelem, (int32_t)P.fronts.size(), 0,
-                     e->d_fronts, e->d_rows, e->d_relind, e->d_children, e->d_kpair, e->d_kcontrib};
+                     e->d_fronts, e->d_rows, e->d_relind, e->d_children, e->d_kpair, e->d_kcontrib,
+                     e->d_asm_rc, e->d_asm_src, e->d_ea_dst, e->d_wave_list, e->d_wave_hbeg,
+                     (int32_t)P.wave_hbeg.size() - 1, (int32_t)P.wave_slice};
+    if (P.wave_hbeg.empty()) e->dev.nwave_h = 0;
+    // whole fronts in LDS when the largest packed front plus its rhs rows fit
+    const int64_t mm = P.max_m;
+    const int64_t need = std::max<int64_t>(mm * (mm + 1) / 2 + mm * P.d * P.d, NWAVE_ * P.wave_slice) *
+                         (int64_t)sizeof(double);
+    e->lds_bytes = need;
+    // (one thread per front row in the pivot sweep: m <= 256; the plan decides)
+    e->dev.lds_ok = (P.lds_path && need + lds_static_bytes() + 1024 <= kLdsBytesMax) ? 1 : 0;
     return RVE_OK;
 }
 
@@ -123,6 +145,8 @@ struct rve_batch_s {
     int d = 0;
     int64_t B = 0;
     int nslots = 0;
+    int64_t lds_front = 0;   // doubles of the packed front part of the dynamic LDS
+    size_t dyn_bytes = 0;
     SlotLayout lay{};
     std::vector<int64_t> state_off;
     // device
@@ -327,6 +351,13 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
         Ust = std::max(Ust, p->host.U_stack);
         Usc = std::max(Usc, p->host.U_scratch);
     }
+    for (PlanEntry* p : plans)
+        if (p->dev.lds_ok) {
+            const int64_t mm = p->host.max_m;
+            b->lds_front = std::max(b->lds_front, mm * (mm + 1) / 2);
+            if (!p->dev.lds_ok) continue;
+            b->dyn_bytes = std::max(b->dyn_bytes, (size_t)p->lds_bytes);
+        }
     auto rnd = [](int64_t x) { return (x + 31) / 32 * 32; };
     SlotLayout& L = b->lay;
     int64_t o = 0;
@@ -421,7 +452,8 @@ int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* 
     a.backtrack = o.det_backtrack;
     a.want_A = A != nullptr;
     a.dim = b->d;
-    hipError_t e = launch_rve_solve(a, b->nslots, (hipStream_t)hip_stream);
+    a.lds_front = (int32_t)b->lds_front;
+    hipError_t e = launch_rve_solve(a, b->nslots, b->dyn_bytes, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(RVE_EHIP, std::string("rve_solve_batch launch: ") + hipGetErrorString(e));
     return RVE_OK;
 }

@@ -36,8 +36,33 @@ namespace fehmm {
 constexpr int NT = 256;
 constexpr int NWAVE = NT / 64;
 
+// Optional per-phase clock accounting (slot 0, thread 0), compiled in only
+// with -DFEHMM_PHASE_PROF=1; the default build records nothing.
+#ifndef FEHMM_PHASE_PROF
+#define FEHMM_PHASE_PROF 0
+#endif
+enum { PH_ELEM, PH_GATHER, PH_ASM, PH_DIAG, PH_TRSM, PH_MFMA, PH_OUT, PH_BACK, PH_LINE, PH_FINAL, PH_TOTAL, PH_N };
+#if FEHMM_PHASE_PROF
+__device__ unsigned long long g_phase[PH_N];
+#define PROF_T0() unsigned long long _pt = clock64()
+#define PROF_MARK(ph)                                                        \
+    do {                                                                     \
+        if (blockIdx.x == 0 && threadIdx.x == 0) {                           \
+            unsigned long long _n = clock64();                               \
+            g_phase[ph] += _n - _pt;                                         \
+            _pt = _n;                                                        \
+        }                                                                    \
+    } while (0)
+#define PROF_RESET() _pt = clock64()
+#else
+#define PROF_T0()
+#define PROF_MARK(ph)
+#define PROF_RESET()
+#endif
+
 struct Smem {
-    double red[NWAVE * 96];
+    double pub[2][18 + kMaxNrhs];  // pivot publication (double-buffered)
+    double red[NWAVE * 81];
     double dN[8 * 8 * 3];    // [gp][a][k]
     double dd[8 * 8 * 8];    // [gp][a][b] grad N_a . grad N_b
     double Fbar[9];
@@ -140,7 +165,7 @@ __device__ inline void load_wl(const RveCtx& c, const double* w, int e, double* 
 // only (on w); mode 2: final outputs (Pbar, <A>, Y rows).  Work item = (e, a)
 // in 2D (rows i = 0,1), (e, a, i) in 3D.
 template <int D>
-__device__ void element_pass(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP, double* accA) {
+__device__ __noinline__ void element_pass(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP, double* accA) {
     constexpr int NEN = 1 << D, ND = NEN * D, RPI = (D == 2) ? 2 : 1;
     const int nitems = c.ne * NEN * (D / RPI);
     const double wJ = sm.wJ;
@@ -273,9 +298,9 @@ __device__ void node_gather(const RveCtx& c, const double* src, int nc, double* 
 
 // Multifrontal LDL^T of K_ff with nrhs right-hand sides in c.rhs (node-major
 // [dof][nrhs]); forward substitution fused.  Returns via sm.flag = 2 on a
-// vanishing pivot.
+// vanishing pivot.  Fronts in global memory (any size); update matrices dense.
 template <int D>
-__device__ void factorize(const RveCtx& c, Smem& sm, int nrhs) {
+__device__ void factorize_glb(const RveCtx& c, Smem& sm, int nrhs) {
     constexpr int NEN = 1 << D, ND = NEN * D;
     const DevPlan& pl = *c.plan;
     for (int s = 0; s < pl.nfront; ++s) {
@@ -387,7 +412,7 @@ __device__ void factorize(const RveCtx& c, Smem& sm, int nrhs) {
 
 // backward substitution L^T x = D^-1 y (nrhs = 1); x in node-major dof order
 template <int D>
-__device__ void backsolve(const RveCtx& c, Smem& sm) {
+__device__ void backsolve_glb(const RveCtx& c, Smem& sm) {
     const DevPlan& pl = *c.plan;
     for (int t = threadIdx.x; t < D; t += NT) c.x[t] = 0.0;  // pinned node
     for (int s = pl.nfront - 1; s >= 0; --s) {
@@ -414,6 +439,484 @@ __device__ void backsolve(const RveCtx& c, Smem& sm) {
     }
 }
 
+
+// ---------------------------------------------------------------- LDS fronts
+// A front that fits in LDS is held there whole as a packed lower triangle,
+// column-major: entry (i, j), i >= j, at cpk(j, m) + i - j.  The first p columns
+// are the L panel and the trailing columns are exactly the packed update matrix,
+// so both leave the front with one contiguous copy each.
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ inline int cpk(int j, int m) { return j * m - ((j * (j - 1)) >> 1); }
+
+__device__ inline double readlane_d(double v, int l) {
+    union { double d; int i[2]; } u;
+    u.d = v;
+    u.i[0] = __builtin_amdgcn_readlane(u.i[0], l);
+    u.i[1] = __builtin_amdgcn_readlane(u.i[1], l);
+    return u.d;
+}
+
+// Multifrontal LDL^T, fronts in LDS (F: packed front, rl: m x nrhs rhs rows).
+// Per pivot block of 16 columns: a row-owner sweep (one barrier per pivot) gives
+// the 16 L columns of every row and the forward-substituted rhs; the trailing
+// lower triangle is then updated with v_mfma_f64_16x16x4 (lane layouts:
+// A[l%16][l/16], B[l/16][l%16], D row = l/16 + 4 v, col = l%16).
+
+
+// One small front (m <= 64) processed by a single wave: lane i owns front row i.
+// Assembly as in the workgroup path, then a right-looking LDL^T sweep over the
+// p pivots done in place in LDS (the wave's slice); within a wave LDS accesses
+// complete in issue order, so no barrier is needed between pivots.
+template <int D, int NRHS>
+__device__ void wave_front(const RveCtx& c, Smem& sm, int s, double* F, double* rl) {
+    const DevPlan& pl = *c.plan;
+    constexpr int NEN = 1 << D;
+    const int lane = threadIdx.x & 63;
+    const DevFront fr = pl.fronts[s];
+    const int m = fr.m, p = fr.p, mu = m - p;
+    const int32_t* rows = pl.rows + fr.rows_off;
+    double* Lg = c.L + fr.L_off;
+    double* Dg = c.L + fr.D_off;
+    double* yg = c.L + fr.y_off;
+    const int tot = cpk(m, m);
+    for (int t = lane; t < tot; t += 64) F[t] = 0.0;
+    for (int t = lane; t < m * NRHS; t += 64) {
+        const int i = t % m, col = t / m;
+        rl[t] = (i < p) ? c.rhs[(int64_t)rows[i] * NRHS + col] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int t = fr.asm_begin + lane; t < fr.asm_end; t += 64) {
+        const int rc = pl.asm_rc[t];
+        int src[NEN];
+#pragma unroll
+        for (int q = 0; q < NEN; ++q) src[q] = pl.asm_src[(int64_t)t * NEN + q];
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NEN; ++q) v += (src[q] >= 0) ? c.ke[src[q]] : 0.0;
+        const int r = rc >> 16, col = rc & 0xffff;
+        F[cpk(col, m) + r - col] = v;
+        if (r == col) Dg[col] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int q = fr.child_begin; q < fr.child_end; ++q) {
+        const DevFront ch = pl.fronts[pl.children[q]];
+        const int mc = ch.m - ch.p;
+        const int32_t* rel = pl.relind + ch.relind_off;
+        const double* Uc = c.U + ch.U_off;
+        const int nu = cpk(mc, mc);
+        const double* ruc = Uc + nu;
+        const int32_t* ea = pl.ea_dst + ch.ea_off;
+        for (int t = lane; t < nu; t += 64) F[ea[t]] += Uc[t];
+        for (int t = lane; t < mc * NRHS; t += 64) {
+            const int i = t % mc, col = t / mc;
+            rl[col * m + rel[i]] += ruc[(int64_t)col * mc + i];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    double* W = rl + m * NRHS;  // 16 x 16 scratch of this wave's slice
+    for (int K = 0; K < p; K += 16) {
+        const int kb = min(16, p - K);
+        // diagonal block: lane r < kb holds row r; readlane broadcast of pivots/multipliers
+        {
+            const bool ownr = lane < kb;
+            double row[16];
+            double yv[NRHS];
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc)
+                row[cc] = (ownr && cc < kb && cc <= lane) ? F[cpk(K + cc, m) + lane - cc] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) yv[q] = ownr ? rl[q * m + K + lane] : 0.0;
+            const double d0 = ownr ? Dg[K + lane] : 1.0;
+            double dpiv = 1.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j < kb) {
+                    const double piv = readlane_d(row[j], j);
+                    const double rp = 1.0 / piv;
+                    if (lane == j) {
+                        dpiv = piv;
+                        if (!(fabs(piv) > 1e-14 * fabs(d0)) || !isfinite(piv)) sm.flag = 2;
+                    }
+                    const double l = (lane > j) ? row[j] * rp : 0.0;
+                    const double lpv = l * piv;
+#pragma unroll
+                    for (int cc = j + 1; cc < 16; ++cc) {
+                        if (cc < kb) {
+                            const double lc = readlane_d(l, cc);
+                            if (cc <= lane) row[cc] -= lpv * lc;
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < NRHS; ++q) {
+                        const double yj = readlane_d(yv[q], j);
+                        if (lane > j) yv[q] -= l * yj;
+                    }
+                    if (lane > j) row[j] = l;
+                }
+            }
+            double inv[16];
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) inv[cc] = (cc == lane) ? 1.0 : 0.0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                if (e < kb) {
+                    const double le = (lane > e) ? row[e] : 0.0;
+#pragma unroll
+                    for (int cc = 0; cc <= e; ++cc) {
+                        const double ie = readlane_d(inv[cc], e);
+                        inv[cc] -= le * ie;
+                    }
+                }
+            }
+            const double rdp = 1.0 / dpiv;
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc)
+                if (lane < 16) W[cc * 16 + lane] = (ownr && cc < kb && cc <= lane) ? inv[cc] * rdp : 0.0;
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc)
+                if (ownr && cc < kb && cc <= lane) F[cpk(K + cc, m) + lane - cc] = (cc == lane) ? dpiv : row[cc];
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q)
+                if (ownr) rl[q * m + K + lane] = yv[q];
+        }
+        __builtin_amdgcn_wave_barrier();
+        // rows below: L = F W (MFMA), then their rhs
+        const int R0 = K + kb;
+        const int nRT = (m - R0 + 15) >> 4;
+        for (int tr = 0; tr < nRT; ++tr) {
+            const int ra = R0 + 16 * tr + (lane & 15);
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int kk = 4 * ks + (lane >> 4);
+                const double av = (kk < kb && ra < m) ? F[cpk(K + kk, m) + ra - K - kk] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[kk * 16 + (lane & 15)], acc, 0, 0, 0);
+            }
+            const int cc = lane & 15;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = R0 + 16 * tr + (lane >> 4) + 4 * v;
+                if (rr < m && cc < kb) F[cpk(K + cc, m) + rr - K - cc] = acc[v];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int rr = R0 + lane; rr < m; rr += 64) {
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) {
+                double v = rl[q * m + rr];
+#pragma unroll
+                for (int c2 = 0; c2 < 16; ++c2)
+                    if (c2 < kb) v -= F[cpk(K + c2, m) + rr - K - c2] * rl[q * m + K + c2];
+                rl[q * m + rr] = v;
+            }
+        }
+        // trailing lower triangle -= L D L^T (MFMA), two independent tiles in flight
+        const int nT = nRT;
+        const int ntile = nT * (nT + 1) / 2;
+        for (int t0 = 0; t0 < ntile; t0 += 2) {
+            dbl4 acc[2];
+            int Ii[2], Jj[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                int I = 0, rem = t0 + u;
+                while (rem > I) { rem -= I + 1; ++I; }
+                Ii[u] = I;
+                Jj[u] = rem;
+                acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+            }
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int kk = 4 * ks + (lane >> 4);
+                const int kc = K + kk;
+                const int base = cpk(kc, m) - kc;
+                const double dk = (kk < kb) ? F[base + kc] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int ra = R0 + 16 * Ii[u] + (lane & 15), rb = R0 + 16 * Jj[u] + (lane & 15);
+                    const bool live = (t0 + u < ntile) && kk < kb;
+                    const double av = (live && ra < m) ? F[base + ra] * dk : 0.0;
+                    const double bv = (live && rb < m) ? F[base + rb] : 0.0;
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (t0 + u >= ntile) continue;
+                const int cc = R0 + 16 * Jj[u] + (lane & 15);
+                if (cc < m) {
+                    const int base = cpk(cc, m) - cc;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int rr = R0 + 16 * Ii[u] + (lane >> 4) + 4 * v;
+                        if (rr < m && rr >= cc) F[base + rr] -= acc[u][v];
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    const int lp = cpk(p, m);
+    for (int t = lane; t < lp; t += 64) Lg[t] = F[t];
+    for (int t = lane; t < p; t += 64) Dg[t] = F[cpk(t, m)];
+    for (int t = lane; t < p * NRHS; t += 64) {
+        const int j = t % p, col = t / p;
+        yg[t] = rl[col * m + j];
+    }
+    if (mu > 0) {
+        double* dst = c.U + fr.U_off;
+        const int usz = tot - lp;
+        for (int t = lane; t < usz; t += 64) dst[t] = F[lp + t];
+        for (int t = lane; t < mu * NRHS; t += 64) {
+            const int ii = t % mu, col = t / mu;
+            dst[usz + t] = rl[col * m + p + ii];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int D, int NRHS>
+__device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, double* F, double* rl) {
+    constexpr int nrhs = NRHS;
+    const DevPlan& pl = *c.plan;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NEN = 1 << D;
+    PROF_T0();
+    // small subtrees: one front per wave, all fronts of one height at a time
+    for (int h = 0; h < pl.nwave_h; ++h) {
+        double* Fw = F + (int64_t)wave * pl.wave_slice;
+        for (int k = pl.wave_hbeg[h] + wave; k < pl.wave_hbeg[h + 1]; k += NWAVE) {
+            const int sw = pl.wave_list[k];
+            const int mw = pl.fronts[sw].m;
+            wave_front<D, NRHS>(c, sm, sw, Fw, Fw + cpk(mw, mw));
+        }
+        __syncthreads();
+    }
+    PROF_MARK(PH_TRSM);
+    for (int s = 0; s < pl.nfront; ++s) {
+        const DevFront fr = pl.fronts[s];
+        if (fr.wave) continue;
+        const int m = fr.m, p = fr.p, mu = m - p;
+        const int32_t* rows = pl.rows + fr.rows_off;
+        double* Lg = c.L + fr.L_off;
+        double* Dg = c.L + fr.D_off;
+        double* yg = c.L + fr.y_off;
+        const int tot = cpk(m, m);
+        for (int t = tid; t < tot; t += NT) F[t] = 0.0;
+        for (int t = tid; t < m * nrhs; t += NT) {
+            const int i = t % m, col = t / m;
+            rl[t] = (i < p) ? c.rhs[(int64_t)rows[i] * nrhs + col] : 0.0;
+        }
+        __syncthreads();
+        // original entries: one gather level, every source load in flight at once
+        for (int t = fr.asm_begin + tid; t < fr.asm_end; t += NT) {
+            const int rc = pl.asm_rc[t];
+            int src[NEN];
+#pragma unroll
+            for (int q = 0; q < NEN; ++q) src[q] = pl.asm_src[(int64_t)t * NEN + q];
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < NEN; ++q) v += (src[q] >= 0) ? c.ke[src[q]] : 0.0;
+            const int r = rc >> 16, col = rc & 0xffff;
+            F[cpk(col, m) + r - col] = v;
+            if (r == col) Dg[col] = v;
+        }
+        __syncthreads();
+        for (int q = fr.child_begin; q < fr.child_end; ++q) {
+            const DevFront ch = pl.fronts[pl.children[q]];
+            const int mc = ch.m - ch.p;
+            const int32_t* rel = pl.relind + ch.relind_off;
+            const double* Uc = c.U + ch.U_off;
+            const int nu = cpk(mc, mc);
+            const double* ruc = Uc + nu;
+            const int32_t* ea = pl.ea_dst + ch.ea_off;
+            for (int t = tid; t < nu; t += NT) F[ea[t]] += Uc[t];
+            for (int t = tid; t < mc * nrhs; t += NT) {
+                const int i = t % mc, col = t / mc;
+                rl[col * m + rel[i]] += ruc[(int64_t)col * mc + i];
+            }
+            __syncthreads();
+        }
+        PROF_MARK(PH_ASM);
+        for (int K = 0; K < p; K += 16) {
+            const int kb = min(16, p - K);
+            // ---- pivot block sweep: each front row below K is owned by one thread
+            // that keeps its 16 block entries in registers; at pivot j the owners of
+            // the block rows publish pivot, reciprocal, column-j entries and the
+            // forward-substituted rhs (double-buffered, one barrier per pivot)
+            const int i = K + tid;
+            const bool own = i < m;
+            double r[16];
+            double b[NRHS];
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc)
+                r[cc] = (own && cc < kb && K + cc <= i) ? F[cpk(K + cc, m) + i - K - cc] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) b[q] = own ? rl[q * m + i] : 0.0;
+            const double d0 = (own && i < K + kb) ? Dg[i] : 1.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j < kb) {
+                    double* P = sm.pub[j & 1];  // [0] piv, [1] 1/piv, [2..17] g, [18..] y
+                    if (i == K + j) {
+                        const double piv = r[j];
+                        if (!(fabs(piv) > 1e-14 * fabs(d0)) || !isfinite(piv)) sm.flag = 2;
+                        P[0] = piv;
+                        P[1] = 1.0 / piv;
+#pragma unroll
+                        for (int q = 0; q < NRHS; ++q) P[18 + q] = b[q];
+                    } else if (i > K + j && i < K + kb) {
+                        P[2 + i - K] = r[j];
+                    }
+                    __syncthreads();
+                    if (own && i > K + j) {
+                        const double l = r[j] * P[1];
+#pragma unroll
+                        for (int cc = j + 1; cc < 16; ++cc)
+                            if (cc < kb && K + cc <= i) r[cc] -= l * P[2 + cc];
+                        r[j] = l;
+#pragma unroll
+                        for (int q = 0; q < NRHS; ++q) b[q] -= l * P[18 + q];
+                    }
+                }
+            }
+            if (own) {
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc)
+                    if (cc < kb && K + cc <= i) F[cpk(K + cc, m) + i - K - cc] = r[cc];
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) rl[q * m + i] = b[q];
+            }
+            __syncthreads();
+            PROF_MARK(PH_DIAG);
+            // ---- trailing lower triangle (rows, cols >= T0) -= L D L^T with MFMA
+            const int T0 = K + kb;
+            const int nT = (m - T0 + 15) >> 4;
+            const int ntile = nT * (nT + 1) / 2;
+            for (int tix = wave; tix < ntile; tix += NWAVE) {
+                int I = 0, rem = tix;
+                while (rem > I) { rem -= I + 1; ++I; }
+                const int J = rem;
+                const int ra = T0 + 16 * I + (lane & 15), rb = T0 + 16 * J + (lane & 15);
+                dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int kk = 4 * ks + (lane >> 4);
+                    const int kc = K + kk;
+                    double a = 0.0, bb = 0.0;
+                    if (kk < kb) {
+                        const int base = cpk(kc, m) - kc;
+                        const double dk = F[base + kc];
+                        if (ra < m) a = F[base + ra] * dk;
+                        if (rb < m) bb = F[base + rb];
+                    }
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+                }
+                const int cc = T0 + 16 * J + (lane & 15);
+                if (cc < m) {
+                    const int base = cpk(cc, m) - cc;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int rr = T0 + 16 * I + (lane >> 4) + 4 * v;
+                        if (rr < m && rr >= cc) F[base + rr] -= acc[v];
+                    }
+                }
+            }
+            __syncthreads();
+            PROF_MARK(PH_MFMA);
+        }
+        // L panel, D, y; update matrix (packed) and its rhs onto the stack
+        const int lp = cpk(p, m);
+        for (int t = tid; t < lp; t += NT) Lg[t] = F[t];
+        for (int t = tid; t < p; t += NT) Dg[t] = F[cpk(t, m)];
+        for (int t = tid; t < p * nrhs; t += NT) {
+            const int j = t % p, col = t / p;
+            yg[t] = rl[col * m + j];
+        }
+        if (mu > 0) {
+            double* dst = c.U + fr.U_off;
+            const int usz = tot - lp;
+            for (int t = tid; t < usz; t += NT) dst[t] = F[lp + t];
+            for (int t = tid; t < mu * nrhs; t += NT) {
+                const int i = t % mu, col = t / mu;
+                dst[usz + t] = rl[col * m + p + i];
+            }
+        }
+        __syncthreads();
+        PROF_MARK(PH_OUT);
+    }
+}
+
+// backward substitution L^T x = D^-1 y (nrhs = 1) over packed L panels staged in
+// LDS; 16-pivot blocks from the last: the block triangle is solved in registers
+// of wave 0 (readlane chain), then all threads fold the block into the rest.
+template <int D>
+__device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, double* F, double* rl) {
+    const DevPlan& pl = *c.plan;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int t = tid; t < D; t += NT) c.x[t] = 0.0;
+    for (int s = pl.nfront - 1; s >= 0; --s) {
+        const DevFront fr = pl.fronts[s];
+        const int m = fr.m, p = fr.p;
+        const int32_t* rows = pl.rows + fr.rows_off;
+        const double* Lg = c.L + fr.L_off;
+        const double* Dg = c.L + fr.D_off;
+        const double* yg = c.L + fr.y_off;
+        const int lp = cpk(p, m);
+        double* v = rl;       // [p]
+        double* xs = rl + p;  // [m - p] solution at the update rows
+        for (int t = tid; t < lp; t += NT) F[t] = Lg[t];
+        for (int t = tid; t < p; t += NT) v[t] = yg[t] / Dg[t];
+        for (int t = tid; t < m - p; t += NT) xs[t] = c.x[rows[p + t]];
+        __syncthreads();
+        // v_j -= sum_{i >= p} L(i, j) x_i : 3 partial sums per column (the rhs rows
+        // hold m * d^2 >= m + 3 p doubles)
+        for (int t = tid; t < 3 * p; t += NT) {
+            const int j = t % p, part = t / p;
+            const double* colj = F + cpk(j, m) - j;
+            double a = 0.0;
+            for (int i = p + part; i < m; i += 3) a += colj[i] * xs[i - p];
+            rl[m + t] = a;
+        }
+        __syncthreads();
+        for (int j = tid; j < p; j += NT) v[j] -= (rl[m + j] + rl[m + p + j]) + rl[m + 2 * p + j];
+        __syncthreads();
+        const int nb = (p + 15) >> 4;
+        for (int bk = nb - 1; bk >= 0; --bk) {
+            const int K = 16 * bk, kb = min(16, p - K);
+            if (wave == 0) {
+                const bool own = lane < kb;
+                double Lr[16];
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc)
+                    Lr[cc] = (own && cc < kb && cc > lane) ? F[cpk(K + lane, m) + cc - lane] : 0.0;
+                double vv = own ? v[K + lane] : 0.0;
+#pragma unroll
+                for (int cc = 15; cc >= 0; --cc) {
+                    if (cc < kb) {
+                        const double xc = readlane_d(vv, cc);
+                        if (lane < cc) vv -= Lr[cc] * xc;
+                    }
+                }
+                if (own) v[K + lane] = vv;
+            }
+            __syncthreads();
+            for (int j = tid; j < K; j += NT) {
+                const double* colj = F + cpk(j, m) - j;
+                double a = v[j];
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc)
+                    if (cc < kb) a -= colj[K + cc] * v[K + cc];
+                v[j] = a;
+            }
+            __syncthreads();
+        }
+        for (int j = tid; j < p; j += NT) c.x[rows[j]] = v[j];
+        __syncthreads();
+    }
+}
+
 template <int D>
 __device__ double free_norm2(const RveCtx& c, Smem& sm, const double* R) {
     double v[1] = {0.0};
@@ -425,6 +928,7 @@ __device__ double free_norm2(const RveCtx& c, Smem& sm, const double* R) {
 template <int D>
 __global__ __launch_bounds__(NT) void rve_solve_kernel(SolveArgs a) {
     __shared__ Smem sm;
+    extern __shared__ double dynF[];
     constexpr int NEN = 1 << D, ND = NEN * D, D2 = D * D;
     const int64_t slot = blockIdx.x;
     double* base = a.ws + slot * a.lay.stride;
@@ -491,6 +995,7 @@ __global__ __launch_bounds__(NT) void rve_solve_kernel(SolveArgs a) {
         }
         // input checks and initial guess
         bool finite_in = true;
+#pragma unroll
         for (int q = 0; q < D2; ++q) finite_in = finite_in && isfinite(sm.Fbar[q]);
         double* wst = a.wstate ? a.wstate + a.state_off[rve] : nullptr;
         for (int t = threadIdx.x; t < ndof; t += NT) c.w[t] = (wst && t >= D) ? wst[t] : 0.0;
@@ -498,22 +1003,30 @@ __global__ __launch_bounds__(NT) void rve_solve_kernel(SolveArgs a) {
         int status = 0, it = 0;
         if (!finite_in) status = 4;
         double r0 = 0.0;
+        PROF_T0();
         while (status == 0) {
+            PROF_RESET();
             element_pass<D>(c, sm, c.w, 0, nullptr, nullptr);
             __syncthreads();
+            PROF_MARK(PH_ELEM);
             if (sm.flag) { status = 2; break; }
             node_gather<D>(c, c.fe, 1, c.R, 1.0);
             __syncthreads();
             const double rn = sqrt(free_norm2<D>(c, sm, c.R));
+            PROF_MARK(PH_GATHER);
             if (!isfinite(rn)) { status = 4; break; }
             if (it == 0) r0 = rn;
             if (rn <= a.rtol * r0 + sm.atol) break;
             if (it == a.max_iter) { status = 1; break; }
             for (int t = threadIdx.x; t < ndof; t += NT) c.rhs[t] = -c.R[t];
             __syncthreads();
-            factorize<D>(c, sm, 1);
+            if (c.plan->lds_ok) factorize_lds<D, 1>(c, sm, dynF, dynF + a.lds_front);
+            else factorize_glb<D>(c, sm, 1);
             if (sm.flag) { status = 3; break; }
-            backsolve<D>(c, sm);
+            PROF_RESET();
+            if (c.plan->lds_ok) backsolve_lds<D>(c, sm, dynF, dynF + a.lds_front);
+            else backsolve_glb<D>(c, sm);
+            PROF_MARK(PH_BACK);
             // step with det F backtracking
             double alpha = 1.0;
             bool ok = false;
@@ -529,17 +1042,21 @@ __global__ __launch_bounds__(NT) void rve_solve_kernel(SolveArgs a) {
                 alpha *= 0.5;
             }
             if (threadIdx.x == 0) sm.flag = 0;
+            PROF_MARK(PH_LINE);
             if (!ok) { status = 2; break; }
             for (int t = threadIdx.x; t < ndof; t += NT) c.w[t] = c.wt[t];
             __syncthreads();
             ++it;
         }
         __syncthreads();
+        PROF_RESET();
         double* Pout = a.P + (int64_t)rve * D2;
         double* Aout = a.A ? a.A + (int64_t)rve * D2 * D2 : nullptr;
         if (status == 0) {
             double accP[D2], accA[D2 * D2];
+#pragma unroll
             for (int q = 0; q < D2; ++q) accP[q] = 0;
+#pragma unroll
             for (int q = 0; q < D2 * D2; ++q) accA[q] = 0;
             element_pass<D>(c, sm, c.w, 2, accP, accA);
             __syncthreads();
@@ -552,12 +1069,14 @@ __global__ __launch_bounds__(NT) void rve_solve_kernel(SolveArgs a) {
                 __syncthreads();
                 node_gather<D>(c, c.re, D2, c.rhs, 1.0);
                 __syncthreads();
-                factorize<D>(c, sm, D2);
+                if (c.plan->lds_ok) factorize_lds<D, D2>(c, sm, dynF, dynF + a.lds_front);
+                else factorize_glb<D>(c, sm, D2);
                 if (sm.flag) {
                     status = 3;
                 } else {
                     // Z^T D^-1 Z over every pivot of every front
                     double acc[D2 * D2];
+#pragma unroll
                     for (int q = 0; q < D2 * D2; ++q) acc[q] = 0;
                     const DevPlan& pl = *c.plan;
                     for (int s = 0; s < pl.nfront; ++s) {
@@ -567,8 +1086,11 @@ __global__ __launch_bounds__(NT) void rve_solve_kernel(SolveArgs a) {
                         for (int j = threadIdx.x; j < fr.p; j += NT) {
                             const double rd = 1.0 / Dg[j];
                             double z[D2];
+#pragma unroll
                             for (int g = 0; g < D2; ++g) z[g] = y[(int64_t)g * fr.p + j];
+#pragma unroll
                             for (int g = 0; g < D2; ++g)
+#pragma unroll
                                 for (int h2 = 0; h2 < D2; ++h2) acc[g * D2 + h2] += z[g] * z[h2] * rd;
                         }
                     }
@@ -585,6 +1107,7 @@ __global__ __launch_bounds__(NT) void rve_solve_kernel(SolveArgs a) {
             if (threadIdx.x < D2) Pout[threadIdx.x] = qnan;
             if (Aout && threadIdx.x < D2 * D2) Aout[threadIdx.x] = qnan;
         }
+        PROF_MARK(PH_FINAL);
         if (threadIdx.x == 0) {
             if (a.status) a.status[rve] = status;
             if (a.iters) a.iters[rve] = it;
@@ -598,13 +1121,34 @@ __global__ void reset_counter_kernel(unsigned int* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
-hipError_t launch_rve_solve(const SolveArgs& a, int nslots, hipStream_t stream) {
+int lds_static_bytes() { return (int)sizeof(Smem); }
+
+hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, hipStream_t stream) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, a.counter);
-    if (a.dim == 2)
-        hipLaunchKernelGGL(rve_solve_kernel<2>, dim3(nslots), dim3(NT), 0, stream, a);
-    else
-        hipLaunchKernelGGL(rve_solve_kernel<3>, dim3(nslots), dim3(NT), 0, stream, a);
+    if (a.dim == 2) {
+        hipError_t e = hipFuncSetAttribute((const void*)rve_solve_kernel<2>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(rve_solve_kernel<2>, dim3(nslots), dim3(NT), dyn_bytes, stream, a);
+    } else {
+        hipError_t e = hipFuncSetAttribute((const void*)rve_solve_kernel<3>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(rve_solve_kernel<3>, dim3(nslots), dim3(NT), dyn_bytes, stream, a);
+    }
     return hipGetLastError();
 }
 
 }  // namespace fehmm
+
+#if FEHMM_PHASE_PROF
+extern "C" int rve_debug_phase_clocks(unsigned long long* out, int reset) {
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(fehmm::g_phase), sizeof(unsigned long long) * fehmm::PH_N) != hipSuccess)
+        return -3;
+    if (reset) {
+        unsigned long long z[fehmm::PH_N] = {0};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(fehmm::g_phase), z, sizeof(z)) != hipSuccess) return -3;
+    }
+    return 0;
+}
+#endif

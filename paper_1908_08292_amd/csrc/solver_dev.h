@@ -7,18 +7,25 @@
 namespace fehmm {
 
 struct DevFront {
-    int32_t m, p, parent, child_begin, child_end, kmap_begin, kmap_end, pad;
-    int64_t rows_off, relind_off, L_off, D_off, y_off, U_off;
+    int32_t m, p, parent, child_begin, child_end, kmap_begin, kmap_end, asm_begin, asm_end, wave;
+    int64_t rows_off, relind_off, L_off, D_off, y_off, U_off, ea_off;
 };
 
 struct DevPlan {
-    int32_t d, n, nnode, nelem, nfront, pad;
+    int32_t d, n, nnode, nelem, nfront, lds_ok;  // lds_ok: every front fits the LDS front buffer
     const DevFront* fronts;
     const int32_t* rows;
     const int32_t* relind;
     const int32_t* children;
     const KPair* kpair;
     const KContrib* kcontrib;
+    const int32_t* asm_rc;
+    const int32_t* asm_src;
+    const int32_t* ea_dst;
+    const int32_t* wave_list;
+    const int32_t* wave_hbeg;
+    int32_t nwave_h;       // number of heights in the wave phase
+    int32_t wave_slice;    // doubles per wave slice
 };
 
 // offsets (in doubles) of the per-slot workspace regions
@@ -48,6 +55,11 @@ struct SolveArgs {
     int32_t* iters;
     double rtol, atol;
     int32_t max_iter, backtrack, want_A, dim;
+    int32_t lds_front;           // doubles of the LDS front buffer (rhs rows follow it)
+    int32_t pad;
 };
+
+// LDS available to the front buffer (packed front + m x d^2 rhs rows)
+constexpr int kLdsBytesMax = 160 * 1024;
 
 }  // namespace fehmm
