@@ -110,10 +110,16 @@ typedef struct {
     int32_t max_iter;      /* Newton updates before RVE_S_NOCONV */
     int32_t precision;     /* RVE_PREC_* */
     int32_t det_backtrack; /* halvings of a Newton step while some J <= 0 */
-    int32_t reserved;
+    int32_t flags;         /* RVE_FLAG_* */
 } rve_opts;
 
-/* rtol 1e-10, atol -1 (default), max_iter 25, FP64, det_backtrack 8 */
+/* With this flag an RVE that reaches max_iter updates without meeting the
+ * tolerance still gets P and A evaluated at its last state (and stores it in
+ * w_state); its status is RVE_S_NOCONV.  The alternating two-level Newton of
+ * Sec. 5.2 (one micro update per macro iteration) relies on it. */
+#define RVE_FLAG_OUTPUTS_AT_CAP 1
+
+/* rtol 1e-10, atol -1 (default), max_iter 25, FP64, det_backtrack 8, flags 0 */
 void rve_opts_default(rve_opts* o);
 
 /* ---- the hot path ------------------------------------------------------------

@@ -1,0 +1,494 @@
+// fehmm.hip -- two-scale FE-HMM driver (include/fehmm.h): macro Q1 mesh, device
+// gather of the quadrature-point deformation gradients, the batched RVE solves,
+// deterministic colour-ordered assembly of the banded macro system, and a
+// single-workgroup banded LDL^T solve; the macro Newton loop runs on the host
+// with one device-to-host norm per iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fehmm.h"
+
+int rve_internal_set_error(int code, const std::string& msg);  // rve_abi.cpp
+static inline int set_error(int code, const std::string& msg) { return rve_internal_set_error(code, msg); }
+
+namespace {
+
+constexpr int NTB = 1024;  // threads of the banded solver
+
+struct MacroGeom {
+    double dN[4][4][2];  // [gp][node][dir]
+    double wdet;
+};
+
+// F at every Gauss point: F = I + sum_a u_a (x) grad N_a
+__global__ void macro_gather_F(const int* __restrict__ conn, int nelem, const double* __restrict__ u, MacroGeom g,
+                               double* __restrict__ F) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 4 * nelem) return;
+    const int e = q >> 2, gp = q & 3;
+    double f[4] = {1.0, 0.0, 0.0, 1.0};
+    for (int a = 0; a < 4; ++a) {
+        const int v = conn[4 * e + a];
+        for (int i = 0; i < 2; ++i)
+            for (int J = 0; J < 2; ++J) f[i * 2 + J] += u[2 * v + i] * g.dN[gp][a][J];
+    }
+    for (int k = 0; k < 4; ++k) F[4 * q + k] = f[k];
+}
+
+// element residual (8) and tangent (8 x 8) from the transferred Pbar, Abar
+__global__ void macro_element(int nelem, const double* __restrict__ P, const double* __restrict__ A, MacroGeom g,
+                              double* __restrict__ ke, double* __restrict__ fe) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nelem * 8) return;
+    const int e = t >> 3, r = t & 7, a = r >> 1, i = r & 1;
+    double fr = 0.0, kr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int gp = 0; gp < 4; ++gp) {
+        const double* Pq = P + 4 * (4 * e + gp);
+        const double* Aq = A + 16 * (4 * e + gp);
+        for (int J = 0; J < 2; ++J) fr += Pq[i * 2 + J] * g.dN[gp][a][J] * g.wdet;
+        for (int b = 0; b < 4; ++b)
+            for (int k = 0; k < 2; ++k) {
+                double s = 0.0;
+                for (int J = 0; J < 2; ++J)
+                    for (int L = 0; L < 2; ++L) s += g.dN[gp][a][J] * Aq[(i * 2 + J) * 4 + k * 2 + L] * g.dN[gp][b][L];
+                kr[b * 2 + k] += s * g.wdet;
+            }
+    }
+    fe[8 * e + r] = fr;
+    for (int c = 0; c < 8; ++c) ke[64 * e + 8 * r + c] = kr[c];
+}
+
+__global__ void macro_zero_int(int* __restrict__ x, int n) {
+    if ((int)threadIdx.x < n) x[threadIdx.x] = 0;
+}
+
+__global__ void macro_zero(double* __restrict__ x, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = 0.0;
+}
+
+// add the elements of one colour (no two share a node) into the lower band
+// K[i * (bw + 1) + (i - j)], i >= j, and into R
+__global__ void macro_scatter(const int* __restrict__ elist, int nel, const int* __restrict__ conn,
+                              const double* __restrict__ ke, const double* __restrict__ fe, int bw,
+                              double* __restrict__ K, double* __restrict__ R) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nel * 8) return;
+    const int e = elist[t >> 3], r = t & 7;
+    const int gi = 2 * conn[4 * e + (r >> 1)] + (r & 1);
+    R[gi] += fe[8 * e + r];
+    for (int c = 0; c < 8; ++c) {
+        const int gj = 2 * conn[4 * e + (c >> 1)] + (c & 1);
+        if (gj <= gi) K[(int64_t)gi * (bw + 1) + (gi - gj)] += ke[64 * e + 8 * r + c];
+    }
+}
+
+// Dirichlet dofs: identity row/column, zero residual (the increment there is 0)
+__global__ void macro_bc(const int* __restrict__ fixed, int ndof, int bw, double* __restrict__ K,
+                         double* __restrict__ R) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ndof) return;
+    for (int k = 1; k <= bw; ++k) {
+        const int j = i - k;
+        if (j >= 0 && (fixed[i] || fixed[j])) K[(int64_t)i * (bw + 1) + k] = 0.0;
+    }
+    if (fixed[i]) {
+        K[(int64_t)i * (bw + 1)] = 1.0;
+        R[i] = 0.0;
+    }
+}
+
+// ||R||^2 and the number of failed RVEs, one workgroup
+__global__ void macro_norm(const double* __restrict__ R, int ndof, const int* __restrict__ status, int nqp,
+                           int tolerate_noconv, double* __restrict__ out) {
+    __shared__ double s[256];
+    __shared__ int bad[256];
+    double acc = 0.0;
+    int nb = 0;
+    for (int i = threadIdx.x; i < ndof; i += 256) acc += R[i] * R[i];
+    for (int q = threadIdx.x; q < nqp; q += 256) {
+        const int st = status[q];
+        nb += (st != 0 && !(tolerate_noconv && st == 1)) ? 1 : 0;
+    }
+    s[threadIdx.x] = acc;
+    bad[threadIdx.x] = nb;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            s[threadIdx.x] += s[threadIdx.x + o];
+            bad[threadIdx.x] += bad[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s[0];
+        out[1] = (double)bad[0];
+    }
+}
+
+// banded LDL^T (lower band, bandwidth bw) and solve K du = -R in one workgroup
+__global__ __launch_bounds__(NTB) void macro_band_solve(double* __restrict__ K, const double* __restrict__ R, int n,
+                                                        int bw, double* __restrict__ du, int* __restrict__ flag) {
+    const int ld = bw + 1;
+    for (int k = 0; k < n; ++k) {
+        const double piv = K[(int64_t)k * ld];
+        if (threadIdx.x == 0 && (!(fabs(piv) > 0.0) || !isfinite(piv))) *flag = 1;
+        const int w = min(bw, n - 1 - k);
+        // trailing band update with the unscaled column: K_ij -= K_ik K_jk / piv
+        for (int t = threadIdx.x; t < w * w; t += NTB) {
+            const int ii = t / w, jj = t % w;
+            if (jj > ii) continue;
+            const int i = k + 1 + ii, j = k + 1 + jj;
+            K[(int64_t)i * ld + (i - j)] -= K[(int64_t)i * ld + (i - k)] * K[(int64_t)j * ld + (j - k)] / piv;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < w; t += NTB) {
+            const int i = k + 1 + t;
+            K[(int64_t)i * ld + (i - k)] /= piv;
+        }
+        __syncthreads();
+    }
+    // forward (unit L), diagonal, backward; one workgroup, dot products by wave 0
+    for (int i = threadIdx.x; i < n; i += NTB) du[i] = -R[i];
+    __syncthreads();
+    __shared__ double red[64];
+    for (int i = 0; i < n; ++i) {
+        if (threadIdx.x < 64) {
+            double s = 0.0;
+            for (int j = max(0, i - bw) + threadIdx.x; j < i; j += 64) s += K[(int64_t)i * ld + (i - j)] * du[j];
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+            if (threadIdx.x == 0) du[i] -= s;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += NTB) du[i] /= K[(int64_t)i * ld];
+    __syncthreads();
+    for (int i = n - 1; i >= 0; --i) {
+        const double xi = du[i];
+        for (int t = threadIdx.x; t < bw; t += NTB) {
+            const int j = i - 1 - t;
+            if (j >= 0) du[j] -= K[(int64_t)i * ld + (i - j)] * xi;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void macro_update(double* __restrict__ u, const double* __restrict__ du, const int* __restrict__ fixed,
+                             int ndof) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ndof && !fixed[i]) u[i] += du[i];
+}
+
+__global__ void macro_dirichlet(double* __restrict__ u, const int* __restrict__ fixed,
+                                const double* __restrict__ uval, int ndof) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ndof && fixed[i]) u[i] = uval[i];
+}
+
+inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+struct fehmm_s {
+    fehmm_desc desc{};
+    int nnode = 0, nelem = 0, ndof = 0, nqp = 0, bw = 0;
+    std::vector<double> xy;
+    std::vector<int> conn, fixed;
+    std::vector<std::vector<int>> colour;
+    MacroGeom geom{};
+    rve_batch batch = nullptr;
+    int64_t state_doubles = 0;
+    hipStream_t stream = nullptr;
+    // device
+    int *d_conn = nullptr, *d_fixed = nullptr, *d_col[4] = {nullptr, nullptr, nullptr, nullptr};
+    int *d_status = nullptr, *d_iters = nullptr, *d_flag = nullptr;
+    double *d_u = nullptr, *d_du = nullptr, *d_uval = nullptr, *d_F = nullptr, *d_P = nullptr, *d_A = nullptr;
+    double *d_w = nullptr, *d_ke = nullptr, *d_fe = nullptr, *d_K = nullptr, *d_R = nullptr, *d_norm = nullptr;
+    bool alive = true;
+};
+
+#define FH_HIP(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return set_error(RVE_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static void fehmm_free(fehmm_s* h) {
+    int* ip[] = {h->d_conn, h->d_fixed, h->d_col[0], h->d_col[1], h->d_col[2], h->d_col[3], h->d_status,
+                 h->d_iters, h->d_flag};
+    for (int* p : ip) (void)hipFree(p);
+    double* dp[] = {h->d_u, h->d_du, h->d_uval, h->d_F, h->d_P, h->d_A, h->d_w, h->d_ke, h->d_fe, h->d_K,
+                    h->d_R, h->d_norm};
+    for (double* p : dp) (void)hipFree(p);
+    if (h->batch) rve_batch_destroy(h->batch);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    h->batch = nullptr;
+}
+
+extern "C" {
+
+int fehmm_create(const fehmm_desc* d, fehmm* out) {
+    if (!d || !out) return set_error(RVE_EINVAL, "fehmm_create: NULL argument");
+    *out = nullptr;
+    if (d->nx < 1 || d->ny < 1 || d->nx > 4096 || d->ny > 4096 || !(d->Lx > 0) || !(d->Ly > 0))
+        return set_error(RVE_EINVAL, "fehmm_create: bad macro grid");
+    if (d->bc != FEHMM_BC_CLAMPED_PULL && d->bc != FEHMM_BC_UNIAXIAL)
+        return set_error(RVE_EINVAL, "fehmm_create: unknown boundary condition");
+    if (d->scheme != FEHMM_NESTED && d->scheme != FEHMM_ALTERNATING)
+        return set_error(RVE_EINVAL, "fehmm_create: unknown scheme");
+    if (d->nsteps < 1 || !(d->rtol_macro > 0) || d->max_macro_iter < 1 || d->max_macro_iter > FEHMM_MAX_HIST - 1)
+        return set_error(RVE_EINVAL, "fehmm_create: bad load-step or Newton settings");
+    if (!d->micro) return set_error(RVE_EINVAL, "fehmm_create: micro mesh required");
+    auto h = std::make_unique<fehmm_s>();
+    h->desc = *d;
+    const int nx = d->nx, ny = d->ny;
+    const double hx = d->Lx / nx, hy = d->Ly / ny;
+    // Q1 gradients at the 2 x 2 Gauss points of a rectangle hx x hy
+    {
+        const int sx[4] = {-1, 1, 1, -1}, sy[4] = {-1, -1, 1, 1};
+        const double g = 1.0 / std::sqrt(3.0);
+        for (int p = 0; p < 4; ++p) {
+            const double xi = sx[p] * g, eta = sy[p] * g;
+            for (int a = 0; a < 4; ++a) {
+                h->geom.dN[p][a][0] = 0.25 * sx[a] * (1 + sy[a] * eta) * 2.0 / hx;
+                h->geom.dN[p][a][1] = 0.25 * sy[a] * (1 + sx[a] * xi) * 2.0 / hy;
+            }
+        }
+        h->geom.wdet = 0.25 * hx * hy;
+    }
+    std::vector<int> keep(nx * ny), used((nx + 1) * (ny + 1), 0), ecol;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const double cx = (i + 0.5) * hx - 0.5 * d->Lx, cy = (j + 0.5) * hy - 0.5 * d->Ly;
+            keep[j * nx + i] = !(d->hole_r > 0 && std::sqrt(cx * cx + cy * cy) < d->hole_r);
+        }
+    std::vector<int> id((nx + 1) * (ny + 1), -1);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+            if (keep[j * nx + i])
+                used[j * (nx + 1) + i] = used[j * (nx + 1) + i + 1] = used[(j + 1) * (nx + 1) + i] =
+                    used[(j + 1) * (nx + 1) + i + 1] = 1;
+    for (int k = 0; k < (nx + 1) * (ny + 1); ++k)
+        if (used[k]) id[k] = h->nnode++;
+    if (h->nnode == 0) return set_error(RVE_EINVAL, "fehmm_create: the hole removes every element");
+    h->xy.resize(2 * h->nnode);
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i)
+            if (id[j * (nx + 1) + i] >= 0) {
+                h->xy[2 * id[j * (nx + 1) + i]] = i * hx;
+                h->xy[2 * id[j * (nx + 1) + i] + 1] = j * hy;
+            }
+    h->colour.resize(4);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+            if (keep[j * nx + i]) {
+                const int e = h->nelem++;
+                h->conn.push_back(id[j * (nx + 1) + i]);
+                h->conn.push_back(id[j * (nx + 1) + i + 1]);
+                h->conn.push_back(id[(j + 1) * (nx + 1) + i + 1]);
+                h->conn.push_back(id[(j + 1) * (nx + 1) + i]);
+                h->colour[(i & 1) + 2 * (j & 1)].push_back(e);
+            }
+    h->ndof = 2 * h->nnode;
+    h->nqp = 4 * h->nelem;
+    h->fixed.assign(h->ndof, 0);
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+            const int v = id[j * (nx + 1) + i];
+            if (v < 0) continue;
+            if (i == 0) {
+                h->fixed[2 * v] = 1;
+                if (d->bc == FEHMM_BC_CLAMPED_PULL || j == 0) h->fixed[2 * v + 1] = 1;
+            }
+            if (i == nx) h->fixed[2 * v] = 1;
+        }
+    for (int e = 0; e < h->nelem; ++e)
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                h->bw = std::max(h->bw, std::abs(2 * h->conn[4 * e + a] - 2 * h->conn[4 * e + b]) + 1);
+    // one RVE per Gauss point
+    std::vector<rve_mesh> meshes(h->nqp, d->micro);
+    int st = rve_batch_create(meshes.data(), h->nqp, &h->batch);
+    if (st) return st;
+    std::vector<int64_t> off(h->nqp + 1);
+    rve_batch_state_offsets(h->batch, off.data());
+    h->state_doubles = off[h->nqp];
+    FH_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    auto up = [&](auto** p, const auto& v) -> int {
+        using T = typename std::remove_reference<decltype(v[0])>::type;
+        FH_HIP(hipMalloc((void**)p, std::max<size_t>(v.size(), 1) * sizeof(T)));
+        if (!v.empty()) FH_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        return RVE_OK;
+    };
+    auto zal = [&](double** p, int64_t n) -> int {
+        FH_HIP(hipMalloc((void**)p, std::max<int64_t>(n, 1) * sizeof(double)));
+        FH_HIP(hipMemset(*p, 0, std::max<int64_t>(n, 1) * sizeof(double)));
+        return RVE_OK;
+    };
+    fehmm_s* H = h.get();
+    if ((st = up(&H->d_conn, H->conn)) || (st = up(&H->d_fixed, H->fixed)) || (st = up(&H->d_col[0], H->colour[0])) ||
+        (st = up(&H->d_col[1], H->colour[1])) || (st = up(&H->d_col[2], H->colour[2])) ||
+        (st = up(&H->d_col[3], H->colour[3])) || (st = zal(&H->d_u, H->ndof)) || (st = zal(&H->d_du, H->ndof)) ||
+        (st = zal(&H->d_uval, H->ndof)) || (st = zal(&H->d_F, 4 * (int64_t)H->nqp)) ||
+        (st = zal(&H->d_P, 4 * (int64_t)H->nqp)) || (st = zal(&H->d_A, 16 * (int64_t)H->nqp)) ||
+        (st = zal(&H->d_w, H->state_doubles)) || (st = zal(&H->d_ke, 64 * (int64_t)H->nelem)) ||
+        (st = zal(&H->d_fe, 8 * (int64_t)H->nelem)) || (st = zal(&H->d_K, (int64_t)H->ndof * (H->bw + 1))) ||
+        (st = zal(&H->d_R, H->ndof)) || (st = zal(&H->d_norm, 2))) {
+        fehmm_free(H);
+        return st;
+    }
+    hipError_t e1 = hipMalloc((void**)&H->d_status, sizeof(int) * H->nqp);
+    hipError_t e2 = hipMalloc((void**)&H->d_iters, sizeof(int) * H->nqp);
+    hipError_t e3 = hipMalloc((void**)&H->d_flag, sizeof(int));
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        fehmm_free(H);
+        return set_error(RVE_ENOMEM, "fehmm_create: allocation failed");
+    }
+    *out = h.release();
+    return RVE_OK;
+}
+
+int fehmm_destroy(fehmm h) {
+    if (!h || !h->alive) return set_error(RVE_EINVAL, "fehmm_destroy: invalid handle");
+    fehmm_free(h);
+    h->alive = false;
+    return RVE_OK;
+}
+
+int fehmm_sizes(fehmm h, int32_t* ndof, int32_t* nqp, int64_t* state_doubles) {
+    if (!h || !h->alive) return set_error(RVE_EINVAL, "fehmm_sizes: invalid handle");
+    if (ndof) *ndof = h->ndof;
+    if (nqp) *nqp = h->nqp;
+    if (state_doubles) *state_doubles = h->state_doubles;
+    return RVE_OK;
+}
+
+int fehmm_macro_step(fehmm h, int32_t step, fehmm_step_info* info) {
+    if (!h || !h->alive) return set_error(RVE_EINVAL, "fehmm_macro_step: invalid handle");
+    const fehmm_desc& d = h->desc;
+    if (step < 1 || step > d.nsteps) return set_error(RVE_EINVAL, "fehmm_macro_step: step out of range");
+    fehmm_step_info loc;
+    fehmm_step_info* I = info ? info : &loc;
+    std::memset(I, 0, sizeof(*I));
+    hipStream_t s = h->stream;
+    // prescribed values of this step
+    std::vector<double> uval(h->ndof, 0.0);
+    const double ux = (d.stretch - 1.0) * d.Lx * (double)step / d.nsteps;
+    for (int v = 0; v < h->nnode; ++v)
+        if (h->fixed[2 * v] && h->xy[2 * v] > 0.5 * d.Lx) uval[2 * v] = ux;
+    FH_HIP(hipMemcpyAsync(h->d_uval, uval.data(), sizeof(double) * h->ndof, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(macro_dirichlet, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_u, h->d_fixed, h->d_uval,
+                       h->ndof);
+    rve_opts mo = d.micro_opts;
+    const bool alt = d.scheme == FEHMM_ALTERNATING;
+    if (alt) {
+        mo.max_iter = 1;
+        mo.flags |= RVE_FLAG_OUTPUTS_AT_CAP;
+    }
+    double r0 = -1.0;
+    int it = 0;
+    int64_t micro = 0;
+    std::vector<int> hiters(h->nqp);
+    for (;;) {
+        hipLaunchKernelGGL(macro_gather_F, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_conn, h->nelem, h->d_u,
+                           h->geom, h->d_F);
+        int st = rve_solve_batch(h->batch, h->d_F, h->d_P, h->d_A, h->d_w, h->d_status, h->d_iters, &mo, s);
+        if (st) return st;
+        hipLaunchKernelGGL(macro_element, dim3(nblk(8 * (int64_t)h->nelem, 256)), dim3(256), 0, s, h->nelem,
+                           h->d_P, h->d_A, h->geom, h->d_ke, h->d_fe);
+        const int64_t nK = (int64_t)h->ndof * (h->bw + 1);
+        hipLaunchKernelGGL(macro_zero, dim3(nblk(nK, 256)), dim3(256), 0, s, h->d_K, nK);
+        hipLaunchKernelGGL(macro_zero, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_R, (int64_t)h->ndof);
+        for (int c = 0; c < 4; ++c) {
+            const int nel = (int)h->colour[c].size();
+            if (nel == 0) continue;
+            hipLaunchKernelGGL(macro_scatter, dim3(nblk(8 * (int64_t)nel, 256)), dim3(256), 0, s, h->d_col[c], nel,
+                               h->d_conn, h->d_ke, h->d_fe, h->bw, h->d_K, h->d_R);
+        }
+        hipLaunchKernelGGL(macro_bc, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_fixed, h->ndof, h->bw, h->d_K,
+                           h->d_R);
+        hipLaunchKernelGGL(macro_norm, dim3(1), dim3(256), 0, s, h->d_R, h->ndof, h->d_status, h->nqp, alt ? 1 : 0,
+                           h->d_norm);
+        double hn[2];
+        FH_HIP(hipMemcpyAsync(hn, h->d_norm, sizeof(hn), hipMemcpyDeviceToHost, s));
+        FH_HIP(hipMemcpyAsync(hiters.data(), h->d_iters, sizeof(int) * h->nqp, hipMemcpyDeviceToHost, s));
+        FH_HIP(hipStreamSynchronize(s));
+        for (int q = 0; q < h->nqp; ++q) micro += hiters[q];
+        if (hn[1] > 0) {
+            I->status = FEHMM_STEP_RVE_FAILED;
+            I->failed_rves = (int)hn[1];
+            break;
+        }
+        const double rn = std::sqrt(hn[0]);
+        if (r0 < 0) r0 = rn;
+        I->res_hist[it] = r0 > 0 ? rn / r0 : 0.0;
+        if (rn <= d.rtol_macro * r0 || rn == 0.0) break;
+        if (it == d.max_macro_iter) {
+            I->status = FEHMM_STEP_NOCONV;
+            break;
+        }
+        hipLaunchKernelGGL(macro_zero_int, dim3(1), dim3(64), 0, s, h->d_flag, 1);
+        hipLaunchKernelGGL(macro_band_solve, dim3(1), dim3(NTB), 0, s, h->d_K, h->d_R, h->ndof, h->bw, h->d_du,
+                           h->d_flag);
+        hipLaunchKernelGGL(macro_update, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_u, h->d_du, h->d_fixed,
+                           h->ndof);
+        ++it;
+    }
+    I->macro_iters = it;
+    I->micro_iters = micro;
+    std::vector<double> u(h->ndof);
+    FH_HIP(hipMemcpyAsync(u.data(), h->d_u, sizeof(double) * h->ndof, hipMemcpyDeviceToHost, s));
+    int flag = 0;
+    FH_HIP(hipMemcpyAsync(&flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    FH_HIP(hipStreamSynchronize(s));
+    double um = 0.0;
+    for (int v = 0; v < h->nnode; ++v) um = std::max(um, std::hypot(u[2 * v], u[2 * v + 1]));
+    I->u_max = um;
+    if (flag && I->status == FEHMM_STEP_CONVERGED) I->status = FEHMM_STEP_NOCONV;
+    return I->status == FEHMM_STEP_CONVERGED ? RVE_OK : RVE_EPARTIAL;
+}
+
+int fehmm_get_nodes(fehmm h, double* xy) {
+    if (!h || !h->alive || !xy) return set_error(RVE_EINVAL, "fehmm_get_nodes: invalid argument");
+    std::memcpy(xy, h->xy.data(), sizeof(double) * h->xy.size());
+    return RVE_OK;
+}
+
+int fehmm_get_u(fehmm h, double* u) {
+    if (!h || !h->alive || !u) return set_error(RVE_EINVAL, "fehmm_get_u: invalid argument");
+    FH_HIP(hipMemcpy(u, h->d_u, sizeof(double) * h->ndof, hipMemcpyDeviceToHost));
+    return RVE_OK;
+}
+
+int fehmm_get_qp(fehmm h, double* F, double* P, double* A) {
+    if (!h || !h->alive) return set_error(RVE_EINVAL, "fehmm_get_qp: invalid handle");
+    FH_HIP(hipStreamSynchronize(h->stream));
+    if (F) FH_HIP(hipMemcpy(F, h->d_F, sizeof(double) * 4 * h->nqp, hipMemcpyDeviceToHost));
+    if (P) FH_HIP(hipMemcpy(P, h->d_P, sizeof(double) * 4 * h->nqp, hipMemcpyDeviceToHost));
+    if (A) FH_HIP(hipMemcpy(A, h->d_A, sizeof(double) * 16 * h->nqp, hipMemcpyDeviceToHost));
+    return RVE_OK;
+}
+
+int fehmm_get_state(fehmm h, double* u_host, double* w_host) {
+    if (!h || !h->alive || !u_host || !w_host) return set_error(RVE_EINVAL, "fehmm_get_state: invalid argument");
+    FH_HIP(hipStreamSynchronize(h->stream));
+    FH_HIP(hipMemcpy(u_host, h->d_u, sizeof(double) * h->ndof, hipMemcpyDeviceToHost));
+    FH_HIP(hipMemcpy(w_host, h->d_w, sizeof(double) * h->state_doubles, hipMemcpyDeviceToHost));
+    return RVE_OK;
+}
+
+int fehmm_set_state(fehmm h, const double* u_host, const double* w_host) {
+    if (!h || !h->alive || !u_host || !w_host) return set_error(RVE_EINVAL, "fehmm_set_state: invalid argument");
+    FH_HIP(hipStreamSynchronize(h->stream));
+    FH_HIP(hipMemcpy(h->d_u, u_host, sizeof(double) * h->ndof, hipMemcpyHostToDevice));
+    FH_HIP(hipMemcpy(h->d_w, w_host, sizeof(double) * h->state_doubles, hipMemcpyHostToDevice));
+    return RVE_OK;
+}
+
+}  // extern "C"

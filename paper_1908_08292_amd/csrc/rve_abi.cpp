@@ -132,6 +132,8 @@ int plan_device(PlanEntry* e) {
 
 }  // namespace
 
+int rve_internal_set_error(int code, const std::string& msg) { return fail(code, msg); }
+
 struct rve_mesh_s {
     int d = 0, n = 0, nphase = 0;
     std::vector<double> lame;
@@ -181,7 +183,7 @@ void rve_opts_default(rve_opts* o) {
     o->max_iter = 25;
     o->precision = RVE_PREC_FP64;
     o->det_backtrack = 8;
-    o->reserved = 0;
+    o->flags = 0;
 }
 
 const char* rve_strerror(int code) {
@@ -452,6 +454,7 @@ int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* 
     a.backtrack = o.det_backtrack;
     a.want_A = A != nullptr;
     a.dim = b->d;
+    a.flags = o.flags;
     a.lds_front = (int32_t)b->lds_front;
     hipError_t e = launch_rve_solve(a, b->nslots, b->dyn_bytes, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(RVE_EHIP, std::string("rve_solve_batch launch: ") + hipGetErrorString(e));

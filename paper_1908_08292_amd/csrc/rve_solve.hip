@@ -1001,6 +1001,7 @@ __global__ __launch_bounds__(NT) void rve_solve_kernel(SolveArgs a) {
         for (int t = threadIdx.x; t < ndof; t += NT) c.w[t] = (wst && t >= D) ? wst[t] : 0.0;
         __syncthreads();
         int status = 0, it = 0;
+        bool capped = false;
         if (!finite_in) status = 4;
         double r0 = 0.0;
         PROF_T0();
@@ -1017,7 +1018,11 @@ __global__ __launch_bounds__(NT) void rve_solve_kernel(SolveArgs a) {
             if (!isfinite(rn)) { status = 4; break; }
             if (it == 0) r0 = rn;
             if (rn <= a.rtol * r0 + sm.atol) break;
-            if (it == a.max_iter) { status = 1; break; }
+            if (it == a.max_iter) {
+                if (a.flags & 1) capped = true;  // outputs at the last state, reported as NOCONV
+                else status = 1;
+                break;
+            }
             for (int t = threadIdx.x; t < ndof; t += NT) c.rhs[t] = -c.R[t];
             __syncthreads();
             if (c.plan->lds_ok) factorize_lds<D, 1>(c, sm, dynF, dynF + a.lds_front);
@@ -1109,7 +1114,7 @@ __global__ __launch_bounds__(NT) void rve_solve_kernel(SolveArgs a) {
         }
         PROF_MARK(PH_FINAL);
         if (threadIdx.x == 0) {
-            if (a.status) a.status[rve] = status;
+            if (a.status) a.status[rve] = (status == 0 && capped) ? 1 : status;
             if (a.iters) a.iters[rve] = it;
             sm.flag = 0;
         }

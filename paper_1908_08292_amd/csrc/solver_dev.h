@@ -56,7 +56,7 @@ struct SolveArgs {
     double rtol, atol;
     int32_t max_iter, backtrack, want_A, dim;
     int32_t lds_front;           // doubles of the LDS front buffer (rhs rows follow it)
-    int32_t pad;
+    int32_t flags;               // RVE_FLAG_* of the options
 };
 
 // LDS available to the front buffer (packed front + m x d^2 rhs rows)

@@ -34,7 +34,7 @@ class MeshDesc(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
-                ("det_backtrack", C.c_int32), ("reserved", C.c_int32)]
+                ("det_backtrack", C.c_int32), ("flags", C.c_int32)]
 
 
 _lib = None

@@ -146,3 +146,12 @@ def test_plan_drives_a_correct_multifrontal_solve(d, n):
     ref = np.linalg.solve(K, b[d:])
     assert np.abs(x[d:] - ref).max() < 1e-9 * np.abs(ref).max()
     assert np.all(x[:d] == 0)
+
+
+def test_fehmm_symbols_exported():
+    from paper_1908_08292_amd import fehmm
+    names = fehmm.declared_functions()
+    assert "fehmm_macro_step" in names and len(names) == 9
+    L = fehmm.lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
