@@ -16,6 +16,11 @@ Prints one JSON line.  Options:
   --no-cpu-baseline        skip the oracle timing
   --calib-copy MiB         after the timed steps, run one plain device copy of
                            this size (for HBM counter calibration under rocprofv3)
+  --macro                  also time the two-scale driver (macro steps/s): 4 x 4
+                           macro grid / RVE 8 x 8 over 10 load steps, and the
+                           64 x 64 plate with a hole (14288 RVEs of 16 x 16) over
+                           its first --macro-steps of 20 load steps, nested and
+                           alternating two-level Newton
 """
 import argparse
 import json
@@ -61,6 +66,29 @@ def algorithmic_flops(rve, d, n_arr, iters):
     return total
 
 
+KERNEL_SOURCES = ["rve_solve.hip", "plan.cpp", "plan.h", "solver_dev.h", "mesh_common.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1908_08292_amd", "csrc")
+    blob = b"".join(open(os.path.join(csrc, f), "rb").read() for f in KERNEL_SOURCES)
+    return hashlib.sha256(blob).hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary of this workload, scaled by the copy-kernel calibration; None when
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"rve_solve_kernel_{workload}.hbm.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(wl, meta, budget_rves):
     import oracle
     d = meta["d"]
@@ -90,6 +118,36 @@ def cpu_baseline(wl, meta, budget_rves):
                        f"OpenMP over RVEs, {nthreads} threads)")
 
 
+def macro_bench(nsteps3):
+    """Macro steps/s of the GPU two-scale driver (host wall clock per load step)."""
+    from paper_1908_08292_amd import fehmm, rve
+    res = {}
+    lame = rve.two_phase_lame(10.0)
+    cases = [("plate4x4_rve8x8", dict(nx=4, ny=4, hole_r=0.0, bc=fehmm.BC_CLAMPED_PULL, stretch=1.1, nsteps=10),
+              8, 10),
+             ("plate64x64_hole_rve16x16", dict(nx=64, ny=64, hole_r=0.2, bc=fehmm.BC_UNIAXIAL, stretch=1.15,
+                                                nsteps=20), 16, nsteps3)]
+    for name, kw, n, nrun in cases:
+        for scheme, sname in ((fehmm.NESTED, "nested"), (fehmm.ALTERNATING, "alternating")):
+            mesh = rve.Mesh(2, n, lame, radius=0.25)
+            drv = fehmm.Driver(mesh, scheme=scheme, **kw)
+            t0 = time.perf_counter()
+            its, mic, ok = [], 0, True
+            for k in range(1, nrun + 1):
+                st = drv.step(k)
+                its.append(st["macro_iters"])
+                mic += st["micro_iters"]
+                ok = ok and st["status"] == 0
+                print(f"[bench] {name} {sname} step {k}: {st['macro_iters']} macro iters", file=sys.stderr,
+                      flush=True)
+            dt = time.perf_counter() - t0
+            res[f"{name}_{sname}"] = dict(macro_steps_per_s=nrun / dt, steps=nrun, rves=drv.nqp,
+                                          macro_iters=its, micro_iters=int(mic), converged=bool(ok),
+                                          seconds=dt)
+            drv.destroy()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +157,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--calib-copy", type=int, default=0)
+    ap.add_argument("--macro", action="store_true")
+    ap.add_argument("--macro-steps", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the RVE batch would be sharded by macro elements "
@@ -160,10 +220,13 @@ def main():
         "config": {"workload": meta["workload"], "rves": B, "dim": d, "elements_per_edge": meta["n"],
                    "precision": "fp64", "newton_rtol": 1e-10,
                    "mean_newton_iters": float(res["iters"].mean()), "failed_rves": nbad},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "rve_solve_kernel<2>", "flops_per_launch": flops},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(meta["workload"]),
+                     "kernel": f"rve_solve_kernel<{d}>", "flops_per_launch": flops,
+                     "flops_counted": "LDL^T factorizations + triangular solves from the symbolic plan"},
     }
+    if args.macro:
+        out["macro"] = macro_bench(args.macro_steps)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, meta, args.cpu_sample)
