@@ -926,7 +926,7 @@ __device__ double free_norm2(const RveCtx& c, Smem& sm, const double* R) {
 }
 
 template <int D>
-__global__ __launch_bounds__(NT) void rve_solve_kernel(SolveArgs a) {
+__global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
     __shared__ Smem sm;
     extern __shared__ double dynF[];
     constexpr int NEN = 1 << D, ND = NEN * D, D2 = D * D;
