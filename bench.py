@@ -158,6 +158,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--calib-copy", type=int, default=0)
     ap.add_argument("--macro", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64")
     ap.add_argument("--macro-steps", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -174,11 +175,12 @@ def main():
     batch, meshes = api.build_batch(d, wl.n, wl.radius, wl.ratio)
     s = api.Solver(batch, want_A=True, keep_state=False)
     s.set_F(wl.F)
+    opts = rve.default_opts(precision=rve.PREC_FP32_IR if args.precision == "fp32ir" else rve.PREC_FP64)
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
     print(f"[bench] {meta['workload']}: warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        s.solve(stream=sp)
+        s.solve(opts=opts, stream=sp)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -186,7 +188,7 @@ def main():
     t0 = time.perf_counter()
     ev0.record(stream)
     for k in range(args.steps):
-        s.solve(stream=sp)
+        s.solve(opts=opts, stream=sp)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -215,10 +217,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32 factors + f64 refinement",
         "data": "synthetic",
         "config": {"workload": meta["workload"], "rves": B, "dim": d, "elements_per_edge": meta["n"],
-                   "precision": "fp64", "newton_rtol": 1e-10,
+                   "precision": args.precision, "newton_rtol": 1e-10,
                    "mean_newton_iters": float(res["iters"].mean()), "failed_rves": nbad},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(meta["workload"]),

@@ -17,7 +17,8 @@
 #include "solver_dev.h"
 
 namespace fehmm {
-hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, hipStream_t stream);
+hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, bool fp32, hipStream_t stream);
+hipError_t prepare_rve_solve();
 int lds_static_bytes();
 constexpr int NWAVE_ = 4;  // waves per workgroup of the solve kernel
 }
@@ -56,7 +57,9 @@ struct PlanEntry {
     int32_t* d_wave_hbeg = nullptr;
     int refs = 0;
     int device = -1;
-    int64_t lds_bytes = 0;
+    int64_t lds_bytes = 0;            // FP64 fronts: dynamic LDS bytes
+    int64_t front_elems[2] = {0, 0};  // LDS front region (elements of FP64 / FP32)
+    int64_t rl_elems = 0;             // rhs rows following it
 };
 
 std::mutex g_mu;
@@ -120,9 +123,16 @@ int plan_device(PlanEntry* e) {
                      e->d_asm_rc, e->d_asm_src, e->d_ea_dst, e->d_wave_list, e->d_wave_hbeg,
                      (int32_t)P.wave_hbeg.size() - 1, (int32_t)P.wave_slice};
     if (P.wave_hbeg.empty()) e->dev.nwave_h = 0;
-    // whole fronts in LDS when the largest packed front plus its rhs rows fit
+    // whole fronts in LDS when the largest packed front plus its rhs rows fit;
+    // the front region also hosts the FP64 scratch of the triangular solves
+    // (m d^2 + 3 m doubles)
     const int64_t mm = P.max_m;
-    const int64_t need = std::max<int64_t>(mm * (mm + 1) / 2 + mm * P.d * P.d, NWAVE_ * P.wave_slice) *
+    int64_t scratch = 0;
+    for (const FrontHost& fr : P.fronts) scratch = std::max<int64_t>(scratch, (int64_t)fr.m * (P.d * P.d + 3));
+    e->front_elems[0] = std::max<int64_t>(mm * (mm + 1) / 2, scratch);
+    e->front_elems[1] = std::max<int64_t>(mm * (mm + 1) / 2, 2 * scratch);
+    e->rl_elems = mm * P.d * P.d;
+    const int64_t need = std::max<int64_t>(e->front_elems[0] + e->rl_elems, NWAVE_ * P.wave_slice) *
                          (int64_t)sizeof(double);
     e->lds_bytes = need;
     // (one thread per front row in the pivot sweep: m <= 256; the plan decides)
@@ -147,8 +157,9 @@ struct rve_batch_s {
     int d = 0;
     int64_t B = 0;
     int nslots = 0;
-    int64_t lds_front = 0;   // doubles of the packed front part of the dynamic LDS
-    size_t dyn_bytes = 0;
+    int64_t lds_front[2] = {0, 0};  // front region of the dynamic LDS (FP64 / FP32 elements)
+    int64_t wave_slice = 0;         // elements per wave slice
+    size_t dyn_bytes[2] = {0, 0};
     SlotLayout lay{};
     std::vector<int64_t> state_off;
     // device
@@ -355,11 +366,18 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
     }
     for (PlanEntry* p : plans)
         if (p->dev.lds_ok) {
-            const int64_t mm = p->host.max_m;
-            b->lds_front = std::max(b->lds_front, mm * (mm + 1) / 2);
-            if (!p->dev.lds_ok) continue;
-            b->dyn_bytes = std::max(b->dyn_bytes, (size_t)p->lds_bytes);
+            for (int k = 0; k < 2; ++k) b->lds_front[k] = std::max(b->lds_front[k], p->front_elems[k]);
+            b->wave_slice = std::max(b->wave_slice, p->host.wave_slice);
         }
+    {
+        int64_t rl = 0;
+        for (PlanEntry* p : plans)
+            if (p->dev.lds_ok) rl = std::max(rl, p->rl_elems);
+        for (int k = 0; k < 2; ++k) {
+            const int64_t es = k == 0 ? 8 : 4;
+            b->dyn_bytes[k] = (size_t)(std::max(b->lds_front[k] + rl, NWAVE_ * b->wave_slice) * es);
+        }
+    }
     auto rnd = [](int64_t x) { return (x + 31) / 32 * 32; };
     SlotLayout& L = b->lay;
     int64_t o = 0;
@@ -374,6 +392,8 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
     L.L = o; o += rnd(Lsz);
     L.U = o; o += rnd(std::max<int64_t>(Ust, 1));
     L.S = o; o += rnd(std::max<int64_t>(Usc, 1));
+    L.ir1 = o; o += rnd(nn * d * d2);
+    L.ir2 = o; o += rnd(nn * d * d2);
     L.stride = o;
     size_t free_b = 0, total_b = 0;
     HIP_OR(hipMemGetInfo(&free_b, &total_b));
@@ -427,7 +447,14 @@ int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* 
         return fail(RVE_EINVAL, "rve_solve_batch: options out of range");
     if (o.precision != RVE_PREC_FP64 && o.precision != RVE_PREC_FP32_IR)
         return fail(RVE_EINVAL, "rve_solve_batch: unknown precision");
-    if (o.precision != RVE_PREC_FP64) return fail(RVE_EUNSUPPORTED, "rve_solve_batch: FP32_IR not built yet");
+    static bool prepared = false;
+    if (!prepared) {
+        hipError_t pe = prepare_rve_solve();
+        if (pe != hipSuccess) return fail(RVE_EHIP, std::string("rve_solve_batch: ") + hipGetErrorString(pe));
+        prepared = true;
+    }
+    // FP32 factors apply to the 2D LDS-resident plans; other plans stay FP64
+    const bool fp32 = o.precision == RVE_PREC_FP32_IR && b->d == 2;
     SolveArgs a{};
     a.plans = b->d_plans;
     a.rve_plan = b->d_rve_plan;
@@ -455,8 +482,17 @@ int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* 
     a.want_A = A != nullptr;
     a.dim = b->d;
     a.flags = o.flags;
-    a.lds_front = (int32_t)b->lds_front;
-    hipError_t e = launch_rve_solve(a, b->nslots, b->dyn_bytes, (hipStream_t)hip_stream);
+    const int k = fp32 ? 1 : 0;
+    a.lds_front = (int32_t)b->lds_front[k];
+    a.wave_slice = (int32_t)b->wave_slice;
+    // FP32 factors: a Newton step is refined only when ||b - K64 x|| > 1e-2 ||b||
+    // (inexact Newton; convergence is judged on the FP64 residual); the tangent
+    // gets one refinement sweep and the second-order form
+    a.ir_max = 2;
+    a.ir_max_tan = 1;
+    a.ir_eta = 1e-2;
+    a.ir_eta_tan = 0.0;
+    hipError_t e = launch_rve_solve(a, b->nslots, b->dyn_bytes[k], fp32, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(RVE_EHIP, std::string("rve_solve_batch launch: ") + hipGetErrorString(e));
     return RVE_OK;
 }

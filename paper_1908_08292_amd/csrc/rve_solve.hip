@@ -64,7 +64,6 @@ struct Smem {
     double pub[2][18 + kMaxNrhs];  // pivot publication (double-buffered)
     double red[NWAVE * 81];
     double dN[8 * 8 * 3];    // [gp][a][k]
-    double dd[8 * 8 * 8];    // [gp][a][b] grad N_a . grad N_b
     double Fbar[9];
     double outv[96];
     double wJ, r0, rnorm, atol, alpha;
@@ -243,7 +242,9 @@ __device__ __noinline__ void element_pass(const RveCtx& c, Smem& sm, const doubl
                     fr[r] += (mu * FdN - c1 * ga[i]) * wJ;
 #pragma unroll
                     for (int b = 0; b < NEN; ++b) {
-                        const double dab = sm.dd[(gp * 8 + a) * 8 + b];
+                        double dab = 0.0;
+#pragma unroll
+                        for (int k2 = 0; k2 < D; ++k2) dab += dNa[k2] * sm.dN[(gp * 8 + b) * 3 + k2];
 #pragma unroll
                         for (int k = 0; k < D; ++k)
                             kr[r][b * D + k] += ((i == k ? mu * dab : 0.0) + c1 * ga[k] * g[b][i] + c2 * ga[i] * g[b][k]) * wJ;
@@ -469,15 +470,15 @@ __device__ inline double readlane_d(double v, int l) {
 // Assembly as in the workgroup path, then a right-looking LDL^T sweep over the
 // p pivots done in place in LDS (the wave's slice); within a wave LDS accesses
 // complete in issue order, so no barrier is needed between pivots.
-template <int D, int NRHS>
-__device__ void wave_front(const RveCtx& c, Smem& sm, int s, double* F, double* rl) {
+template <int D, int NRHS, typename T>
+__device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
     const DevPlan& pl = *c.plan;
     constexpr int NEN = 1 << D;
     const int lane = threadIdx.x & 63;
     const DevFront fr = pl.fronts[s];
     const int m = fr.m, p = fr.p, mu = m - p;
     const int32_t* rows = pl.rows + fr.rows_off;
-    double* Lg = c.L + fr.L_off;
+    T* Lg = reinterpret_cast<T*>(c.L + fr.L_off);
     double* Dg = c.L + fr.D_off;
     double* yg = c.L + fr.y_off;
     const int tot = cpk(m, m);
@@ -504,9 +505,9 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, double* F, double* 
         const DevFront ch = pl.fronts[pl.children[q]];
         const int mc = ch.m - ch.p;
         const int32_t* rel = pl.relind + ch.relind_off;
-        const double* Uc = c.U + ch.U_off;
+        const T* Uc = reinterpret_cast<const T*>(c.U + ch.U_off);
         const int nu = cpk(mc, mc);
-        const double* ruc = Uc + nu;
+        const T* ruc = Uc + nu;
         const int32_t* ea = pl.ea_dst + ch.ea_off;
         for (int t = lane; t < nu; t += 64) F[ea[t]] += Uc[t];
         for (int t = lane; t < mc * NRHS; t += 64) {
@@ -515,7 +516,7 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, double* F, double* 
         }
         __builtin_amdgcn_wave_barrier();
     }
-    double* W = rl + m * NRHS;  // 16 x 16 scratch of this wave's slice
+    T* W = rl + m * NRHS;  // 16 x 16 scratch of this wave's slice
     for (int K = 0; K < p; K += 16) {
         const int kb = min(16, p - K);
         // diagonal block: lane r < kb holds row r; readlane broadcast of pivots/multipliers
@@ -665,7 +666,7 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, double* F, double* 
         yg[t] = rl[col * m + j];
     }
     if (mu > 0) {
-        double* dst = c.U + fr.U_off;
+        T* dst = reinterpret_cast<T*>(c.U + fr.U_off);
         const int usz = tot - lp;
         for (int t = lane; t < usz; t += 64) dst[t] = F[lp + t];
         for (int t = lane; t < mu * NRHS; t += 64) {
@@ -676,8 +677,8 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, double* F, double* 
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int D, int NRHS>
-__device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, double* F, double* rl) {
+template <int D, int NRHS, typename T>
+__device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* rl, int wave_slice) {
     constexpr int nrhs = NRHS;
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -685,11 +686,11 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, double* F,
     PROF_T0();
     // small subtrees: one front per wave, all fronts of one height at a time
     for (int h = 0; h < pl.nwave_h; ++h) {
-        double* Fw = F + (int64_t)wave * pl.wave_slice;
+        T* Fw = F + (int64_t)wave * wave_slice;
         for (int k = pl.wave_hbeg[h] + wave; k < pl.wave_hbeg[h + 1]; k += NWAVE) {
             const int sw = pl.wave_list[k];
             const int mw = pl.fronts[sw].m;
-            wave_front<D, NRHS>(c, sm, sw, Fw, Fw + cpk(mw, mw));
+            wave_front<D, NRHS, T>(c, sm, sw, Fw, Fw + cpk(mw, mw));
         }
         __syncthreads();
     }
@@ -699,7 +700,7 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, double* F,
         if (fr.wave) continue;
         const int m = fr.m, p = fr.p, mu = m - p;
         const int32_t* rows = pl.rows + fr.rows_off;
-        double* Lg = c.L + fr.L_off;
+        T* Lg = reinterpret_cast<T*>(c.L + fr.L_off);
         double* Dg = c.L + fr.D_off;
         double* yg = c.L + fr.y_off;
         const int tot = cpk(m, m);
@@ -727,9 +728,9 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, double* F,
             const DevFront ch = pl.fronts[pl.children[q]];
             const int mc = ch.m - ch.p;
             const int32_t* rel = pl.relind + ch.relind_off;
-            const double* Uc = c.U + ch.U_off;
+            const T* Uc = reinterpret_cast<const T*>(c.U + ch.U_off);
             const int nu = cpk(mc, mc);
-            const double* ruc = Uc + nu;
+            const T* ruc = Uc + nu;
             const int32_t* ea = pl.ea_dst + ch.ea_off;
             for (int t = tid; t < nu; t += NT) F[ea[t]] += Uc[t];
             for (int t = tid; t < mc * nrhs; t += NT) {
@@ -835,7 +836,7 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, double* F,
             yg[t] = rl[col * m + j];
         }
         if (mu > 0) {
-            double* dst = c.U + fr.U_off;
+            T* dst = reinterpret_cast<T*>(c.U + fr.U_off);
             const int usz = tot - lp;
             for (int t = tid; t < usz; t += NT) dst[t] = F[lp + t];
             for (int t = tid; t < mu * nrhs; t += NT) {
@@ -848,39 +849,80 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, double* F,
     }
 }
 
-// backward substitution L^T x = D^-1 y (nrhs = 1) over packed L panels staged in
-// LDS; 16-pivot blocks from the last: the block triangle is solved in registers
-// of wave 0 (readlane chain), then all threads fold the block into the rest.
-template <int D>
-__device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, double* F, double* rl) {
+// backward substitution L^T x = D^-1 y with NRHS columns; y is each front's
+// stored forward-substituted rhs, x (node-major [dof][NRHS], FP64) receives the
+// solution.  FP64 panels are staged in LDS; FP32 panels are read from global
+// memory and the LDS front buffer serves as FP64 scratch.  16-pivot blocks from
+// the last: the block triangle is solved in registers of wave 0 (readlane
+// chain), then all threads fold the block into the remaining pivots.
+template <int D, int NRHS, typename T>
+__device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* rl, double* x, int front_elems) {
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int t = tid; t < D; t += NT) c.x[t] = 0.0;
+    constexpr int NPART = (NRHS == 1) ? 3 : 1;
+    for (int t = tid; t < D * NRHS; t += NT) x[t] = 0.0;  // pinned node
     for (int s = pl.nfront - 1; s >= 0; --s) {
         const DevFront fr = pl.fronts[s];
         const int m = fr.m, p = fr.p;
         const int32_t* rows = pl.rows + fr.rows_off;
-        const double* Lg = c.L + fr.L_off;
+        const T* Lg = reinterpret_cast<const T*>(c.L + fr.L_off);
         const double* Dg = c.L + fr.D_off;
         const double* yg = c.L + fr.y_off;
         const int lp = cpk(p, m);
-        double* v = rl;       // [p]
-        double* xs = rl + p;  // [m - p] solution at the update rows
-        for (int t = tid; t < lp; t += NT) F[t] = Lg[t];
-        for (int t = tid; t < p; t += NT) v[t] = yg[t] / Dg[t];
-        for (int t = tid; t < m - p; t += NT) xs[t] = c.x[rows[p + t]];
-        __syncthreads();
-        // v_j -= sum_{i >= p} L(i, j) x_i : 3 partial sums per column (the rhs rows
-        // hold m * d^2 >= m + 3 p doubles)
-        for (int t = tid; t < 3 * p; t += NT) {
-            const int j = t % p, part = t / p;
-            const double* colj = F + cpk(j, m) - j;
-            double a = 0.0;
-            for (int i = p + part; i < m; i += 3) a += colj[i] * xs[i - p];
-            rl[m + t] = a;
+        const T* Lp;
+        double* vb;
+        if constexpr (sizeof(T) == sizeof(double)) {
+            for (int t = tid; t < lp; t += NT) F[t] = Lg[t];
+            Lp = F;
+            vb = reinterpret_cast<double*>(rl);
+        } else {
+            // FP32 panel staged after the FP64 scratch when both fit the front region
+            const int vneed = 2 * (m * NRHS + 3 * p);
+            if (vneed + lp <= front_elems) {
+                for (int t = tid; t < lp; t += NT) F[vneed + t] = Lg[t];
+                Lp = F + vneed;
+            } else {
+                Lp = Lg;
+            }
+            vb = reinterpret_cast<double*>(F);
+        }
+        double* v = vb;                 // [NRHS][p]
+        double* xs = vb + NRHS * p;     // [NRHS][m - p]
+        double* part = vb + NRHS * m;   // [NPART][p] (NRHS == 1)
+        for (int t = tid; t < p * NRHS; t += NT) {
+            const int j = t % p, q = t / p;
+            v[t] = yg[(int64_t)q * p + j] / Dg[j];
+        }
+        for (int t = tid; t < (m - p) * NRHS; t += NT) {
+            const int i = t % (m - p), q = t / (m - p);
+            xs[t] = x[(int64_t)rows[p + i] * NRHS + q];
         }
         __syncthreads();
-        for (int j = tid; j < p; j += NT) v[j] -= (rl[m + j] + rl[m + p + j]) + rl[m + 2 * p + j];
+        if constexpr (NRHS == 1) {
+            for (int t = tid; t < NPART * p; t += NT) {
+                const int j = t % p, pt = t / p;
+                const T* colj = Lp + cpk(j, m) - j;
+                double acc = 0.0;
+                for (int i = p + pt; i < m; i += NPART) acc += (double)colj[i] * xs[i - p];
+                part[t] = acc;
+            }
+            __syncthreads();
+            for (int j = tid; j < p; j += NT) v[j] -= (part[j] + part[p + j]) + part[2 * p + j];
+        } else {
+            for (int j = tid; j < p; j += NT) {
+                const T* colj = Lp + cpk(j, m) - j;
+                double acc[NRHS];
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) acc[q] = 0.0;
+                for (int i = p; i < m; ++i) {
+                    const double l = colj[i];
+#pragma unroll
+                    for (int q = 0; q < NRHS; ++q) acc[q] += l * xs[q * (m - p) + i - p];
+                }
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) v[q * p + j] -= acc[q];
+            }
+        }
         __syncthreads();
         const int nb = (p + 15) >> 4;
         for (int bk = nb - 1; bk >= 0; --bk) {
@@ -890,30 +932,156 @@ __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, double* F,
                 double Lr[16];
 #pragma unroll
                 for (int cc = 0; cc < 16; ++cc)
-                    Lr[cc] = (own && cc < kb && cc > lane) ? F[cpk(K + lane, m) + cc - lane] : 0.0;
-                double vv = own ? v[K + lane] : 0.0;
+                    Lr[cc] = (own && cc < kb && cc > lane) ? (double)Lp[cpk(K + lane, m) + cc - lane] : 0.0;
 #pragma unroll
-                for (int cc = 15; cc >= 0; --cc) {
-                    if (cc < kb) {
-                        const double xc = readlane_d(vv, cc);
-                        if (lane < cc) vv -= Lr[cc] * xc;
+                for (int q = 0; q < NRHS; ++q) {
+                    double vv = own ? v[q * p + K + lane] : 0.0;
+#pragma unroll
+                    for (int cc = 15; cc >= 0; --cc) {
+                        if (cc < kb) {
+                            const double xc = readlane_d(vv, cc);
+                            if (lane < cc) vv -= Lr[cc] * xc;
+                        }
                     }
+                    if (own) v[q * p + K + lane] = vv;
                 }
-                if (own) v[K + lane] = vv;
             }
             __syncthreads();
             for (int j = tid; j < K; j += NT) {
-                const double* colj = F + cpk(j, m) - j;
-                double a = v[j];
+                const T* colj = Lp + cpk(j, m) - j;
+                double lk[16];
 #pragma unroll
-                for (int cc = 0; cc < 16; ++cc)
-                    if (cc < kb) a -= colj[K + cc] * v[K + cc];
-                v[j] = a;
+                for (int cc = 0; cc < 16; ++cc) lk[cc] = (cc < kb) ? (double)colj[K + cc] : 0.0;
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) {
+                    double acc = v[q * p + j];
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc)
+                        if (cc < kb) acc -= lk[cc] * v[q * p + K + cc];
+                    v[q * p + j] = acc;
+                }
             }
             __syncthreads();
         }
-        for (int j = tid; j < p; j += NT) c.x[rows[j]] = v[j];
+        for (int t = tid; t < p * NRHS; t += NT) {
+            const int j = t % p, q = t / p;
+            x[(int64_t)rows[j] * NRHS + q] = v[t];
+        }
         __syncthreads();
+    }
+}
+
+// forward substitution L y = b for a new rhs b (node-major [dof][NRHS], FP64,
+// overwritten): fronts in elimination order; per front the pivot rows are
+// solved in 16-pivot blocks (readlane chain in wave 0) and folded into the rows
+// below; the update rows are scattered back into b; the pivot part is stored as
+// the front's forward-substituted rhs for backsolve_lds.
+template <int D, int NRHS, typename T>
+__device__ __noinline__ void forward_lds(const RveCtx& c, Smem& sm, T* F, double* b, int front_elems) {
+    const DevPlan& pl = *c.plan;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* vb = reinterpret_cast<double*>(F);  // [NRHS][m] front rows of b
+    for (int s = 0; s < pl.nfront; ++s) {
+        const DevFront fr = pl.fronts[s];
+        const int m = fr.m, p = fr.p;
+        const int32_t* rows = pl.rows + fr.rows_off;
+        const T* Lp = reinterpret_cast<const T*>(c.L + fr.L_off);
+        {
+            // stage the panel after the FP64 rows of b when both fit
+            const int vneed = (int)((sizeof(double) / sizeof(T)) * m * NRHS);
+            const int lp = cpk(p, m);
+            if (vneed + lp <= front_elems) {
+                T* Ls = F + vneed;
+                for (int t = tid; t < lp; t += NT) Ls[t] = Lp[t];
+                Lp = Ls;
+            }
+        }
+        double* yg = c.L + fr.y_off;
+        for (int t = tid; t < m * NRHS; t += NT) {
+            const int i = t % m, q = t / m;
+            vb[t] = (i < p) ? b[(int64_t)rows[i] * NRHS + q] : 0.0;
+        }
+        __syncthreads();
+        for (int K = 0; K < p; K += 16) {
+            const int kb = min(16, p - K);
+            if (wave == 0) {
+                const bool own = lane < kb;
+                double Lr[16];
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc)
+                    Lr[cc] = (own && cc < kb && cc < lane) ? (double)Lp[cpk(K + cc, m) + lane - cc] : 0.0;
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) {
+                    double vv = own ? vb[q * m + K + lane] : 0.0;
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc) {
+                        if (cc < kb) {
+                            const double yc = readlane_d(vv, cc);
+                            if (lane > cc) vv -= Lr[cc] * yc;
+                        }
+                    }
+                    if (own) vb[q * m + K + lane] = vv;
+                }
+            }
+            __syncthreads();
+            for (int i = K + kb + tid; i < m; i += NT) {
+                double lk[16];
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc) lk[cc] = (cc < kb) ? (double)Lp[cpk(K + cc, m) + i - K - cc] : 0.0;
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) {
+                    double acc = vb[q * m + i];
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc)
+                        if (cc < kb) acc -= lk[cc] * vb[q * m + K + cc];
+                    vb[q * m + i] = acc;
+                }
+            }
+            __syncthreads();
+        }
+        for (int t = tid; t < p * NRHS; t += NT) {
+            const int j = t % p, q = t / p;
+            yg[(int64_t)q * p + j] = vb[q * m + j];
+        }
+        for (int t = tid; t < (m - p) * NRHS; t += NT) {
+            const int i = t % (m - p), q = t / (m - p);
+            b[(int64_t)rows[p + i] * NRHS + q] += vb[q * m + p + i];  // rows[p+i] holds b; add the update
+        }
+        __syncthreads();
+    }
+}
+
+// out = b - K x with the FP64 element tangents (matrix-free), free rows only;
+// node-major [dof][NRHS]
+template <int D, int NRHS>
+__device__ void residual_ke(const RveCtx& c, const double* b, const double* x, double* out) {
+    constexpr int NEN = 1 << D, ND = NEN * D;
+    const int tot = c.nn * D;
+    for (int vi = threadIdx.x; vi < tot; vi += NT) {
+        const int v = vi / D, i = vi % D;
+        double acc[NRHS];
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) acc[q] = 0.0;
+        if (v != 0) {
+#pragma unroll
+            for (int a = 0; a < NEN; ++a) {
+                const int e = element_of_node(D, c.n, v, a);
+                int nodes[NEN];
+                element_nodes(D, c.n, e, nodes);
+                const double* kr = c.ke + ((int64_t)e * ND + a * D + i) * ND;
+#pragma unroll
+                for (int bb = 0; bb < NEN; ++bb)
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const double kv = kr[bb * D + k];
+                        const double* xr = x + ((int64_t)nodes[bb] * D + k) * NRHS;
+#pragma unroll
+                        for (int q = 0; q < NRHS; ++q) acc[q] += kv * xr[q];
+                    }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) out[(int64_t)vi * NRHS + q] = (v != 0) ? b[(int64_t)vi * NRHS + q] - acc[q] : 0.0;
     }
 }
 
@@ -925,10 +1093,12 @@ __device__ double free_norm2(const RveCtx& c, Smem& sm, const double* R) {
     return sm.outv[0];
 }
 
-template <int D>
+template <int D, typename T>
 __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
     __shared__ Smem sm;
-    extern __shared__ double dynF[];
+    extern __shared__ double dynRaw[];
+    T* dynF = reinterpret_cast<T*>(dynRaw);
+    constexpr bool IR = sizeof(T) < sizeof(double);  // FP32 factors + FP64 refinement
     constexpr int NEN = 1 << D, ND = NEN * D, D2 = D * D;
     const int64_t slot = blockIdx.x;
     double* base = a.ws + slot * a.lay.stride;
@@ -961,6 +1131,8 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
         c.L = base + a.lay.L;
         c.U = base + a.lay.U;
         c.S = base + a.lay.S;
+        double* ir1 = base + a.lay.ir1;
+        double* ir2 = base + a.lay.ir2;
         const int ndof = c.nn * D;
         // constants of the uniform grid: grad N at the Gauss points, w|J|
         if (threadIdx.x < NEN * NEN) {
@@ -987,12 +1159,6 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
             sm.atol = a.atol >= 0 ? a.atol : a.rve_atol[rve];
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < NEN * NEN * NEN; t += NT) {
-            const int gp = t / (NEN * NEN), an = (t / NEN) % NEN, bn = t % NEN;
-            double s = 0;
-            for (int k = 0; k < D; ++k) s += sm.dN[(gp * 8 + an) * 3 + k] * sm.dN[(gp * 8 + bn) * 3 + k];
-            sm.dd[(gp * 8 + an) * 8 + bn] = s;
-        }
         // input checks and initial guess
         bool finite_in = true;
 #pragma unroll
@@ -1025,13 +1191,28 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
             }
             for (int t = threadIdx.x; t < ndof; t += NT) c.rhs[t] = -c.R[t];
             __syncthreads();
-            if (c.plan->lds_ok) factorize_lds<D, 1>(c, sm, dynF, dynF + a.lds_front);
+            if (c.plan->lds_ok) factorize_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
             else factorize_glb<D>(c, sm, 1);
             if (sm.flag) { status = 3; break; }
             PROF_RESET();
-            if (c.plan->lds_ok) backsolve_lds<D>(c, sm, dynF, dynF + a.lds_front);
+            if (c.plan->lds_ok) backsolve_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, c.x, a.lds_front);
             else backsolve_glb<D>(c, sm);
             PROF_MARK(PH_BACK);
+            if constexpr (IR) {
+                // refinement against the FP64 tangent: dx = K32^-1 (b - K64 x)
+                if (c.plan->lds_ok) {
+                    for (int ref = 0; ref < a.ir_max; ++ref) {
+                        residual_ke<D, 1>(c, c.rhs, c.x, ir1);
+                        __syncthreads();
+                        const double rl2 = sqrt(free_norm2<D>(c, sm, ir1));
+                        if (!(rl2 > a.ir_eta * rn)) break;
+                        forward_lds<D, 1, T>(c, sm, dynF, ir1, a.lds_front);
+                        backsolve_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front);
+                        for (int t = threadIdx.x; t < ndof; t += NT) c.x[t] += ir2[t];
+                        __syncthreads();
+                    }
+                }
+            }
             // step with det F backtracking
             double alpha = 1.0;
             bool ok = false;
@@ -1074,10 +1255,39 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
                 __syncthreads();
                 node_gather<D>(c, c.re, D2, c.rhs, 1.0);
                 __syncthreads();
-                if (c.plan->lds_ok) factorize_lds<D, D2>(c, sm, dynF, dynF + a.lds_front);
+                if (c.plan->lds_ok) factorize_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
                 else factorize_glb<D>(c, sm, D2);
                 if (sm.flag) {
                     status = 3;
+                } else if (IR && c.plan->lds_ok) {
+                    // X ~ K^-1 Y from the FP32 factors, refined ir_max_tan times against
+                    // the FP64 tangent; then the stationary (second-order) form
+                    //   Abar = <A> - Y^T X - X^T r,  r = Y - K X,
+                    // whose error is (X - X*)^T K (X - X*) (energy-norm error squared)
+                    double* X = c.re;  // element Y no longer needed: [dof][D2]
+                    backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front);
+                    for (int ref = 0;; ++ref) {
+                        residual_ke<D, D2>(c, c.rhs, X, ir1);
+                        __syncthreads();
+                        if (ref == a.ir_max_tan) break;
+                        forward_lds<D, D2, T>(c, sm, dynF, ir1, a.lds_front);
+                        backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front);
+                        for (int t = threadIdx.x; t < ndof * D2; t += NT) X[t] += ir2[t];
+                        __syncthreads();
+                    }
+                    double acc[D2 * D2];
+#pragma unroll
+                    for (int q = 0; q < D2 * D2; ++q) acc[q] = 0;
+                    for (int t = D + threadIdx.x; t < ndof; t += NT) {
+#pragma unroll
+                        for (int g = 0; g < D2; ++g)
+#pragma unroll
+                            for (int h2 = 0; h2 < D2; ++h2)
+                                acc[g * D2 + h2] += c.rhs[t * D2 + g] * X[t * D2 + h2] + X[t * D2 + g] * ir1[t * D2 + h2];
+                    }
+                    block_sum<D2 * D2>(acc, sm);
+                    if (threadIdx.x < D2 * D2) Aout[threadIdx.x] = Aavg - sm.outv[threadIdx.x];
+                    __syncthreads();
                 } else {
                     // Z^T D^-1 Z over every pivot of every front
                     double acc[D2 * D2];
@@ -1128,19 +1338,26 @@ __global__ void reset_counter_kernel(unsigned int* counter) {
 
 int lds_static_bytes() { return (int)sizeof(Smem); }
 
-hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, hipStream_t stream) {
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, a.counter);
-    if (a.dim == 2) {
-        hipError_t e = hipFuncSetAttribute((const void*)rve_solve_kernel<2>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+// dynamic LDS limits are raised once per process, outside any stream capture
+hipError_t prepare_rve_solve() {
+    const void* ks[3] = {(const void*)rve_solve_kernel<2, double>, (const void*)rve_solve_kernel<2, float>,
+                         (const void*)rve_solve_kernel<3, double>};
+    for (const void* k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kLdsBytesMax - (int)sizeof(Smem));
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(rve_solve_kernel<2>, dim3(nslots), dim3(NT), dyn_bytes, stream, a);
-    } else {
-        hipError_t e = hipFuncSetAttribute((const void*)rve_solve_kernel<3>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(rve_solve_kernel<3>, dim3(nslots), dim3(NT), dyn_bytes, stream, a);
     }
+    return hipSuccess;
+}
+
+hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, bool fp32, hipStream_t stream) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, a.counter);
+    if (a.dim == 2 && fp32)
+        hipLaunchKernelGGL((rve_solve_kernel<2, float>), dim3(nslots), dim3(NT), dyn_bytes, stream, a);
+    else if (a.dim == 2)
+        hipLaunchKernelGGL((rve_solve_kernel<2, double>), dim3(nslots), dim3(NT), dyn_bytes, stream, a);
+    else
+        hipLaunchKernelGGL((rve_solve_kernel<3, double>), dim3(nslots), dim3(NT), dyn_bytes, stream, a);
     return hipGetLastError();
 }
 

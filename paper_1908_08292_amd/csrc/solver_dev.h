@@ -30,7 +30,7 @@ struct DevPlan {
 
 // offsets (in doubles) of the per-slot workspace regions
 struct SlotLayout {
-    int64_t w, wt, R, rhs, x, fe, ke, re, L, U, S, stride;
+    int64_t w, wt, R, rhs, x, fe, ke, re, L, U, S, ir1, ir2, stride;
 };
 
 struct SolveArgs {
@@ -55,8 +55,14 @@ struct SolveArgs {
     int32_t* iters;
     double rtol, atol;
     int32_t max_iter, backtrack, want_A, dim;
-    int32_t lds_front;           // doubles of the LDS front buffer (rhs rows follow it)
+    int32_t lds_front;           // elements (of the front type) of the LDS front region; rhs rows follow
     int32_t flags;               // RVE_FLAG_* of the options
+    int32_t wave_slice;          // elements of one wave's LDS slice in the wave phase
+    int32_t ir_max;              // refinement sweeps per Newton step (FP32 factors)
+    int32_t ir_max_tan;          // refinement sweeps of the tangent solves
+    int32_t pad2;
+    double ir_eta;               // stop refining when ||b - K x|| <= ir_eta ||R||
+    double ir_eta_tan;           // same for the d^2 tangent columns (Frobenius)
 };
 
 // LDS available to the front buffer (packed front + m x d^2 rhs rows)

@@ -45,6 +45,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        # torch ships its own HIP/HSA runtime; loading it first makes the
+        # library's libamdhip64 dependency resolve to that same runtime, so the
+        # process holds one HIP runtime whichever module touches the GPU first
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         L.rve_lame.argtypes = [dp, dp, C.POINTER(dp), C.POINTER(dp)]

@@ -143,3 +143,38 @@ def test_parity_config1_full_size_sampled():
     A = out["A"]
     asym = np.abs(A - np.swapaxes(A, 1, 2)).max(axis=(1, 2)) / np.abs(A).max(axis=(1, 2))
     assert asym.max() < 1e-10
+
+
+def compare_loose_iters(d, n_list, r_list, q_list, F, out, idx=None):
+    """FP32 factors + FP64 refinement: same accuracy bar, Newton counts may differ."""
+    idx = range(len(F)) if idx is None else idx
+    worst_P = worst_A = 0.0
+    for b in idx:
+        ref = run_oracle(d, int(n_list[b]), r_list[b], q_list[b], F[b])
+        assert out["status"][b] == ref["status"] == 0, (b, out["status"][b], ref["status"])
+        assert abs(int(out["iters"][b]) - ref["iters"]) <= 1, (b, out["iters"][b], ref["iters"])
+        mu_max = oracle.two_phase_lame(q_list[b])[:, 1].max()
+        eP = rel(out["P"][b], ref["P"], 1e-12 * mu_max)
+        eA = rel(out["A"][b], ref["A"], 1e-12 * mu_max)
+        worst_P, worst_A = max(worst_P, eP), max(worst_A, eA)
+        assert eP <= P_TOL, (b, eP)
+        assert eA <= A_TOL, (b, eA)
+    print(f"  FP32+IR worst P rel {worst_P:.2e}, worst A rel {worst_A:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 8, 16])
+def test_parity_fp32_ir_2d(n):
+    B = 12
+    wl = workloads.rve2d(B, n=n, seed=1500 + n)
+    print(f"case fp32+ir 2d n={n} B={B}", flush=True)
+    out = run_gpu(2, wl.n, wl.radius, wl.ratio, wl.F, opts=rve.default_opts(precision=rve.PREC_FP32_IR))
+    compare_loose_iters(2, wl.n, wl.radius, wl.ratio, wl.F, out)
+
+
+def test_parity_fp32_ir_config1_sampled():
+    wl = workloads.rve2d(4096, n=32)
+    print("case fp32+ir 2d n=32 B=4096", flush=True)
+    out = run_gpu(2, wl.n, wl.radius, wl.ratio, wl.F, opts=rve.default_opts(precision=rve.PREC_FP32_IR))
+    assert np.all(out["status"] == 0), np.bincount(out["status"])
+    idx = np.random.default_rng(2).choice(4096, 24, replace=False)
+    compare_loose_iters(2, wl.n, wl.radius, wl.ratio, wl.F, out, idx=idx)
