@@ -174,3 +174,20 @@ def random_params(seed, scale=1.0):
     th[OFF_B3:OFF_W4] = rng.uniform(-0.1, 0.1, WIDTH)
     th[OFF_W4:NPARAM] = glorot(WIDTH, 1)
     return th
+
+
+def network_derivs(theta, x):
+    """Gradient [n,3] and Hessian [n,3,3] of the raw network N at the scaled
+    inputs x [n,3] (used to scale comparison tolerances)."""
+    p = unpack(to_t(theta))
+    xt = to_t(x).clone().requires_grad_(True)
+    g = torch.autograd.grad(mlp(p, xt).sum(), xt, create_graph=True)[0]
+    H = torch.stack([torch.autograd.grad(g[:, k].sum(), xt, retain_graph=True)[0] for k in range(3)], 1)
+    return g.detach().numpy(), H.detach().numpy()
+
+
+def scaled_inputs(desc, F):
+    F = np.asarray(F, np.float64).reshape(-1, 2, 2)
+    C = np.einsum("nki,nkj->nij", F, F)
+    s = desc["c_scale"]
+    return np.stack([(C[:, 0, 0] - 1) / s[0], (C[:, 1, 1] - 1) / s[1], C[:, 0, 1] / s[2]], 1)
