@@ -62,10 +62,12 @@ typedef struct {
     float beta1, beta2, eps;
     float wP, wA, rhoP, rhoA;
     uint64_t seed;          /* mini-batch sampling (epoch-wise shuffles) */
+    int32_t precision;      /* forward products of training: RVE_SURR_BF16 or RVE_SURR_BF16X3;
+                               the reverse pass multiplies plain bf16 operands */
 } rve_train_opts;
 
-/* Fills defaults: steps 4000, batch 3840, lr 2e-3 -> 2e-5, Adam (0.9, 0.999,
- * 1e-8), wP 1, wA 0.1, rhoP 1e-3, rhoA 1e-3, seed 1. */
+/* Fills defaults: steps 40000, batch 3840, lr 2e-3 -> 2e-5, Adam (0.9, 0.999,
+ * 1e-8), wP 1, wA 0.1, rhoP 1e-3, rhoA 1e-3, seed 1, precision BF16X3. */
 void rve_train_opts_default(rve_train_opts* o);
 
 /* Creates a surrogate on the current device.  EINVAL for non-positive scales. */

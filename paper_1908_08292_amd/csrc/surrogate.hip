@@ -324,11 +324,16 @@ __global__ __launch_bounds__(NT, 1) void surr_tile_kernel(Args a) {
 
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, lr = l & 15, lg = l >> 4;
     const int64_t tile = blockIdx.x;
-    __bf16* H1 = dyn;                                    // layer-1 activations (hi)
-    __bf16* H1lo = (MODE == MODE_EVAL && PASSES == 3) ? dyn + HBUF : nullptr;
-    __bf16* H2 = (MODE == MODE_TRAIN) ? dyn + HBUF : dyn;       // layer-2 activations
-    __bf16* H2lo = H1lo;
-    __bf16* DZ = dyn + 2 * HBUF;                         // reverse-pass buffer (training)
+    // LDS: evaluation keeps one activation buffer (and its bf16 residual with
+    // PASSES = 3) and overwrites it layer by layer; training keeps H1 and H2 for
+    // the weight gradients, and a third buffer holds the residual of H1, then
+    // of H2, then the reverse pass's pre-activation adjoints
+    __bf16* H1 = dyn;
+    __bf16* H2 = (MODE == MODE_TRAIN) ? dyn + HBUF : dyn;
+    __bf16* LO = (PASSES == 3) ? (MODE == MODE_TRAIN ? dyn + 2 * HBUF : dyn + HBUF) : nullptr;
+    __bf16* H1lo = LO;
+    __bf16* H2lo = LO;
+    __bf16* DZ = dyn + 2 * HBUF;
     const float* th = a.theta;
 
     // ---- inputs
@@ -397,7 +402,7 @@ __global__ __launch_bounds__(NT, 1) void surr_tile_kernel(Args a) {
             }
             jet_fwd(z, h[rb][v]);
         }
-    if (MODE == MODE_EVAL) __syncthreads();  // H2 overwrites H1 in place
+    if (MODE == MODE_EVAL || PASSES == 3) __syncthreads();  // buffers reused in place
     store_act(h, H2, H2lo);
     __syncthreads();
 
@@ -751,6 +756,7 @@ __global__ void zero_int_kernel(int32_t* p) {
 constexpr size_t lds_bytes(int mode, int passes) {
     return (size_t)HBUF * sizeof(__bf16) * (mode == MODE_TRAIN ? 3 : (passes == 3 ? 2 : 1));
 }
+static_assert(lds_bytes(MODE_TRAIN, 3) + 8192 <= 160 * 1024, "training tile exceeds LDS");
 
 }  // namespace surr
 
@@ -800,6 +806,8 @@ int prepare() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(MODE_EVAL, 3)));
     SHIP(hipFuncSetAttribute((const void*)surr_tile_kernel<MODE_TRAIN, 1>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(MODE_TRAIN, 1)));
+    SHIP(hipFuncSetAttribute((const void*)surr_tile_kernel<MODE_TRAIN, 3>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(MODE_TRAIN, 3)));
     g_prepared = true;
     return RVE_OK;
 }
@@ -888,7 +896,8 @@ int ensure_train_scratch(rve_surrogate h, int64_t tiles, int64_t nidx, int64_t n
 int check_train_opts(const rve_train_opts& o) {
     if (o.steps < 0 || o.batch < 1 || !(o.lr > 0) || !(o.lr_final > 0) || !(o.beta1 >= 0 && o.beta1 < 1) ||
         !(o.beta2 >= 0 && o.beta2 < 1) || !(o.eps > 0) || !(o.wP >= 0) || !(o.wA >= 0) || !(o.rhoP >= 0) ||
-        !(o.rhoA >= 0) || (o.wP == 0 && o.wA == 0))
+        !(o.rhoA >= 0) || (o.wP == 0 && o.wA == 0) ||
+        (o.precision != RVE_SURR_BF16 && o.precision != RVE_SURR_BF16X3))
         return fail(RVE_EINVAL, "rve_train_opts out of range");
     return RVE_OK;
 }
@@ -899,7 +908,7 @@ extern "C" {
 
 void rve_train_opts_default(rve_train_opts* o) {
     if (!o) return;
-    o->steps = 4000;
+    o->steps = 40000;
     o->batch = 3840;
     o->lr = 2e-3f;
     o->lr_final = 2e-5f;
@@ -911,6 +920,7 @@ void rve_train_opts_default(rve_train_opts* o) {
     o->rhoP = 1e-3f;
     o->rhoA = 1e-3f;
     o->seed = 1;
+    o->precision = RVE_SURR_BF16X3;
 }
 
 int rve_surrogate_create(const rve_surrogate_desc* d, rve_surrogate* out) {
@@ -1057,7 +1067,12 @@ static int run_grad(rve_surrogate h, const double* F, const double* P, const dou
     a.wA = o.wA;
     a.rhoP = o.rhoP;
     a.rhoA = o.rhoA;
-    hipLaunchKernelGGL((surr_tile_kernel<MODE_TRAIN, 1>), dim3((unsigned)tiles), dim3(NT), lds_bytes(MODE_TRAIN, 1), st, a);
+    if (o.precision == RVE_SURR_BF16X3)
+        hipLaunchKernelGGL((surr_tile_kernel<MODE_TRAIN, 3>), dim3((unsigned)tiles), dim3(NT), lds_bytes(MODE_TRAIN, 3),
+                           st, a);
+    else
+        hipLaunchKernelGGL((surr_tile_kernel<MODE_TRAIN, 1>), dim3((unsigned)tiles), dim3(NT), lds_bytes(MODE_TRAIN, 1),
+                           st, a);
     SHIP(hipGetLastError());
     return RVE_OK;
 }

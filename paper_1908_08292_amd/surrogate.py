@@ -17,7 +17,8 @@ class SurrogateDesc(C.Structure):
 class TrainOpts(C.Structure):
     _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("lr_final", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("wP", C.c_float),
-                ("wA", C.c_float), ("rhoP", C.c_float), ("rhoA", C.c_float), ("seed", C.c_uint64)]
+                ("wA", C.c_float), ("rhoP", C.c_float), ("rhoA", C.c_float), ("seed", C.c_uint64),
+                ("precision", C.c_int32)]
 
 
 _done = False

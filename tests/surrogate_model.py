@@ -87,10 +87,28 @@ def assemble(F, G, Hc):
     return P, A
 
 
-def loss_grad(theta, desc, F, Pt, At, wP=1.0, wA=0.1, rhoP=1e-3, rhoA=1e-3, round_bf16=False):
-    """Mean loss and gradient as the kernels compute them (one tile holding all
-    points plus the origin)."""
-    r = bf16 if round_bf16 else (lambda a: a)
+def loss_grad(theta, desc, F, Pt, At, wP=1.0, wA=0.1, rhoP=1e-3, rhoA=1e-3, round_bf16=False, round_fwd=None,
+              tile=15):
+    """Mean loss and gradient as the kernels compute them: tiles of `tile`
+    points, each with its own copy of the origin (whose adjoint cancels the
+    tile's first-order terms, so where the rounding happens matters).
+    round_bf16 rounds the reverse pass's MFMA operands; round_fwd (default:
+    round_bf16) those of the forward pass (off for the split hi/lo products)."""
+    F = np.asarray(F, np.float64).reshape(-1, 4)
+    n = len(F)
+    step = tile if tile else n
+    L, g = 0.0, np.zeros(OS.NPARAM)
+    for a in range(0, n, step):
+        b = min(n, a + step)
+        La, ga = _tile(theta, desc, F[a:b], Pt[a:b], At[a:b], wP, wA, rhoP, rhoA, round_bf16, round_fwd)
+        L += La
+        g += ga
+    return L / n, g / n
+
+
+def _tile(theta, desc, F, Pt, At, wP, wA, rhoP, rhoA, round_bf16, round_fwd):
+    rb = bf16 if round_bf16 else (lambda a: a)
+    r = bf16 if (round_bf16 if round_fwd is None else round_fwd) else (lambda a: a)
     p = OS.unpack(np.asarray(theta, np.float64))
     W1, b1, W2, b2, W3, b3, w4 = [np.asarray(p[k]) for k in ["W1", "b1", "W2", "b2", "W3", "b3", "w4"]]
     M = np.asarray(desc["M"]).reshape(9)
@@ -158,15 +176,15 @@ def loss_grad(theta, desc, F, Pt, At, wP=1.0, wA=0.1, rhoP=1e-3, rhoA=1e-3, roun
     g[OS.OFF_W4:] = np.einsum("qrp,qp->r", H3[1:], dY)
     dZ3 = jet_bwd(Z3, dH3)
     g[OS.OFF_B3:OS.OFF_W4] = dZ3[0].sum(1)
-    g[OS.OFF_W3:OS.OFF_B3] = np.einsum("qrp,qnp->rn", r(dZ3), r(H2)).reshape(-1)
-    dZ2 = jet_bwd(Z2, np.einsum("rn,qrp->qnp", r(W3), r(dZ3)))
+    g[OS.OFF_W3:OS.OFF_B3] = np.einsum("qrp,qnp->rn", rb(dZ3), rb(H2)).reshape(-1)
+    dZ2 = jet_bwd(Z2, np.einsum("rn,qrp->qnp", rb(W3), rb(dZ3)))
     g[OS.OFF_B2:OS.OFF_W3] = dZ2[0].sum(1)
-    g[OS.OFF_W2:OS.OFF_B2] = np.einsum("qrp,qnp->rn", r(dZ2), r(H1)).reshape(-1)
-    dZ1 = jet_bwd(Z1, np.einsum("rn,qrp->qnp", r(W2), r(dZ2)))
+    g[OS.OFF_W2:OS.OFF_B2] = np.einsum("qrp,qnp->rn", rb(dZ2), rb(H1)).reshape(-1)
+    dZ1 = jet_bwd(Z1, np.einsum("rn,qrp->qnp", rb(W2), rb(dZ2)))
     gW1 = np.einsum("rp,pk->rk", dZ1[0], Xa) + np.stack([dZ1[1 + k].sum(1) for k in range(3)], 1)
     g[OS.OFF_W1:OS.OFF_B1] = gW1.reshape(-1)
     g[OS.OFF_B1:OS.OFF_W2] = dZ1[0].sum(1)
-    return L / n, g / n
+    return L, g
 
 
 BLOCKS = [("W1", OS.OFF_W1, OS.OFF_B1), ("b1", OS.OFF_B1, OS.OFF_W2), ("W2", OS.OFF_W2, OS.OFF_B2),

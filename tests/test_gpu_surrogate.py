@@ -85,7 +85,8 @@ def test_eval_matches_oracle(precision, rtol):
     sg.destroy()
 
 
-def test_loss_gradient_matches_oracle():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_loss_gradient_matches_oracle(precision):
     torch = torch_cuda()
     from paper_1908_08292_amd import surrogate as S
     A0 = _A0()
@@ -107,7 +108,7 @@ def test_loss_gradient_matches_oracle():
     sg = S.Surrogate(A0, w_scale=0.1)
     sg.set_params(th)
     L, g = sg.loss_grad(torch.tensor(F, device="cuda"), torch.tensor(Pt, device="cuda"),
-                        torch.tensor(At, device="cuda"))
+                        torch.tensor(At, device="cuda"), S.train_opts(precision=precision))
     g = g.cpu().numpy().astype(np.float64)
     print(f"loss gpu {L:.6e} oracle {L_ref:.6e}")
     assert abs(L - L_ref) <= 3e-2 * L_ref
@@ -122,14 +123,16 @@ def test_loss_gradient_matches_oracle():
         assert e <= 2e-2, (name, e)
     cos = g @ g_ref / np.linalg.norm(g) / np.linalg.norm(g_ref)
     assert cos > 0.999, cos
-    # the same algorithm modelled in numpy with bf16 rounding at the kernel's
-    # rounding points: what remains is FP32 accumulation order (and the rare
-    # bf16 rounding it flips)
-    Lm, gm = SM.loss_grad(th, desc, F, Pt, At, round_bf16=True)
+    # the same algorithm modelled in numpy, tile by tile, with bf16 rounding at
+    # the kernel's rounding points.  Plain bf16: what remains is FP32
+    # accumulation order (and the rare bf16 rounding it flips), measured
+    # <= 1e-4.  Split forward: the model's forward is exact, the kernel's keeps
+    # ~2^-16 per product, amplified by the origin's cancellation (~2e-3).
+    Lm, gm = SM.loss_grad(th, desc, F, Pt, At, round_bf16=True, round_fwd=(precision == 0))
     errm = {name: np.linalg.norm(g[a:b] - gm[a:b]) / np.linalg.norm(gm[a:b]) for name, a, b in SM.BLOCKS}
     print("gradient rel err vs bf16 model:", {k: f"{v:.2e}" for k, v in errm.items()})
     for name, e in errm.items():
-        assert e <= 3e-3, (name, e)
+        assert e <= (5e-4 if precision == 0 else 6e-3), (name, e)
     sg.destroy()
 
 
