@@ -73,6 +73,8 @@ typedef struct {
     double res_hist[FEHMM_MAX_HIST];     /* ||R_H|| / ||R_H^(0)|| per macro iteration (macro_iters + 1 entries) */
     double u_max;                        /* largest nodal |u| after the step */
     int32_t failed_rves;
+    int64_t surrogate_points;            /* quadrature-point evaluations answered by the surrogate */
+    int64_t fallback_points;             /* evaluations sent to the RVE solve by the indicator */
 } fehmm_step_info;
 
 /* Builds the macro mesh, uploads it, and creates the RVE batch (one RVE per
@@ -88,6 +90,18 @@ int fehmm_macro_step(fehmm h, int32_t step, fehmm_step_info* info);
 int fehmm_get_nodes(fehmm h, double* xy);
 int fehmm_get_u(fehmm h, double* u);
 int fehmm_get_qp(fehmm h, double* F, double* P, double* A);
+/* Replaces micro solves by a trained surrogate (surrogate.h) wherever its
+ * error indicator is <= threshold; the other quadrature points fall back to
+ * the RVE solve (rve_solve_batch_subset).  The fallback set of a load step
+ * only grows: every macro iteration evaluates the indicator at the current
+ * state and adds the points that fail it, and the step counts as converged
+ * only in an iteration that added none, with ||R_H|| <= max(rtol_macro,
+ * macro_rtol) ||R_H^(0)|| (the surrogate's stresses carry FP32 rounding of
+ * order 1e-5 of a load increment, so rtol_macro = 1e-10 is out of reach).
+ * precision: RVE_SURR_BF16 or RVE_SURR_BF16X3.  s = NULL switches the
+ * surrogate off.  The surrogate must outlive its use by the driver.  Only the
+ * nested scheme uses it (alternating: EUNSUPPORTED). */
+int fehmm_set_surrogate(fehmm h, struct rve_surrogate_s* s, float threshold, int32_t precision, double macro_rtol);
 /* Checkpoint / resume: u [ndof] in host memory, the micro fluctuations
  * [state_doubles] in host memory.  set_state restores both. */
 int fehmm_get_state(fehmm h, double* u_host, double* w_host);

@@ -141,6 +141,16 @@ void rve_opts_default(rve_opts* o);
 int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
                     int32_t* iters, const rve_opts* opts, void* hip_stream);
 
+/* As rve_solve_batch, restricted to the RVEs listed in idx[0 .. *count) (both
+ * device pointers; the count is read on the device when the kernel runs, so a
+ * list produced by an earlier kernel on the same stream needs no host round
+ * trip).  Entries outside [0, B) are skipped; RVEs not listed keep their P, A,
+ * w_state, status and iters untouched.  This is the fallback path of the
+ * surrogate (surrogate.h: rve_surrogate_select).  Asynchronous. */
+int rve_solve_batch_subset(rve_batch b, const int32_t* idx, const int32_t* count, const double* F, double* P,
+                           double* A, double* w_state, int32_t* status, int32_t* iters, const rve_opts* opts,
+                           void* hip_stream);
+
 /* As rve_solve_batch, then synchronizes the stream and returns RVE_EPARTIAL if
  * any RVE failed (status must then be non-NULL). */
 int rve_solve_batch_sync(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,

@@ -46,3 +46,55 @@ class Solver:
         if self.A is not None:
             out["A"] = self.A.cpu().numpy().reshape(B, d * d, d * d)
         return out
+
+
+def small_strain_tangent(n, radius, ratio):
+    """Homogenized tangent at F = I of one 2D RVE, from the GPU solver ([4,4])."""
+    b, _ = build_batch(2, np.array([n]), np.array([radius]), np.array([ratio]))
+    s = Solver(b, keep_state=False)
+    s.set_F(np.eye(2).reshape(1, 4))
+    s.solve()
+    out = s.results()
+    if out["status"][0] != 0:
+        raise RuntimeError("RVE solve at F = I failed")
+    return out["A"][0]
+
+
+def fit_surrogate(n=16, radius=0.25, ratio=10.0, n_train=200000, n_calib=20000, h=0.2, seed=1004,
+                  train_opts=None, precision=1, w_scale=0.1, timings=None):
+    """A trained and calibrated surrogate of one 2D RVE (surrogate.h), from
+    (F, P, A) triples that the batched RVE solver generates: F = I + H with H_ij
+    iid U[-h, h] (det F >= 0.5), n_train for Adam and n_calib more, judged by the
+    same solver, for the error indicator.  Returns the Surrogate."""
+    import time
+
+    import torch
+
+    from . import surrogate, workloads
+    t0 = time.perf_counter()
+    F = workloads.draw_F(np.random.default_rng(seed), n_train + n_calib, 2, h).reshape(-1, 4)
+    batch, _ = build_batch(2, np.full(len(F), n), np.full(len(F), radius), np.full(len(F), ratio))
+    sol = Solver(batch, keep_state=False)
+    sol.set_F(F)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sol.solve()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ok = sol.status == 0
+    ok_tr, ok_cal = ok.clone(), ok.clone()
+    ok_tr[n_train:] = False
+    ok_cal[:n_train] = False
+    Fv, Pv, Av = sol.F.view(-1, 4), sol.P.view(-1, 4), sol.A.view(-1, 16)
+    sg = surrogate.Surrogate(small_strain_tangent(n, radius, ratio), w_scale=w_scale, seed=seed)
+    opts = train_opts if train_opts is not None else surrogate.train_opts()
+    loss = sg.train(Fv[ok_tr].contiguous(), Pv[ok_tr].contiguous(), Av[ok_tr].contiguous(), opts)
+    t3 = time.perf_counter()
+    sg.calibrate(Fv[ok_cal].contiguous(), Pv[ok_cal].contiguous(), precision=precision)
+    t4 = time.perf_counter()
+    if timings is not None:
+        timings.update(setup_s=t1 - t0, data_s=t2 - t1, data_solves=len(F), failed_solves=int((~ok).sum().item()),
+                       train_s=t3 - t2, train_steps=int(opts.steps), train_batch=int(opts.batch),
+                       final_loss=float(np.mean(loss[-min(50, len(loss)):])) if len(loss) else None,
+                       calibrate_s=t4 - t3)
+    return sg

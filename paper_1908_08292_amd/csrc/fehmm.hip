@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/fehmm.h"
+#include "../../include/surrogate.h"
 
 int rve_internal_set_error(int code, const std::string& msg);  // rve_abi.cpp
 static inline int set_error(int code, const std::string& msg) { return rve_internal_set_error(code, msg); }
@@ -66,6 +67,28 @@ __global__ void macro_element(int nelem, const double* __restrict__ P, const dou
 
 __global__ void macro_zero_int(int* __restrict__ x, int n) {
     if ((int)threadIdx.x < n) x[threadIdx.x] = 0;
+}
+
+// fallback set of a load step: a point joins when its indicator exceeds the
+// threshold (or is NaN) and stays; flag reports a new member; ind is
+// rewritten as +inf for members and 0 otherwise, for the compaction
+__global__ void macro_merge_fallback(float* __restrict__ ind, int* __restrict__ mask, float thr, int n,
+                                     int* __restrict__ flag) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const float v = ind[q];
+    int m = mask[q];
+    if (!m && !(v <= thr)) {
+        m = 1;
+        mask[q] = 1;
+        flag[1] = 1;
+    }
+    ind[q] = m ? INFINITY : 0.0f;
+}
+
+__global__ void macro_zero_ints(int* __restrict__ x, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = 0;
 }
 
 __global__ void macro_zero(double* __restrict__ x, int64_t n) {
@@ -210,6 +233,13 @@ struct fehmm_s {
     int *d_status = nullptr, *d_iters = nullptr, *d_flag = nullptr;
     double *d_u = nullptr, *d_du = nullptr, *d_uval = nullptr, *d_F = nullptr, *d_P = nullptr, *d_A = nullptr;
     double *d_w = nullptr, *d_ke = nullptr, *d_fe = nullptr, *d_K = nullptr, *d_R = nullptr, *d_norm = nullptr;
+    // surrogate replacement of micro solves
+    rve_surrogate surr = nullptr;
+    float surr_thr = 0.f;
+    int surr_prec = RVE_SURR_BF16X3;
+    double surr_rtol = 1e-4;
+    float* d_ind = nullptr;
+    int32_t *d_sidx = nullptr, *d_scnt = nullptr, *d_smask = nullptr;
     bool alive = true;
 };
 
@@ -226,6 +256,10 @@ static void fehmm_free(fehmm_s* h) {
     double* dp[] = {h->d_u, h->d_du, h->d_uval, h->d_F, h->d_P, h->d_A, h->d_w, h->d_ke, h->d_fe, h->d_K,
                     h->d_R, h->d_norm};
     for (double* p : dp) (void)hipFree(p);
+    (void)hipFree(h->d_ind);
+    (void)hipFree(h->d_sidx);
+    (void)hipFree(h->d_scnt);
+    (void)hipFree(h->d_smask);
     if (h->batch) rve_batch_destroy(h->batch);
     if (h->stream) (void)hipStreamDestroy(h->stream);
     h->batch = nullptr;
@@ -345,7 +379,7 @@ int fehmm_create(const fehmm_desc* d, fehmm* out) {
     }
     hipError_t e1 = hipMalloc((void**)&H->d_status, sizeof(int) * H->nqp);
     hipError_t e2 = hipMalloc((void**)&H->d_iters, sizeof(int) * H->nqp);
-    hipError_t e3 = hipMalloc((void**)&H->d_flag, sizeof(int));
+    hipError_t e3 = hipMalloc((void**)&H->d_flag, 2 * sizeof(int));  // [0] band solve, [1] new fallbacks
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         fehmm_free(H);
         return set_error(RVE_ENOMEM, "fehmm_create: allocation failed");
@@ -385,6 +419,11 @@ int fehmm_macro_step(fehmm h, int32_t step, fehmm_step_info* info) {
     FH_HIP(hipMemcpyAsync(h->d_uval, uval.data(), sizeof(double) * h->ndof, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(macro_dirichlet, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_u, h->d_fixed, h->d_uval,
                        h->ndof);
+    if (h->surr) {
+        // a new load step starts with an empty fallback set
+        hipLaunchKernelGGL(macro_zero_ints, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_smask, (int64_t)h->nqp);
+        hipLaunchKernelGGL(macro_zero_int, dim3(1), dim3(64), 0, s, h->d_flag + 1, 1);
+    }
     rve_opts mo = d.micro_opts;
     const bool alt = d.scheme == FEHMM_ALTERNATING;
     if (alt) {
@@ -398,8 +437,26 @@ int fehmm_macro_step(fehmm h, int32_t step, fehmm_step_info* info) {
     for (;;) {
         hipLaunchKernelGGL(macro_gather_F, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_conn, h->nelem, h->d_u,
                            h->geom, h->d_F);
-        int st = rve_solve_batch(h->batch, h->d_F, h->d_P, h->d_A, h->d_w, h->d_status, h->d_iters, &mo, s);
-        if (st) return st;
+        if (h->surr) {
+            // surrogate answers where its indicator allows; the rest fall back to
+            // the RVE solve, listed on the device (no host round trip)
+            int st = rve_surrogate_eval(h->surr, h->d_F, h->d_P, h->d_A, h->d_ind, h->nqp, h->surr_prec, s);
+            if (st) return st;
+            hipLaunchKernelGGL(macro_merge_fallback, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_ind, h->d_smask,
+                               h->surr_thr, h->nqp, h->d_flag);
+            st = rve_surrogate_select(h->d_ind, h->nqp, 0.5f, h->d_sidx, h->d_scnt, s);
+            if (st) return st;
+            hipLaunchKernelGGL(macro_zero_ints, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_status,
+                               (int64_t)h->nqp);
+            hipLaunchKernelGGL(macro_zero_ints, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_iters,
+                               (int64_t)h->nqp);
+            st = rve_solve_batch_subset(h->batch, h->d_sidx, h->d_scnt, h->d_F, h->d_P, h->d_A, h->d_w, h->d_status,
+                                        h->d_iters, &mo, s);
+            if (st) return st;
+        } else {
+            int st = rve_solve_batch(h->batch, h->d_F, h->d_P, h->d_A, h->d_w, h->d_status, h->d_iters, &mo, s);
+            if (st) return st;
+        }
         hipLaunchKernelGGL(macro_element, dim3(nblk(8 * (int64_t)h->nelem, 256)), dim3(256), 0, s, h->nelem,
                            h->d_P, h->d_A, h->geom, h->d_ke, h->d_fe);
         const int64_t nK = (int64_t)h->ndof * (h->bw + 1);
@@ -418,7 +475,17 @@ int fehmm_macro_step(fehmm h, int32_t step, fehmm_step_info* info) {
         double hn[2];
         FH_HIP(hipMemcpyAsync(hn, h->d_norm, sizeof(hn), hipMemcpyDeviceToHost, s));
         FH_HIP(hipMemcpyAsync(hiters.data(), h->d_iters, sizeof(int) * h->nqp, hipMemcpyDeviceToHost, s));
+        int32_t nfall = 0, grew[2] = {0, 0};
+        if (h->surr) {
+            FH_HIP(hipMemcpyAsync(&nfall, h->d_scnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            FH_HIP(hipMemcpyAsync(grew, h->d_flag, sizeof(grew), hipMemcpyDeviceToHost, s));
+        }
         FH_HIP(hipStreamSynchronize(s));
+        if (h->surr) {
+            I->fallback_points += nfall;
+            I->surrogate_points += h->nqp - nfall;
+            hipLaunchKernelGGL(macro_zero_int, dim3(1), dim3(64), 0, s, h->d_flag + 1, 1);
+        }
         for (int q = 0; q < h->nqp; ++q) micro += hiters[q];
         if (hn[1] > 0) {
             I->status = FEHMM_STEP_RVE_FAILED;
@@ -428,7 +495,11 @@ int fehmm_macro_step(fehmm h, int32_t step, fehmm_step_info* info) {
         const double rn = std::sqrt(hn[0]);
         if (r0 < 0) r0 = rn;
         I->res_hist[it] = r0 > 0 ? rn / r0 : 0.0;
-        if (rn <= d.rtol_macro * r0 || rn == 0.0) break;
+        // with the surrogate the stresses carry its FP32 rounding, so the macro
+        // Newton stops at surr_rtol, and only in an iteration whose indicator
+        // check (at the current state) added no fallback point
+        const double rtol = h->surr ? std::max(d.rtol_macro, h->surr_rtol) : d.rtol_macro;
+        if ((rn <= rtol * r0 || rn == 0.0) && !grew[1]) break;
         if (it == d.max_macro_iter) {
             I->status = FEHMM_STEP_NOCONV;
             break;
@@ -452,6 +523,31 @@ int fehmm_macro_step(fehmm h, int32_t step, fehmm_step_info* info) {
     I->u_max = um;
     if (flag && I->status == FEHMM_STEP_CONVERGED) I->status = FEHMM_STEP_NOCONV;
     return I->status == FEHMM_STEP_CONVERGED ? RVE_OK : RVE_EPARTIAL;
+}
+
+int fehmm_set_surrogate(fehmm h, rve_surrogate sg, float threshold, int32_t precision, double macro_rtol) {
+    if (!h || !h->alive) return set_error(RVE_EINVAL, "fehmm_set_surrogate: invalid handle");
+    if (!sg) {
+        h->surr = nullptr;
+        return RVE_OK;
+    }
+    if (h->desc.scheme != FEHMM_NESTED)
+        return set_error(RVE_EUNSUPPORTED, "fehmm_set_surrogate: only the nested scheme uses the surrogate");
+    if (precision != RVE_SURR_BF16 && precision != RVE_SURR_BF16X3)
+        return set_error(RVE_EINVAL, "fehmm_set_surrogate: unknown precision");
+    if (!(threshold >= 0)) return set_error(RVE_EINVAL, "fehmm_set_surrogate: threshold must be >= 0");
+    if (!(macro_rtol > 0 && macro_rtol < 1)) return set_error(RVE_EINVAL, "fehmm_set_surrogate: macro_rtol out of (0, 1)");
+    if (!h->d_ind) {
+        FH_HIP(hipMalloc((void**)&h->d_ind, sizeof(float) * h->nqp));
+        FH_HIP(hipMalloc((void**)&h->d_sidx, sizeof(int32_t) * h->nqp));
+        FH_HIP(hipMalloc((void**)&h->d_scnt, sizeof(int32_t)));
+        FH_HIP(hipMalloc((void**)&h->d_smask, sizeof(int32_t) * h->nqp));
+    }
+    h->surr_rtol = macro_rtol;
+    h->surr = sg;
+    h->surr_thr = threshold;
+    h->surr_prec = precision;
+    return RVE_OK;
 }
 
 int fehmm_get_nodes(fehmm h, double* xy) {

@@ -436,8 +436,9 @@ int rve_batch_state_offsets(rve_batch b, int64_t* host_off) {
     return RVE_OK;
 }
 
-int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
-                    int32_t* iters, const rve_opts* opts, void* hip_stream) {
+static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* subset_count, const double* F,
+                            double* P, double* A, double* w_state, int32_t* status, int32_t* iters,
+                            const rve_opts* opts, void* hip_stream) {
     if (!b || !b->alive) return fail(RVE_EINVAL, "rve_solve_batch: invalid batch handle");
     if (!F || !P) return fail(RVE_EINVAL, "rve_solve_batch: F and P are required");
     rve_opts o;
@@ -464,7 +465,8 @@ int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* 
     a.lame_pool = b->d_lame_pool;
     a.state_off = b->d_state_off;
     a.rve_atol = b->d_atol;
-    a.order = b->d_order;
+    a.order = subset ? subset : b->d_order;
+    a.count_dev = subset ? subset_count : nullptr;
     a.B = b->B;
     a.ws = b->d_ws;
     a.lay = b->lay;
@@ -495,6 +497,18 @@ int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* 
     hipError_t e = launch_rve_solve(a, b->nslots, b->dyn_bytes[k], fp32, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(RVE_EHIP, std::string("rve_solve_batch launch: ") + hipGetErrorString(e));
     return RVE_OK;
+}
+
+int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
+                    int32_t* iters, const rve_opts* opts, void* hip_stream) {
+    return solve_batch_impl(b, nullptr, nullptr, F, P, A, w_state, status, iters, opts, hip_stream);
+}
+
+int rve_solve_batch_subset(rve_batch b, const int32_t* idx, const int32_t* count, const double* F, double* P,
+                           double* A, double* w_state, int32_t* status, int32_t* iters, const rve_opts* opts,
+                           void* hip_stream) {
+    if (!idx || !count) return fail(RVE_EINVAL, "rve_solve_batch_subset: idx and count are required");
+    return solve_batch_impl(b, idx, count, F, P, A, w_state, status, iters, opts, hip_stream);
 }
 
 int rve_solve_batch_sync(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,

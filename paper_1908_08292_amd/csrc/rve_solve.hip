@@ -1104,8 +1104,21 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
     double* base = a.ws + slot * a.lay.stride;
     for (;;) {
         if (threadIdx.x == 0) {
-            unsigned int idx = atomicAdd(a.counter, 1u);
-            sm.rve = (idx < (unsigned int)a.B) ? a.order[idx] : -1;
+            // queue length: the whole batch, or a device-side count of a subset
+            // list (entries outside [0, B) are skipped)
+            const unsigned int nq =
+                a.count_dev ? (unsigned int)min((int64_t)max(*a.count_dev, 0), a.B) : (unsigned int)a.B;
+            int r = -1;
+            for (;;) {
+                const unsigned int idx = atomicAdd(a.counter, 1u);
+                if (idx >= nq) break;
+                const int cand = a.order[idx];
+                if (cand >= 0 && (int64_t)cand < a.B) {
+                    r = cand;
+                    break;
+                }
+            }
+            sm.rve = r;
         }
         __syncthreads();
         const int rve = sm.rve;

@@ -42,7 +42,8 @@ struct SolveArgs {
     const double* lame_pool;
     const int64_t* state_off;    // [B+1]
     const double* rve_atol;      // [B] default absolute tolerance
-    const int32_t* order;        // [B] queue order (longest first)
+    const int32_t* order;        // [B] queue order (longest first), or a subset list
+    const int32_t* count_dev;    // length of a subset list (device), or null for the whole batch
     int64_t B;
     double* ws;
     SlotLayout lay;

@@ -23,7 +23,8 @@ class Desc(C.Structure):
 
 class StepInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("macro_iters", C.c_int32), ("micro_iters", C.c_int64),
-                ("res_hist", C.c_double * MAX_HIST), ("u_max", C.c_double), ("failed_rves", C.c_int32)]
+                ("res_hist", C.c_double * MAX_HIST), ("u_max", C.c_double), ("failed_rves", C.c_int32),
+                ("surrogate_points", C.c_int64), ("fallback_points", C.c_int64)]
 
 
 _setup_done = False
@@ -43,6 +44,7 @@ def lib():
         L.fehmm_get_qp.argtypes = [vp, vp, vp, vp]
         L.fehmm_get_state.argtypes = [vp, vp, vp]
         L.fehmm_set_state.argtypes = [vp, vp, vp]
+        L.fehmm_set_surrogate.argtypes = [vp, vp, C.c_float, C.c_int32, C.c_double]
         _setup_done = True
     return L
 
@@ -74,7 +76,16 @@ class Driver:
         rve.check(code, "fehmm_macro_step")
         return dict(code=code, status=info.status, macro_iters=info.macro_iters, micro_iters=info.micro_iters,
                     res_hist=np.array(info.res_hist[: info.macro_iters + 1]), u_max=info.u_max,
-                    failed_rves=info.failed_rves)
+                    failed_rves=info.failed_rves, surrogate_points=info.surrogate_points,
+                    fallback_points=info.fallback_points)
+
+    def set_surrogate(self, surrogate, threshold=1e-3, precision=1, macro_rtol=1e-4):
+        """Use a trained surrogate (paper_1908_08292_amd.surrogate.Surrogate) where its
+        indicator is <= threshold; None switches it off."""
+        self._surrogate = surrogate
+        rve.check(lib().fehmm_set_surrogate(self.h, surrogate.h if surrogate is not None else None,
+                                            float(threshold), int(precision), float(macro_rtol)),
+                  "fehmm_set_surrogate")
 
     def u(self):
         out = np.zeros(self.ndof)

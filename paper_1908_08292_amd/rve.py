@@ -62,6 +62,7 @@ def lib():
         L.rve_opts_default.restype = None
         L.rve_solve_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(Opts), vp]
         L.rve_solve_batch_sync.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(Opts), vp]
+        L.rve_solve_batch_subset.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Opts), vp]
         L.rve_plan_info.argtypes = [i32, i32, C.POINTER(dp), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]
         L.rve_plan_export.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.rve_strerror.argtypes = [C.c_int]
@@ -212,6 +213,26 @@ class Batch:
         fn = lib().rve_solve_batch_sync if sync else lib().rve_solve_batch
         return check(fn(self.h, _ptr(F), _ptr(P), _ptr(A), _ptr(w_state), _ptr(status), _ptr(iters),
                         C.byref(o), s), "rve_solve_batch")
+
+    def solve_subset(self, idx, count, F, P, A=None, w_state=None, status=None, iters=None, opts=None, stream=None):
+        """Solves only the RVEs idx[0 .. count[0]) (device int32 tensors)."""
+        import torch
+        d2 = self.d * self.d
+        self._check(idx, idx.numel(), torch.int32, "idx")
+        self._check(count, 1, torch.int32, "count")
+        if idx.numel() > self.B:
+            raise ValueError("idx: more entries than RVEs")
+        self._check(F, self.B * d2, torch.float64, "F")
+        self._check(P, self.B * d2, torch.float64, "P")
+        self._check(A, self.B * d2 * d2, torch.float64, "A")
+        self._check(w_state, int(self.state_offsets[-1]), torch.float64, "w_state")
+        self._check(status, self.B, torch.int32, "status")
+        self._check(iters, self.B, torch.int32, "iters")
+        o = opts if opts is not None else default_opts()
+        s = C.c_void_p(stream) if stream is not None else None
+        return check(lib().rve_solve_batch_subset(self.h, _ptr(idx), _ptr(count), _ptr(F), _ptr(P), _ptr(A),
+                                                  _ptr(w_state), _ptr(status), _ptr(iters), C.byref(o), s),
+                     "rve_solve_batch_subset")
 
     def destroy(self):
         if self.h is not None:

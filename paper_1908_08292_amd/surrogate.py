@@ -1,9 +1,13 @@
 """ctypes binding of the surrogate C ABI (include/surrogate.h); argument marshalling only."""
 import ctypes as C
+import os
+import re
 
 import numpy as np
 
 from . import rve
+
+HEADER = os.path.join(os.path.dirname(rve.HERE), "include", "surrogate.h")
 
 NPARAM = 33664
 BF16, BF16X3 = 0, 1
@@ -43,6 +47,11 @@ def lib():
         L.rve_surrogate_select.argtypes = [vp, i64, fp, vp, vp, vp]
         _done = True
     return L
+
+
+def declared_functions():
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void)\s+(rve_\w+)\s*\(", txt, flags=re.M)))
 
 
 def train_opts(**kw):

@@ -151,7 +151,33 @@ def test_plan_drives_a_correct_multifrontal_solve(d, n):
 def test_fehmm_symbols_exported():
     from paper_1908_08292_amd import fehmm
     names = fehmm.declared_functions()
-    assert "fehmm_macro_step" in names and len(names) == 9
+    assert "fehmm_macro_step" in names and "fehmm_set_surrogate" in names and len(names) == 10
     L = fehmm.lib()
     for nm in names:
         assert hasattr(L, nm), nm
+
+
+def test_surrogate_symbols_and_validation():
+    from paper_1908_08292_amd import surrogate as S
+    names = S.declared_functions()
+    assert "rve_surrogate_train" in names and "rve_surrogate_eval" in names and len(names) == 11
+    L = S.lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert "rve_solve_batch_subset" in rve.declared_functions()
+    o = S.train_opts()
+    assert o.steps == 40000 and o.batch == 3840 and o.precision == S.BF16X3
+    assert abs(o.lr - 2e-3) < 1e-9 and abs(o.beta2 - 0.999) < 1e-7
+    # argument checks run before any device call
+    with pytest.raises(rve.RveError) as e:
+        S.Surrogate(np.eye(4), c_scale=(0.5, -1.0, 0.5))
+    assert e.value.code == rve.RVE_EINVAL
+    with pytest.raises(rve.RveError) as e:
+        S.Surrogate(np.eye(4), w_scale=0.0)
+    assert e.value.code == rve.RVE_EINVAL
+    bad = np.eye(4)
+    bad[0, 0] = np.nan
+    with pytest.raises(rve.RveError):
+        S.Surrogate(bad)
+    assert L.rve_surrogate_select(None, 10, 1e-3, None, None, None) == rve.RVE_EINVAL
+    assert L.rve_surrogate_eval(None, None, None, None, None, 0, 1, None) == rve.RVE_EINVAL

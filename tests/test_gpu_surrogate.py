@@ -223,3 +223,112 @@ def test_training_reduces_stress_error_against_rve_judge():
     assert np.all(np.isfinite(loss)) and loss[-1] < 0.1 * loss[0]
     assert np.median(e_net) < 0.25 * np.median(e_base)
     sg.destroy()
+
+
+def test_subset_solve_matches_full_solve():
+    torch = torch_cuda()
+    from paper_1908_08292_amd import api, workloads
+    B = 300
+    F = workloads.draw_F(np.random.default_rng(9), B, 2, 0.15).reshape(-1, 4)
+    batch, meshes = api.build_batch(2, np.full(B, 8), np.full(B, 0.25), np.full(B, 10.0))
+    full = api.Solver(batch)
+    full.set_F(F)
+    full.solve()
+    sub = api.Solver(batch)
+    sub.set_F(F)
+    sub.P.fill_(np.nan)
+    sub.status.fill_(-7)
+    pick = np.array([5, 17, 299, 0, 123, -1, 400, 42], np.int32)  # two entries out of range: skipped
+    idx = torch.tensor(pick, device="cuda")
+    cnt = torch.tensor([len(pick)], dtype=torch.int32, device="cuda")
+    batch.solve_subset(idx, cnt, sub.F, sub.P, sub.A, sub.w, sub.status, sub.iters)
+    torch.cuda.synchronize()
+    rf, rs = full.results(), sub.results()
+    valid = pick[(pick >= 0) & (pick < B)]
+    np.testing.assert_array_equal(rs["P"][valid], rf["P"][valid])
+    np.testing.assert_array_equal(rs["A"][valid], rf["A"][valid])
+    np.testing.assert_array_equal(rs["status"][valid], rf["status"][valid])
+    rest = np.setdiff1d(np.arange(B), valid)
+    assert np.all(np.isnan(rs["P"][rest])) and np.all(rs["status"][rest] == -7)
+
+
+@pytest.fixture(scope="module")
+def fitted():
+    torch_cuda()
+    from paper_1908_08292_amd import api
+    info = {}
+    sg = api.fit_surrogate(n=16, radius=0.25, ratio=10.0, timings=info)
+    print("fit:", info)
+    yield sg, info
+    sg.destroy()
+
+
+def test_surrogate_audit_against_rve_judge(fitted):
+    """Fresh judged sample (4000 points, 2% of the training size) from the same
+    generator: every point the indicator accepts at 1e-3 is within 1e-3 of the
+    RVE solve in P, and most points are accepted."""
+    torch = torch_cuda()
+    from paper_1908_08292_amd import api, workloads
+    sg, _ = fitted
+    n = 4000
+    F = workloads.draw_F(np.random.default_rng(2024), n, 2, 0.2).reshape(-1, 4)
+    batch, _ = api.build_batch(2, np.full(n, 16), np.full(n, 0.25), np.full(n, 10.0))
+    sol = api.Solver(batch, keep_state=False)
+    sol.set_F(F)
+    sol.solve()
+    Fd = sol.F.view(-1, 4)
+    Ps = torch.empty(n, 4, dtype=torch.float64, device="cuda")
+    As = torch.empty(n, 16, dtype=torch.float64, device="cuda")
+    ind = torch.empty(n, dtype=torch.float32, device="cuda")
+    sg.eval(Fd, Ps, As, ind)
+    torch.cuda.synchronize()
+    Pj = sol.P.view(-1, 4).cpu().numpy()
+    Aj = sol.A.view(-1, 16).cpu().numpy()
+    ok = sol.status.cpu().numpy() == 0
+    e = np.linalg.norm(Ps.cpu().numpy() - Pj, axis=1) / np.linalg.norm(Pj, axis=1)
+    eA = np.linalg.norm(As.cpu().numpy() - Aj, axis=1) / np.linalg.norm(Aj, axis=1)
+    acc = (ind.cpu().numpy() <= 1e-3) & ok
+    print(f"accepted {acc.mean():.3f}; err_P accepted max {e[acc].max():.2e} p99 {np.quantile(e[acc], .99):.2e}; "
+          f"all points median {np.median(e[ok]):.2e}; err_A accepted median {np.median(eA[acc]):.2e}")
+    assert acc.mean() > 0.5
+    assert e[acc].max() <= 1e-3
+
+
+def test_surrogate_gain_on_two_scale_problem(fitted):
+    """Plate with a hole (16 x 16 macro grid, r = 0.2, uniaxial stretch to 1.15 in
+    20 steps, first 4 steps), nested two-level Newton on 16 x 16 RVEs, with and
+    without the surrogate: the surrogate run must reach the same macro solution
+    (relative displacement difference below 1e-3) with a fraction of the RVE
+    solves and in less time.  With the surrogate the macro Newton stops at 1e-4
+    of the step's first residual (its stresses carry FP32 rounding); the plain
+    run converges to 1e-10."""
+    torch = torch_cuda()
+    import time
+    from paper_1908_08292_amd import fehmm, rve
+    sg, _ = fitted
+    lame = rve.two_phase_lame(10.0)
+    res = {}
+    for use in (False, True):
+        mesh = rve.Mesh(2, 16, lame, radius=0.25)
+        drv = fehmm.Driver(mesh, nx=16, ny=16, hole_r=0.2, bc=fehmm.BC_UNIAXIAL, stretch=1.15, nsteps=20)
+        if use:
+            drv.set_surrogate(sg, threshold=1e-3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solves = evals = 0
+        for k in range(1, 5):
+            st = drv.step(k)
+            assert st["status"] == 0, (use, k, st)
+            n_eval = (st["macro_iters"] + 1) * drv.nqp
+            solves += st["fallback_points"] if use else n_eval
+            evals += n_eval
+        dt = time.perf_counter() - t0
+        res[use] = dict(u=drv.u(), t=dt, solves=solves, evals=evals)
+        drv.destroy()
+    du = np.linalg.norm(res[True]["u"] - res[False]["u"]) / np.linalg.norm(res[False]["u"])
+    frac = res[True]["solves"] / res[True]["evals"]
+    print(f"RVE solves {res[False]['solves']} -> {res[True]['solves']} ({frac:.3f} of evaluations); "
+          f"time {res[False]['t']:.3f} s -> {res[True]['t']:.3f} s; rel |du| {du:.2e}")
+    assert du < 1e-3
+    assert frac < 0.5
+    assert res[True]["t"] < res[False]["t"]
