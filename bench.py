@@ -21,6 +21,15 @@ Prints one JSON line.  Options:
                            64 x 64 plate with a hole (14288 RVEs of 16 x 16) over
                            its first --macro-steps of 20 load steps, nested and
                            alternating two-level Newton
+  --precision fp64|fp32ir|both   the timed RVE path(s); `value` is the FP64 path
+                           when it is timed, the FP32-factor path otherwise
+  --no-surrogate           skip the surrogate block: MLP energy W(C) trained by the
+                           library on 2e5 solver-generated triples (16 x 16 RVE,
+                           H in [-0.2, 0.2]), its evals/s on 14288 points, a 2 %
+                           random audit of the plate problem's accepted points
+                           against RVE solves, and macro steps/s of the 64 x 64
+                           plate with a hole, nested, plain FP64 vs surrogate with
+                           fallback at indicator 1e-3
 """
 import argparse
 import json
@@ -34,6 +43,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector = FP64 matrix (dense)
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 MFMA
 PEAK_HBM_GBS = 8000.0
 
 
@@ -89,13 +99,16 @@ def measured_traffic(workload):
     return rec["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(wl, meta, budget_rves):
+def cpu_baseline(wl, meta, budget_rves, gpu_results=None):
+    """Oracle throughput on the first RVEs of the workload; when GPU results of
+    the same RVEs are given, also the largest relative errors against them."""
     import oracle
     d = meta["d"]
     B = min(budget_rves, len(wl.F))
     nthreads = len(os.sched_getaffinity(0))
     t_total = 0.0
     ndone = 0
+    worst = {}
     for n in sorted(set(int(x) for x in wl.n[:B])):
         idx = np.nonzero(wl.n[:B] == n)[0]
         phases = np.stack([oracle.phase_by_centroid(d, n, wl.radius[b]) for b in idx])
@@ -112,10 +125,124 @@ def cpu_baseline(wl, meta, budget_rves):
             out = oracle.rve_solve_batch(d, n, phases, lame, wl.F[idx], nthreads=nthreads)
             t_total += time.perf_counter() - t0
             assert np.all(out["status"] == 0)
+            mu_max = lame[:, 1].max()
+            for name, res in (gpu_results or {}).items():
+                Pg = res["P"].reshape(len(wl.F), -1)[idx]
+                Ag = res["A"].reshape(len(wl.F), -1)[idx]
+                Po, Ao = out["P"].reshape(len(idx), -1), out["A"].reshape(len(idx), -1)
+                eP = np.linalg.norm(Pg - Po, axis=1) / np.maximum(np.linalg.norm(Po, axis=1), 1e-12 * mu_max)
+                eA = np.linalg.norm(Ag - Ao, axis=1) / np.maximum(np.linalg.norm(Ao, axis=1), 1e-12 * mu_max)
+                w = worst.setdefault(name, [0.0, 0.0])
+                w[0], w[1] = max(w[0], float(eP.max())), max(w[1], float(eA.max()))
         ndone += len(idx)
-    return dict(value=ndone / t_total, unit="RVE solves/s", cores=nthreads, kind="oracle",
-                sample=f"first {ndone} of {len(wl.F)} RVEs of the same workload ({t_total:.1f} s, "
-                       f"OpenMP over RVEs, {nthreads} threads)")
+    out = dict(value=ndone / t_total, unit="RVE solves/s", cores=nthreads, kind="oracle",
+               sample=f"first {ndone} of {len(wl.F)} RVEs of the same workload ({t_total:.1f} s, "
+                      f"OpenMP over RVEs, {nthreads} threads)")
+    if worst:
+        out["gpu_vs_oracle_on_sample"] = {k: {"max_rel_err_P": v[0], "max_rel_err_A": v[1]} for k, v in worst.items()}
+    return out
+
+
+def time_solves(s, opts, stream, steps, warmup):
+    import torch
+    sp = stream.cuda_stream
+    for _ in range(warmup):
+        s.solve(opts=opts, stream=sp)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        s.solve(opts=opts, stream=sp)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def surrogate_bench(macro_steps):
+    """configs[4]: the surrogate of the 64 x 64 plate problem's RVE."""
+    import torch
+
+    from paper_1908_08292_amd import api, fehmm, rve, surrogate
+    out = {}
+    fit = {}
+    sg = api.fit_surrogate(n=16, radius=0.25, ratio=10.0, n_train=200000, n_calib=20000, h=0.2, timings=fit)
+    out["train"] = fit
+    print(f"[bench] surrogate trained: {fit}", file=sys.stderr, flush=True)
+    # macro steps/s, plain FP64 vs surrogate with fallback (nested)
+    lame = rve.two_phase_lame(10.0)
+    runs = {}
+    for use in (False, True):
+        mesh = rve.Mesh(2, 16, lame, radius=0.25)
+        drv = fehmm.Driver(mesh, nx=64, ny=64, hole_r=0.2, bc=fehmm.BC_UNIAXIAL, stretch=1.15, nsteps=20)
+        if use:
+            drv.set_surrogate(sg, threshold=1e-3, precision=surrogate.BF16X3, macro_rtol=1e-4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, fb, ev, ok = [], 0, 0, True
+        for k in range(1, macro_steps + 1):
+            st = drv.step(k)
+            its.append(st["macro_iters"])
+            ev += (st["macro_iters"] + 1) * drv.nqp
+            fb += st["fallback_points"] if use else (st["macro_iters"] + 1) * drv.nqp
+            ok = ok and st["status"] == 0
+        dt = time.perf_counter() - t0
+        runs[use] = dict(macro_steps_per_s=macro_steps / dt, seconds=dt, macro_iters=its, rve_solves=int(fb),
+                         qp_evaluations=int(ev), converged=bool(ok), u=drv.u())
+        if use:
+            F_last = torch.tensor(drv.qp()[0], device="cuda").reshape(-1, 4).contiguous()
+        drv.destroy()
+        print(f"[bench] plate 64x64 {'surrogate' if use else 'plain'}: {runs[use]['seconds']:.2f} s",
+              file=sys.stderr, flush=True)
+    du = float(np.linalg.norm(runs[True]["u"] - runs[False]["u"]) / np.linalg.norm(runs[False]["u"]))
+    for r in runs.values():
+        r.pop("u")
+    out["macro_plate64_hole_rve16"] = dict(plain_fp64=runs[False], surrogate=runs[True],
+                                           speedup=runs[True]["macro_steps_per_s"] / runs[False]["macro_steps_per_s"],
+                                           rel_displacement_diff=du, steps=macro_steps, rves=int(F_last.shape[0]))
+    # evals/s on the last state's 14288 points, and the audit of a 2% random sample
+    nq = F_last.shape[0]
+    P = torch.empty(nq, 4, dtype=torch.float64, device="cuda")
+    A = torch.empty(nq, 16, dtype=torch.float64, device="cuda")
+    ind = torch.empty(nq, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        sg.eval(F_last, P, A, ind, precision=surrogate.BF16X3, stream=stream.cuda_stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    reps = 50
+    ev0.record(stream)
+    for _ in range(reps):
+        sg.eval(F_last, P, A, ind, precision=surrogate.BF16X3, stream=stream.cuda_stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) / reps * 1e3
+    rng = np.random.default_rng(1004)
+    pick = np.sort(rng.choice(nq, size=max(1, int(np.ceil(0.02 * nq))), replace=False))
+    Fa = F_last.cpu().numpy()[pick]
+    batch, _ = api.build_batch(2, np.full(len(pick), 16), np.full(len(pick), 0.25), np.full(len(pick), 10.0))
+    judge = api.Solver(batch, keep_state=False)
+    judge.set_F(Fa)
+    judge.solve()
+    jr = judge.results()
+    Pj = jr["P"].reshape(-1, 4)
+    Ps = P.cpu().numpy()[pick]
+    acc = (ind.cpu().numpy()[pick] <= 1e-3) & (jr["status"] == 0)
+    e = np.linalg.norm(Ps - Pj, axis=1) / np.linalg.norm(Pj, axis=1)
+    flops = 2 * 2.0 * 128 * 128 * 10  # two 128x128 layers on 10-component jets (algorithmic, per point)
+    out["eval"] = dict(points=int(nq), us_per_launch=us, evals_per_s=nq / (us * 1e-6), precision="bf16x3",
+                       roofline={"bound": "mfma", "achieved": flops * nq / (us * 1e-6) / 1e12,
+                                 "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": flops * nq / (us * 1e-6) / 1e12 / PEAK_BF16_TFLOPS,
+                                 "flops_counted": "2 x 2*128*128*10 per point (jet GEMMs; the split "
+                                                  "form executes 3x that on the MFMA)"})
+    out["audit"] = dict(sample=f"{len(pick)} random points (2%) of the last load step's {nq}",
+                        accepted_fraction=float(acc.mean()),
+                        max_rel_err_P_accepted=float(e[acc].max()) if acc.any() else None,
+                        p99_rel_err_P_accepted=float(np.quantile(e[acc], 0.99)) if acc.any() else None,
+                        threshold=1e-3)
+    sg.destroy()
+    return out
 
 
 def macro_bench(nsteps3):
@@ -158,8 +285,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--calib-copy", type=int, default=0)
     ap.add_argument("--macro", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32ir", "both"], default="both")
     ap.add_argument("--macro-steps", type=int, default=4)
+    ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the RVE batch would be sharded by macro elements "
@@ -175,27 +303,19 @@ def main():
     batch, meshes = api.build_batch(d, wl.n, wl.radius, wl.ratio)
     s = api.Solver(batch, want_A=True, keep_state=False)
     s.set_F(wl.F)
-    opts = rve.default_opts(precision=rve.PREC_FP32_IR if args.precision == "fp32ir" else rve.PREC_FP64)
     stream = torch.cuda.current_stream()
-    sp = stream.cuda_stream
-    print(f"[bench] {meta['workload']}: warmup {args.warmup}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        s.solve(opts=opts, stream=sp)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for k in range(args.steps):
-        s.solve(opts=opts, stream=sp)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / args.steps
-    print(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
-    res = s.results()
-    nbad = int((res["status"] != 0).sum())
+    precs = ["fp64", "fp32ir"] if args.precision == "both" else [args.precision]
+    timed = {}
+    for p in precs:
+        opts = rve.default_opts(precision=rve.PREC_FP32_IR if p == "fp32ir" else rve.PREC_FP64)
+        print(f"[bench] {meta['workload']} {p}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
+              flush=True)
+        ms = time_solves(s, opts, stream, args.steps, args.warmup)
+        res = s.results()
+        timed[p] = dict(ms=ms, res=res, nbad=int((res["status"] != 0).sum()))
+        print(f"[bench] {p}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    head = "fp64" if "fp64" in timed else precs[0]
+    ms, res = timed[head]["ms"], timed[head]["res"]
     if args.calib_copy > 0:
         nel = args.calib_copy * (1 << 20) // 8
         x = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -217,21 +337,31 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 factors + f64 refinement",
+        "dtype": "f64" if head == "fp64" else "f32 factors + f64 refinement",
         "data": "synthetic",
         "config": {"workload": meta["workload"], "rves": B, "dim": d, "elements_per_edge": meta["n"],
-                   "precision": args.precision, "newton_rtol": 1e-10,
-                   "mean_newton_iters": float(res["iters"].mean()), "failed_rves": nbad},
+                   "precision": head, "newton_rtol": 1e-10,
+                   "mean_newton_iters": float(res["iters"].mean()), "failed_rves": timed[head]["nbad"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(meta["workload"]),
                      "kernel": f"rve_solve_kernel<{d}>", "flops_per_launch": flops,
                      "flops_counted": "LDL^T factorizations + triangular solves from the symbolic plan"},
     }
+    if "fp32ir" in timed and head != "fp32ir":
+        t = timed["fp32ir"]
+        out["mixed_precision"] = dict(value=B / (t["ms"] * 1e-3), unit="RVE solves/s", ms_per_step=t["ms"],
+                                      speedup_vs_fp64=ms / t["ms"], failed_rves=t["nbad"],
+                                      mean_newton_iters=float(t["res"]["iters"].mean()),
+                                      dtype="f32 factors (LDL^T, solves) + f64 residuals, refinement, "
+                                            "norms, averages and condensation")
     if args.macro:
         out["macro"] = macro_bench(args.macro_steps)
+    if not args.no_surrogate and d == 2:
+        out["surrogate"] = surrogate_bench(args.macro_steps)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, meta, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(wl, meta, args.cpu_sample,
+                                           gpu_results={p: t["res"] for p, t in timed.items()})
     print(json.dumps(out), flush=True)
 
 
