@@ -202,6 +202,229 @@ __global__ __launch_bounds__(NTB) void macro_band_solve(double* __restrict__ K, 
     }
 }
 
+// Blocked banded LDL^T and solve K du = -R in one workgroup of 4 waves, for
+// bandwidths up to kBandMaxBw.  Per block of kPanel columns: wave 0 factors the
+// panel (kPanel columns x up to kPanel + bw rows) in registers, one column
+// after the other with the pivot row's values broadcast by readlane (no
+// barrier inside a panel); then all waves apply the panel's rank-kPanel update
+// to the trailing bw x bw triangle as 16 x 16 FP64 MFMA tiles.  The factor is
+// also written transposed (Kt: row j holds column j of L), so both triangular
+// solves read contiguous band rows: blocks of 64 rows are staged in LDS by the
+// whole workgroup, the contributions of earlier (forward) or later (backward)
+// blocks are dot products split over the waves, and the 64 x 64 diagonal
+// triangle is a sweep in wave 0 (lane = row) with readlane broadcasts.
+// Solution values of the last bw rows live in an LDS ring.  Global loads are
+// issued unconditionally (clamped addresses) so that they pipeline.
+constexpr int kPanel = 16;
+constexpr int kPanelStride = kPanel + 1;                   // LDS row stride (doubles), bank spread
+constexpr int kPanelSlotsMax = 4;                          // rows per lane in the panel
+constexpr int kBandMaxBw = 64 * kPanelSlotsMax - kPanel;   // 240
+constexpr int kBandNT = 256;
+constexpr int kRing = 256;                                 // power of two > kBandMaxBw
+
+typedef double band_dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ inline double rdlane(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// dynamic LDS of the band solve (doubles): max(panel staging, 64 solve rows) + ring + partial sums
+inline size_t band_lds_bytes(int bw) {
+    const size_t panel = 2 * (size_t)(kPanel + kBandMaxBw) * kPanelStride;
+    const size_t rows = 64 * (size_t)(bw + 1);
+    return sizeof(double) * (std::max(panel, rows) + kRing + 4 * 64);
+}
+
+template <int SLOTS>
+__global__ __launch_bounds__(kBandNT) void macro_band_solve_blocked(double* __restrict__ K, double* __restrict__ Kt,
+                                                                    const double* __restrict__ R, int n, int bw,
+                                                                    double* __restrict__ du, int* __restrict__ flag) {
+    extern __shared__ double band_lds[];
+    const int ld = bw + 1, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const size_t big = std::max<size_t>(2 * (size_t)(kPanel + kBandMaxBw) * kPanelStride, 64 * (size_t)ld);
+    double* Ls = band_lds;                                          // scaled panel columns L[r][c]
+    double* Ws = band_lds + (kPanel + kBandMaxBw) * kPanelStride;   // L[r][c] * D[c]
+    double* Kb = band_lds;                                          // staged solve rows (after the factorization)
+    double* ring = band_lds + big;
+    double* red = ring + kRing;
+    const int64_t last = (int64_t)n * ld - 1;
+    for (int k0 = 0; k0 < n; k0 += kPanel) {
+        const int nb = min(kPanel, n - k0);
+        const int m = min(n - k0, nb + bw);  // rows touched by the panel
+        if (wave == 0) {
+            double pv[SLOTS][kPanel];
+#pragma clang loop unroll(full)
+            for (int s = 0; s < SLOTS; ++s) {
+                const int rr = lane + 64 * s, r = k0 + rr;
+#pragma clang loop unroll(full)
+                for (int c = 0; c < kPanel; ++c) {
+                    const int off = rr - c;  // r - (k0 + c)
+                    const bool in = c < nb && rr < m && off >= 0 && off <= bw;
+                    const double v = K[in ? (int64_t)r * ld + off : 0];
+                    pv[s][c] = in ? v : 0.0;
+                }
+            }
+#pragma clang loop unroll(full)
+            for (int c = 0; c < kPanel; ++c) {
+                if (c < nb) {
+                    const double piv = rdlane(pv[0][c], c);
+                    if (lane == 0 && (!(fabs(piv) > 0.0) || !isfinite(piv))) *flag = 1;
+                    const double inv = 1.0 / piv;
+                    double colv[kPanel];
+#pragma clang loop unroll(full)
+                    for (int j = 0; j < kPanel; ++j) colv[j] = (j > c) ? rdlane(pv[0][c], j) : 0.0;
+                    // rows at or above the pivot get l = 0 (predicated, no branch)
+#pragma clang loop unroll(full)
+                    for (int s = 0; s < SLOTS; ++s) {
+                        const int rr = lane + 64 * s;
+                        const double l = (rr > c) ? pv[s][c] * inv : 0.0;
+#pragma clang loop unroll(full)
+                        for (int j = c + 1; j < kPanel; ++j) pv[s][j] -= (rr >= j) ? l * colv[j] : 0.0;
+                        pv[s][c] = (rr > c) ? l : pv[s][c];
+                    }
+                }
+            }
+            // write back (L below the diagonal, D on it; transposed copy in Kt) and
+            // stage L, L*D for the update
+            double dcol[kPanel];
+#pragma clang loop unroll(full)
+            for (int c = 0; c < kPanel; ++c) dcol[c] = rdlane(pv[0][c], c);
+#pragma clang loop unroll(full)
+            for (int s = 0; s < SLOTS; ++s) {
+                const int rr = lane + 64 * s, r = k0 + rr;
+                if (rr < m) {
+#pragma clang loop unroll(full)
+                    for (int c = 0; c < kPanel; ++c) {
+                        const int off = rr - c;
+                        const bool in = c < nb && off >= 0 && off <= bw;
+                        if (in) {
+                            K[(int64_t)r * ld + off] = pv[s][c];
+                            Kt[(int64_t)(k0 + c) * ld + off] = pv[s][c];
+                        }
+                        const double l = (in && off > 0) ? pv[s][c] : 0.0;
+                        Ls[rr * kPanelStride + c] = l;
+                        Ws[rr * kPanelStride + c] = l * dcol[c];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // trailing update: K[i][j] -= sum_c L[i][c] D[c] L[j][c] for nb <= j <= i < m
+        // trailing update on FP64 MFMA: 16 x 16 lower-triangle tiles of the
+        // (T x 16)(16 x T) product, two tiles per wave and pass (their old values
+        // are loaded before the MFMAs)
+        {
+            const int T = m - nb;
+            const int n16 = (T + 15) >> 4;
+            const int ntile = n16 * (n16 + 1) / 2;
+            for (int tt = 2 * wave; tt < ntile; tt += 8) {
+                int Ii[2], Jj[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int t = tt + u;
+                    int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+                    if ((r + 1) * (r + 2) / 2 <= t) ++r;
+                    if (r * (r + 1) / 2 > t) --r;
+                    Ii[u] = r;
+                    Jj[u] = t - r * (r + 1) / 2;
+                }
+                double old[2][4];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * Ii[u] + (lane >> 4) + 4 * v, col = 16 * Jj[u] + (lane & 15);
+                        const bool in = tt + u < ntile && row < T && col <= row;
+                        old[u][v] = K[in ? (int64_t)(k0 + nb + row) * ld + (row - col) : 0];
+                    }
+                band_dbl4 acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int kk = 4 * ks + (lane >> 4);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int ra = nb + 16 * Ii[u] + (lane & 15), rb = nb + 16 * Jj[u] + (lane & 15);
+                        const double av = Ls[(ra < m ? ra : 0) * kPanelStride + kk];
+                        const double bv = Ws[(rb < m ? rb : 0) * kPanelStride + kk];
+                        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra < m ? av : 0.0, rb < m ? bv : 0.0, acc[u],
+                                                                     0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * Ii[u] + (lane >> 4) + 4 * v, col = 16 * Jj[u] + (lane & 15);
+                        if (tt + u < ntile && row < T && col <= row)
+                            K[(int64_t)(k0 + nb + row) * ld + (row - col)] = old[u][v] - acc[u][v];
+                    }
+            }
+        }
+        __syncthreads();
+    }
+    // triangular solves: forward (pass 0) L y = -R on K, backward (pass 1)
+    // x = D^-1 y - L^T x on Kt; blocks of 64 rows staged in LDS
+    for (int pass = 0; pass < 2; ++pass) {
+        const double* Src = pass == 0 ? K : Kt;
+        const int nblk64 = (n + 63) / 64;
+        for (int bi = 0; bi < nblk64; ++bi) {
+            const int i0 = (pass == 0 ? bi : nblk64 - 1 - bi) * 64;
+            const int rows = min(64, n - i0);
+            const int64_t base = (int64_t)i0 * ld;
+            const int cnt = rows * ld;
+            for (int e = tid; e < cnt; e += kBandNT) Kb[e] = Src[base + e];
+            __syncthreads();
+            // contributions of rows outside the block, split over the waves
+            const int i = i0 + lane;
+            double sdot = 0.0;
+            if (lane < rows) {
+                if (pass == 0) {
+                    // t = i - j with j < i0
+                    const int tmax = min(i, bw);
+                    for (int t = lane + 1 + wave; t <= tmax; t += 4)
+                        sdot += Kb[lane * ld + t] * ring[(i - t) & (kRing - 1)];
+                } else {
+                    // t = j - i with j >= i0 + 64
+                    const int tmax = min(n - 1 - i, bw);
+                    for (int t = 64 - lane + wave; t <= tmax; t += 4)
+                        sdot += Kb[lane * ld + t] * ring[(i + t) & (kRing - 1)];
+                }
+            }
+            red[wave * 64 + lane] = sdot;
+            __syncthreads();
+            if (wave == 0) {
+                double acc = 0.0;
+                if (lane < rows) {
+                    const double s4 = red[lane] + red[64 + lane] + red[128 + lane] + red[192 + lane];
+                    acc = pass == 0 ? -R[i] - s4 : du[i] / Kb[lane * ld] - s4;  // du[i]: stored by this lane
+                }
+                if (pass == 0) {
+                    for (int k = 0; k < rows; ++k) {
+                        const double yk = rdlane(acc, k);
+                        const int off = lane - k;
+                        const double l = Kb[lane * ld + ((off > 0 && off <= bw && lane < rows) ? off : 0)];
+                        if (off > 0 && off <= bw && lane < rows) acc -= l * yk;
+                    }
+                } else {
+                    for (int k = rows - 1; k >= 0; --k) {
+                        const double xk = rdlane(acc, k);
+                        const int off = k - lane;
+                        const double l = Kb[lane * ld + ((off > 0 && off <= bw) ? off : 0)];
+                        if (off > 0 && off <= bw) acc -= l * xk;
+                    }
+                }
+                if (lane < rows) {
+                    ring[i & (kRing - 1)] = acc;
+                    du[i] = acc;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 __global__ void macro_update(double* __restrict__ u, const double* __restrict__ du, const int* __restrict__ fixed,
                              int ndof) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -233,6 +456,7 @@ struct fehmm_s {
     int *d_status = nullptr, *d_iters = nullptr, *d_flag = nullptr;
     double *d_u = nullptr, *d_du = nullptr, *d_uval = nullptr, *d_F = nullptr, *d_P = nullptr, *d_A = nullptr;
     double *d_w = nullptr, *d_ke = nullptr, *d_fe = nullptr, *d_K = nullptr, *d_R = nullptr, *d_norm = nullptr;
+    double* d_Kt = nullptr;  // transposed copy of the band factor (blocked band solve)
     // surrogate replacement of micro solves
     rve_surrogate surr = nullptr;
     float surr_thr = 0.f;
@@ -253,7 +477,7 @@ static void fehmm_free(fehmm_s* h) {
     int* ip[] = {h->d_conn, h->d_fixed, h->d_col[0], h->d_col[1], h->d_col[2], h->d_col[3], h->d_status,
                  h->d_iters, h->d_flag};
     for (int* p : ip) (void)hipFree(p);
-    double* dp[] = {h->d_u, h->d_du, h->d_uval, h->d_F, h->d_P, h->d_A, h->d_w, h->d_ke, h->d_fe, h->d_K,
+    double* dp[] = {h->d_Kt, h->d_u, h->d_du, h->d_uval, h->d_F, h->d_P, h->d_A, h->d_w, h->d_ke, h->d_fe, h->d_K,
                     h->d_R, h->d_norm};
     for (double* p : dp) (void)hipFree(p);
     (void)hipFree(h->d_ind);
@@ -279,6 +503,17 @@ int fehmm_create(const fehmm_desc* d, fehmm* out) {
     if (d->nsteps < 1 || !(d->rtol_macro > 0) || d->max_macro_iter < 1 || d->max_macro_iter > FEHMM_MAX_HIST - 1)
         return set_error(RVE_EINVAL, "fehmm_create: bad load-step or Newton settings");
     if (!d->micro) return set_error(RVE_EINVAL, "fehmm_create: micro mesh required");
+    static bool band_prepared = false;
+    if (!band_prepared) {
+        const int lds = (int)band_lds_bytes(kBandMaxBw);
+        FH_HIP(hipFuncSetAttribute((const void*)macro_band_solve_blocked<2>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        FH_HIP(hipFuncSetAttribute((const void*)macro_band_solve_blocked<3>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        FH_HIP(hipFuncSetAttribute((const void*)macro_band_solve_blocked<4>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        band_prepared = true;
+    }
     auto h = std::make_unique<fehmm_s>();
     h->desc = *d;
     const int nx = d->nx, ny = d->ny;
@@ -373,6 +608,7 @@ int fehmm_create(const fehmm_desc* d, fehmm* out) {
         (st = zal(&H->d_P, 4 * (int64_t)H->nqp)) || (st = zal(&H->d_A, 16 * (int64_t)H->nqp)) ||
         (st = zal(&H->d_w, H->state_doubles)) || (st = zal(&H->d_ke, 64 * (int64_t)H->nelem)) ||
         (st = zal(&H->d_fe, 8 * (int64_t)H->nelem)) || (st = zal(&H->d_K, (int64_t)H->ndof * (H->bw + 1))) ||
+        (st = zal(&H->d_Kt, (int64_t)H->ndof * (H->bw + 1))) ||
         (st = zal(&H->d_R, H->ndof)) || (st = zal(&H->d_norm, 2))) {
         fehmm_free(H);
         return st;
@@ -505,8 +741,20 @@ int fehmm_macro_step(fehmm h, int32_t step, fehmm_step_info* info) {
             break;
         }
         hipLaunchKernelGGL(macro_zero_int, dim3(1), dim3(64), 0, s, h->d_flag, 1);
-        hipLaunchKernelGGL(macro_band_solve, dim3(1), dim3(NTB), 0, s, h->d_K, h->d_R, h->ndof, h->bw, h->d_du,
-                           h->d_flag);
+        const int slots = (kPanel + h->bw + 63) / 64;  // panel rows per lane
+        const size_t lds = band_lds_bytes(h->bw);
+        if (slots <= 2)
+            hipLaunchKernelGGL(macro_band_solve_blocked<2>, dim3(1), dim3(kBandNT), lds, s, h->d_K, h->d_Kt, h->d_R,
+                               h->ndof, h->bw, h->d_du, h->d_flag);
+        else if (slots == 3)
+            hipLaunchKernelGGL(macro_band_solve_blocked<3>, dim3(1), dim3(kBandNT), lds, s, h->d_K, h->d_Kt, h->d_R,
+                               h->ndof, h->bw, h->d_du, h->d_flag);
+        else if (slots == 4)
+            hipLaunchKernelGGL(macro_band_solve_blocked<4>, dim3(1), dim3(kBandNT), lds, s, h->d_K, h->d_Kt, h->d_R,
+                               h->ndof, h->bw, h->d_du, h->d_flag);
+        else
+            hipLaunchKernelGGL(macro_band_solve, dim3(1), dim3(NTB), 0, s, h->d_K, h->d_R, h->ndof, h->bw, h->d_du,
+                               h->d_flag);
         hipLaunchKernelGGL(macro_update, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_u, h->d_du, h->d_fixed,
                            h->ndof);
         ++it;

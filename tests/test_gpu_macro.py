@@ -98,3 +98,30 @@ def test_checkpoint_resume_bitwise():
     for k in (3, 4):
         c.step(k)
     assert np.array_equal(a.u(), c.u())
+
+
+@pytest.mark.parametrize("nx", [20, 60, 100, 130])
+def test_uniaxial_homogeneous_exact(nx):
+    """Homogeneous RVE, uniaxial stretch a = 1.02 in 4 load steps (the first
+    Newton iterate of a step has the increment only on the right edge, one
+    element wide): the discrete solution is the
+    homogeneous deformation u = ((a - 1) x, (b - 1) y) with P22 = 0, i.e.
+    b^2 = (mu + lam/2) / (mu + lam a^2 / 2) for P = mu F - (mu - lam/2 (J^2 - 1)) F^-T.
+    The grid sizes give band widths 43, 123, 203 and 263, which exercise every
+    variant of the macro band solver (panel registers per lane 2, 3, 4, and the
+    unblocked kernel beyond width 240)."""
+    need_gpu()
+    print(f"case uniaxial homogeneous {nx} x {nx}", flush=True)
+    lame = rve.two_phase_lame(10.0)
+    lam, mu = lame[0]
+    mesh = rve.Mesh(2, 3, lame, phase=np.zeros(9, np.uint8))
+    a = 1.02
+    drv = fehmm.Driver(mesh, nx, nx, bc=fehmm.BC_UNIAXIAL, stretch=a, nsteps=4, rtol_macro=1e-12)
+    for k in range(1, 5):
+        st = drv.step(k)
+        assert st["status"] == 0 and st["macro_iters"] <= 8, (k, st)
+    b = np.sqrt((mu + lam / 2) / (mu + lam * a * a / 2))
+    xy = drv.nodes()
+    u = drv.u().reshape(-1, 2)
+    ue = np.stack([(a - 1) * xy[:, 0], (b - 1) * xy[:, 1]], 1)
+    assert np.abs(u - ue).max() <= 1e-9, np.abs(u - ue).max()
