@@ -102,6 +102,13 @@ int fehmm_get_qp(fehmm h, double* F, double* P, double* A);
  * surrogate off.  The surrogate must outlive its use by the driver.  Only the
  * nested scheme uses it (alternating: EUNSUPPORTED). */
 int fehmm_set_surrogate(fehmm h, struct rve_surrogate_s* s, float threshold, int32_t precision, double macro_rtol);
+/* enable != 0: each later fehmm_macro_step runs as one HIP graph launch -- the
+ * load step's start and max_macro_iter + 1 macro iterations, with the macro
+ * Newton's convergence test on the device and every kernel after convergence a
+ * no-op -- captured on first use and replayed for the following steps; the
+ * host waits once per step instead of once per macro iteration.  Results are
+ * identical to the eager path.  Changing the surrogate drops the graph. */
+int fehmm_set_graph(fehmm h, int32_t enable);
 /* Checkpoint / resume: u [ndof] in host memory, the micro fluctuations
  * [state_doubles] in host memory.  set_state restores both. */
 int fehmm_get_state(fehmm h, double* u_host, double* w_host);

@@ -494,10 +494,17 @@ int oracle_rve_solve(int d, int n, const uint8_t* phase, const double* lame, con
     double* wt = (double*)malloc(sizeof(double) * ndof);
     if (w_io) memcpy(w, w_io, sizeof(double) * ndof);
     for (int k = 0; k < d; ++k) w[k] = 0.0; /* pinned node */
-    int status = ORC_OK, it = 0;
+    int status = ORC_OK, it = 0, restarted = 0;
     double r0 = 0;
     for (;;) {
         int st = rve_assemble(&r, phase, lame, Fbar, w, R, 1);
+        if (st == ORC_DETF && it == 0 && w_io && !restarted) {
+            /* a stored fluctuation that folds an element under the new Fbar is
+             * discarded: restart from w = 0, where J = det Fbar > 0 */
+            memset(w, 0, sizeof(double) * ndof);
+            restarted = 1;
+            continue;
+        }
         if (st) { status = st; break; }
         double rn = norm_free(&r, R);
         if (!isfinite(rn)) { status = ORC_NONFINITE; break; }
@@ -681,6 +688,11 @@ int oracle__rve_one_step(int d, int n, const uint8_t* phase, const double* lame,
     double* dw = (double*)malloc(sizeof(double) * (r.nf ? r.nf : 1));
     double* wt = (double*)malloc(sizeof(double) * ndof);
     int status = rve_assemble(&r, phase, lame, Fbar, w_io, R, 1);
+    if (status == ORC_DETF) {
+        /* stored fluctuation infeasible under the new Fbar: restart from w = 0 */
+        memset(w_io, 0, sizeof(double) * ndof);
+        status = rve_assemble(&r, phase, lame, Fbar, w_io, R, 1);
+    }
     double rn = status ? NAN : norm_free(&r, R);
     if (rnorm) *rnorm = rn;
     if (!status && rn > o->atol) {

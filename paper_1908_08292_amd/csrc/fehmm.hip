@@ -29,7 +29,8 @@ struct MacroGeom {
 
 // F at every Gauss point: F = I + sum_a u_a (x) grad N_a
 __global__ void macro_gather_F(const int* __restrict__ conn, int nelem, const double* __restrict__ u, MacroGeom g,
-                               double* __restrict__ F) {
+                               double* __restrict__ F, const int* __restrict__ done) {
+    if (*done) return;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= 4 * nelem) return;
     const int e = q >> 2, gp = q & 3;
@@ -44,7 +45,8 @@ __global__ void macro_gather_F(const int* __restrict__ conn, int nelem, const do
 
 // element residual (8) and tangent (8 x 8) from the transferred Pbar, Abar
 __global__ void macro_element(int nelem, const double* __restrict__ P, const double* __restrict__ A, MacroGeom g,
-                              double* __restrict__ ke, double* __restrict__ fe) {
+                              double* __restrict__ ke, double* __restrict__ fe, const int* __restrict__ done) {
+    if (*done) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nelem * 8) return;
     const int e = t >> 3, r = t & 7, a = r >> 1, i = r & 1;
@@ -73,7 +75,8 @@ __global__ void macro_zero_int(int* __restrict__ x, int n) {
 // threshold (or is NaN) and stays; flag reports a new member; ind is
 // rewritten as +inf for members and 0 otherwise, for the compaction
 __global__ void macro_merge_fallback(float* __restrict__ ind, int* __restrict__ mask, float thr, int n,
-                                     int* __restrict__ flag) {
+                                     int* __restrict__ grew, const int* __restrict__ done) {
+    if (*done) return;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const float v = ind[q];
@@ -81,17 +84,19 @@ __global__ void macro_merge_fallback(float* __restrict__ ind, int* __restrict__ 
     if (!m && !(v <= thr)) {
         m = 1;
         mask[q] = 1;
-        flag[1] = 1;
+        *grew = 1;
     }
     ind[q] = m ? INFINITY : 0.0f;
 }
 
-__global__ void macro_zero_ints(int* __restrict__ x, int64_t n) {
+__global__ void macro_zero_ints(int* __restrict__ x, int64_t n, const int* __restrict__ done) {
+    if (done && *done) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) x[t] = 0;
 }
 
-__global__ void macro_zero(double* __restrict__ x, int64_t n) {
+__global__ void macro_zero(double* __restrict__ x, int64_t n, const int* __restrict__ done) {
+    if (*done) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) x[t] = 0.0;
 }
@@ -100,7 +105,8 @@ __global__ void macro_zero(double* __restrict__ x, int64_t n) {
 // K[i * (bw + 1) + (i - j)], i >= j, and into R
 __global__ void macro_scatter(const int* __restrict__ elist, int nel, const int* __restrict__ conn,
                               const double* __restrict__ ke, const double* __restrict__ fe, int bw,
-                              double* __restrict__ K, double* __restrict__ R) {
+                              double* __restrict__ K, double* __restrict__ R, const int* __restrict__ done) {
+    if (*done) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nel * 8) return;
     const int e = elist[t >> 3], r = t & 7;
@@ -114,7 +120,8 @@ __global__ void macro_scatter(const int* __restrict__ elist, int nel, const int*
 
 // Dirichlet dofs: identity row/column, zero residual (the increment there is 0)
 __global__ void macro_bc(const int* __restrict__ fixed, int ndof, int bw, double* __restrict__ K,
-                         double* __restrict__ R) {
+                         double* __restrict__ R, const int* __restrict__ done) {
+    if (*done) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ndof) return;
     for (int k = 1; k <= bw; ++k) {
@@ -127,37 +134,109 @@ __global__ void macro_bc(const int* __restrict__ fixed, int ndof, int bw, double
     }
 }
 
-// ||R||^2 and the number of failed RVEs, one workgroup
-__global__ void macro_norm(const double* __restrict__ R, int ndof, const int* __restrict__ status, int nqp,
-                           int tolerate_noconv, double* __restrict__ out) {
+// Device-side state of one load step.  The macro Newton's decisions are taken
+// on the device (macro_norm_step), and every later kernel of the step returns
+// at once when `done` is set, so a whole load step -- with its data-dependent
+// number of macro iterations -- can be replayed as one captured graph.
+struct StepState {
+    int step;       // load step (written by the host before the step)
+    int done;       // converged, failed or out of iterations
+    int it;         // macro Newton updates taken when done
+    int status;     // FEHMM_STEP_*
+    int failed;     // failed RVEs at the stopping iteration
+    int grew;       // surrogate: the fallback set grew in this iteration
+    int band_flag;  // zero or non-finite pivot in a macro solve
+    int pad;
+    double r0;
+    long long micro, fallback, surrogate;
+    double hist[FEHMM_MAX_HIST];
+};
+
+// start of a load step: prescribed displacements (right-edge x dofs: the step's
+// fraction of the stretch, other fixed dofs 0) and a reset state
+__global__ void macro_step_init(StepState* __restrict__ st, double* __restrict__ u, const int* __restrict__ fixed,
+                                const int* __restrict__ rightx, double ux_per_step, int ndof) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int step = st->step;
+    if (i < ndof && fixed[i]) u[i] = rightx[i] ? ux_per_step * step : 0.0;
+    if (i == 0) {
+        st->done = 0;
+        st->it = 0;
+        st->status = FEHMM_STEP_CONVERGED;
+        st->failed = 0;
+        st->grew = 0;
+        st->band_flag = 0;
+        st->r0 = -1.0;
+        st->micro = st->fallback = st->surrogate = 0;
+    }
+}
+
+// one workgroup: ||R||, failed RVEs and micro iterations of this macro
+// iteration; records the residual history and decides convergence
+__global__ void macro_norm_step(const double* __restrict__ R, int ndof, const int* __restrict__ status,
+                                const int* __restrict__ iters, int nqp, int tolerate_noconv,
+                                const int* __restrict__ fallback_count, StepState* __restrict__ st, int it,
+                                double rtol, int max_iter) {
+    if (st->done) return;
     __shared__ double s[256];
     __shared__ int bad[256];
+    __shared__ long long mi[256];
     double acc = 0.0;
     int nb = 0;
+    long long m = 0;
     for (int i = threadIdx.x; i < ndof; i += 256) acc += R[i] * R[i];
     for (int q = threadIdx.x; q < nqp; q += 256) {
-        const int st = status[q];
-        nb += (st != 0 && !(tolerate_noconv && st == 1)) ? 1 : 0;
+        const int sq = status[q];
+        nb += (sq != 0 && !(tolerate_noconv && sq == 1)) ? 1 : 0;
+        m += iters[q];
     }
     s[threadIdx.x] = acc;
     bad[threadIdx.x] = nb;
+    mi[threadIdx.x] = m;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) {
             s[threadIdx.x] += s[threadIdx.x + o];
             bad[threadIdx.x] += bad[threadIdx.x + o];
+            mi[threadIdx.x] += mi[threadIdx.x + o];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        out[0] = s[0];
-        out[1] = (double)bad[0];
+    if (threadIdx.x != 0) return;
+    st->micro += mi[0];
+    if (fallback_count) {
+        const int nf = *fallback_count;
+        st->fallback += nf;
+        st->surrogate += nqp - nf;
+    }
+    const int grew = st->grew;
+    st->grew = 0;
+    if (bad[0] > 0) {
+        st->status = FEHMM_STEP_RVE_FAILED;
+        st->failed = bad[0];
+        st->it = it;
+        st->done = 1;
+        return;
+    }
+    const double rn = sqrt(s[0]);
+    if (st->r0 < 0) st->r0 = rn;
+    const double r0 = st->r0;
+    st->hist[it] = r0 > 0 ? rn / r0 : 0.0;
+    if ((rn <= rtol * r0 || rn == 0.0) && !grew) {
+        st->it = it;
+        st->done = 1;
+    } else if (it == max_iter) {
+        st->status = FEHMM_STEP_NOCONV;
+        st->it = it;
+        st->done = 1;
     }
 }
 
 // banded LDL^T (lower band, bandwidth bw) and solve K du = -R in one workgroup
 __global__ __launch_bounds__(NTB) void macro_band_solve(double* __restrict__ K, const double* __restrict__ R, int n,
-                                                        int bw, double* __restrict__ du, int* __restrict__ flag) {
+                                                        int bw, double* __restrict__ du, int* __restrict__ flag,
+                                                        const int* __restrict__ done) {
+    if (*done) return;
     const int ld = bw + 1;
     for (int k = 0; k < n; ++k) {
         const double piv = K[(int64_t)k * ld];
@@ -240,7 +319,9 @@ inline size_t band_lds_bytes(int bw) {
 template <int SLOTS>
 __global__ __launch_bounds__(kBandNT) void macro_band_solve_blocked(double* __restrict__ K, double* __restrict__ Kt,
                                                                     const double* __restrict__ R, int n, int bw,
-                                                                    double* __restrict__ du, int* __restrict__ flag) {
+                                                                    double* __restrict__ du, int* __restrict__ flag,
+                                                                    const int* __restrict__ done) {
+    if (*done) return;
     extern __shared__ double band_lds[];
     const int ld = bw + 1, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const size_t big = std::max<size_t>(2 * (size_t)(kPanel + kBandMaxBw) * kPanelStride, 64 * (size_t)ld);
@@ -426,15 +507,10 @@ __global__ __launch_bounds__(kBandNT) void macro_band_solve_blocked(double* __re
 }
 
 __global__ void macro_update(double* __restrict__ u, const double* __restrict__ du, const int* __restrict__ fixed,
-                             int ndof) {
+                             int ndof, const int* __restrict__ done) {
+    if (*done) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ndof && !fixed[i]) u[i] += du[i];
-}
-
-__global__ void macro_dirichlet(double* __restrict__ u, const int* __restrict__ fixed,
-                                const double* __restrict__ uval, int ndof) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ndof && fixed[i]) u[i] = uval[i];
 }
 
 inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
@@ -453,8 +529,9 @@ struct fehmm_s {
     hipStream_t stream = nullptr;
     // device
     int *d_conn = nullptr, *d_fixed = nullptr, *d_col[4] = {nullptr, nullptr, nullptr, nullptr};
-    int *d_status = nullptr, *d_iters = nullptr, *d_flag = nullptr;
-    double *d_u = nullptr, *d_du = nullptr, *d_uval = nullptr, *d_F = nullptr, *d_P = nullptr, *d_A = nullptr;
+    int *d_status = nullptr, *d_iters = nullptr, *d_rightx = nullptr;
+    StepState* d_state = nullptr;
+    double *d_u = nullptr, *d_du = nullptr, *d_F = nullptr, *d_P = nullptr, *d_A = nullptr;
     double *d_w = nullptr, *d_ke = nullptr, *d_fe = nullptr, *d_K = nullptr, *d_R = nullptr, *d_norm = nullptr;
     double* d_Kt = nullptr;  // transposed copy of the band factor (blocked band solve)
     // surrogate replacement of micro solves
@@ -464,6 +541,10 @@ struct fehmm_s {
     double surr_rtol = 1e-4;
     float* d_ind = nullptr;
     int32_t *d_sidx = nullptr, *d_scnt = nullptr, *d_smask = nullptr;
+    // a whole load step captured as one graph (fehmm_set_graph)
+    bool graph_on = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     bool alive = true;
 };
 
@@ -475,9 +556,14 @@ struct fehmm_s {
 
 static void fehmm_free(fehmm_s* h) {
     int* ip[] = {h->d_conn, h->d_fixed, h->d_col[0], h->d_col[1], h->d_col[2], h->d_col[3], h->d_status,
-                 h->d_iters, h->d_flag};
+                 h->d_iters, h->d_rightx};
     for (int* p : ip) (void)hipFree(p);
-    double* dp[] = {h->d_Kt, h->d_u, h->d_du, h->d_uval, h->d_F, h->d_P, h->d_A, h->d_w, h->d_ke, h->d_fe, h->d_K,
+    (void)hipFree(h->d_state);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+    double* dp[] = {h->d_Kt, h->d_u, h->d_du, h->d_F, h->d_P, h->d_A, h->d_w, h->d_ke, h->d_fe, h->d_K,
                     h->d_R, h->d_norm};
     for (double* p : dp) (void)hipFree(p);
     (void)hipFree(h->d_ind);
@@ -589,6 +675,9 @@ int fehmm_create(const fehmm_desc* d, fehmm* out) {
     rve_batch_state_offsets(h->batch, off.data());
     h->state_doubles = off[h->nqp];
     FH_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    std::vector<int> rightx(h->ndof, 0);  // x dofs of the right edge (prescribed stretch)
+    for (int v = 0; v < h->nnode; ++v)
+        if (h->fixed[2 * v] && h->xy[2 * v] > 0.5 * d->Lx) rightx[2 * v] = 1;
     auto up = [&](auto** p, const auto& v) -> int {
         using T = typename std::remove_reference<decltype(v[0])>::type;
         FH_HIP(hipMalloc((void**)p, std::max<size_t>(v.size(), 1) * sizeof(T)));
@@ -604,7 +693,7 @@ int fehmm_create(const fehmm_desc* d, fehmm* out) {
     if ((st = up(&H->d_conn, H->conn)) || (st = up(&H->d_fixed, H->fixed)) || (st = up(&H->d_col[0], H->colour[0])) ||
         (st = up(&H->d_col[1], H->colour[1])) || (st = up(&H->d_col[2], H->colour[2])) ||
         (st = up(&H->d_col[3], H->colour[3])) || (st = zal(&H->d_u, H->ndof)) || (st = zal(&H->d_du, H->ndof)) ||
-        (st = zal(&H->d_uval, H->ndof)) || (st = zal(&H->d_F, 4 * (int64_t)H->nqp)) ||
+        (st = up(&H->d_rightx, rightx)) || (st = zal(&H->d_F, 4 * (int64_t)H->nqp)) ||
         (st = zal(&H->d_P, 4 * (int64_t)H->nqp)) || (st = zal(&H->d_A, 16 * (int64_t)H->nqp)) ||
         (st = zal(&H->d_w, H->state_doubles)) || (st = zal(&H->d_ke, 64 * (int64_t)H->nelem)) ||
         (st = zal(&H->d_fe, 8 * (int64_t)H->nelem)) || (st = zal(&H->d_K, (int64_t)H->ndof * (H->bw + 1))) ||
@@ -615,11 +704,12 @@ int fehmm_create(const fehmm_desc* d, fehmm* out) {
     }
     hipError_t e1 = hipMalloc((void**)&H->d_status, sizeof(int) * H->nqp);
     hipError_t e2 = hipMalloc((void**)&H->d_iters, sizeof(int) * H->nqp);
-    hipError_t e3 = hipMalloc((void**)&H->d_flag, 2 * sizeof(int));  // [0] band solve, [1] new fallbacks
+    hipError_t e3 = hipMalloc((void**)&H->d_state, sizeof(StepState));
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         fehmm_free(H);
         return set_error(RVE_ENOMEM, "fehmm_create: allocation failed");
     }
+    FH_HIP(hipMemset(H->d_state, 0, sizeof(StepState)));
     *out = h.release();
     return RVE_OK;
 }
@@ -639,6 +729,103 @@ int fehmm_sizes(fehmm h, int32_t* ndof, int32_t* nqp, int64_t* state_doubles) {
     return RVE_OK;
 }
 
+}  // extern "C"
+
+int rve_internal_solve(rve_batch b, const int32_t* subset, const int32_t* count, const double* F, double* P,
+                       double* A, double* w_state, int32_t* status, int32_t* iters, const rve_opts* opts,
+                       void* hip_stream, const int* skip);  // rve_abi.cpp
+extern "C" int rve_internal_surrogate_eval(rve_surrogate h, const double* F, double* P, double* A, float* indicator,
+                                           int64_t n, int32_t precision, void* hip_stream,
+                                           const int* skip);  // surrogate.hip
+
+// the kernels of one load step: its start, then macro Newton iterations
+// it_begin .. it_end - 1 (each a no-op once the step is done)
+static int enqueue_step(fehmm_s* h, int it_begin, int it_end, bool with_init) {
+    const fehmm_desc& d = h->desc;
+    hipStream_t s = h->stream;
+    StepState* st = h->d_state;
+    const int* done = &st->done;
+    if (with_init) {
+        hipLaunchKernelGGL(macro_step_init, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, st, h->d_u, h->d_fixed,
+                           h->d_rightx, (d.stretch - 1.0) * d.Lx / d.nsteps, h->ndof);
+        if (h->surr)  // a new load step starts with an empty fallback set
+            hipLaunchKernelGGL(macro_zero_ints, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_smask,
+                               (int64_t)h->nqp, (const int*)nullptr);
+    }
+    rve_opts mo = d.micro_opts;
+    const bool alt = d.scheme == FEHMM_ALTERNATING;
+    if (alt) {
+        mo.max_iter = 1;
+        mo.flags |= RVE_FLAG_OUTPUTS_AT_CAP;
+    }
+    // with the surrogate the stresses carry its FP32 rounding, so the macro
+    // Newton stops at surr_rtol, and only in an iteration whose indicator check
+    // (at the current state) added no fallback point
+    const double rtol = h->surr ? std::max(d.rtol_macro, h->surr_rtol) : d.rtol_macro;
+    for (int it = it_begin; it < it_end; ++it) {
+        hipLaunchKernelGGL(macro_gather_F, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_conn, h->nelem, h->d_u,
+                           h->geom, h->d_F, done);
+        if (h->surr) {
+            // surrogate answers where its indicator allows; the rest fall back to
+            // the RVE solve, listed on the device (no host round trip)
+            int e = rve_internal_surrogate_eval(h->surr, h->d_F, h->d_P, h->d_A, h->d_ind, h->nqp, h->surr_prec, s,
+                                                done);
+            if (e) return e;
+            hipLaunchKernelGGL(macro_merge_fallback, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_ind, h->d_smask,
+                               h->surr_thr, h->nqp, &st->grew, done);
+            e = rve_surrogate_select(h->d_ind, h->nqp, 0.5f, h->d_sidx, h->d_scnt, s);
+            if (e) return e;
+            hipLaunchKernelGGL(macro_zero_ints, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_status,
+                               (int64_t)h->nqp, done);
+            hipLaunchKernelGGL(macro_zero_ints, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_iters,
+                               (int64_t)h->nqp, done);
+            e = rve_internal_solve(h->batch, h->d_sidx, h->d_scnt, h->d_F, h->d_P, h->d_A, h->d_w, h->d_status,
+                                   h->d_iters, &mo, s, done);
+            if (e) return e;
+        } else {
+            int e = rve_internal_solve(h->batch, nullptr, nullptr, h->d_F, h->d_P, h->d_A, h->d_w, h->d_status,
+                                       h->d_iters, &mo, s, done);
+            if (e) return e;
+        }
+        hipLaunchKernelGGL(macro_element, dim3(nblk(8 * (int64_t)h->nelem, 256)), dim3(256), 0, s, h->nelem,
+                           h->d_P, h->d_A, h->geom, h->d_ke, h->d_fe, done);
+        const int64_t nK = (int64_t)h->ndof * (h->bw + 1);
+        hipLaunchKernelGGL(macro_zero, dim3(nblk(nK, 256)), dim3(256), 0, s, h->d_K, nK, done);
+        hipLaunchKernelGGL(macro_zero, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_R, (int64_t)h->ndof, done);
+        for (int c = 0; c < 4; ++c) {
+            const int nel = (int)h->colour[c].size();
+            if (nel == 0) continue;
+            hipLaunchKernelGGL(macro_scatter, dim3(nblk(8 * (int64_t)nel, 256)), dim3(256), 0, s, h->d_col[c], nel,
+                               h->d_conn, h->d_ke, h->d_fe, h->bw, h->d_K, h->d_R, done);
+        }
+        hipLaunchKernelGGL(macro_bc, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_fixed, h->ndof, h->bw, h->d_K,
+                           h->d_R, done);
+        hipLaunchKernelGGL(macro_norm_step, dim3(1), dim3(256), 0, s, h->d_R, h->ndof, h->d_status, h->d_iters,
+                           h->nqp, alt ? 1 : 0, h->surr ? (const int*)h->d_scnt : (const int*)nullptr, st, it, rtol,
+                           d.max_macro_iter);
+        const int slots = (kPanel + h->bw + 63) / 64;  // panel rows per lane
+        const size_t lds = band_lds_bytes(h->bw);
+        if (slots <= 2)
+            hipLaunchKernelGGL(macro_band_solve_blocked<2>, dim3(1), dim3(kBandNT), lds, s, h->d_K, h->d_Kt, h->d_R,
+                               h->ndof, h->bw, h->d_du, &st->band_flag, done);
+        else if (slots == 3)
+            hipLaunchKernelGGL(macro_band_solve_blocked<3>, dim3(1), dim3(kBandNT), lds, s, h->d_K, h->d_Kt, h->d_R,
+                               h->ndof, h->bw, h->d_du, &st->band_flag, done);
+        else if (slots == 4)
+            hipLaunchKernelGGL(macro_band_solve_blocked<4>, dim3(1), dim3(kBandNT), lds, s, h->d_K, h->d_Kt, h->d_R,
+                               h->ndof, h->bw, h->d_du, &st->band_flag, done);
+        else
+            hipLaunchKernelGGL(macro_band_solve, dim3(1), dim3(NTB), 0, s, h->d_K, h->d_R, h->ndof, h->bw, h->d_du,
+                               &st->band_flag, done);
+        hipLaunchKernelGGL(macro_update, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_u, h->d_du, h->d_fixed,
+                           h->ndof, done);
+    }
+    FH_HIP(hipGetLastError());
+    return RVE_OK;
+}
+
+extern "C" {
+
 int fehmm_macro_step(fehmm h, int32_t step, fehmm_step_info* info) {
     if (!h || !h->alive) return set_error(RVE_EINVAL, "fehmm_macro_step: invalid handle");
     const fehmm_desc& d = h->desc;
@@ -647,134 +834,73 @@ int fehmm_macro_step(fehmm h, int32_t step, fehmm_step_info* info) {
     fehmm_step_info* I = info ? info : &loc;
     std::memset(I, 0, sizeof(*I));
     hipStream_t s = h->stream;
-    // prescribed values of this step
-    std::vector<double> uval(h->ndof, 0.0);
-    const double ux = (d.stretch - 1.0) * d.Lx * (double)step / d.nsteps;
-    for (int v = 0; v < h->nnode; ++v)
-        if (h->fixed[2 * v] && h->xy[2 * v] > 0.5 * d.Lx) uval[2 * v] = ux;
-    FH_HIP(hipMemcpyAsync(h->d_uval, uval.data(), sizeof(double) * h->ndof, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(macro_dirichlet, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_u, h->d_fixed, h->d_uval,
-                       h->ndof);
-    if (h->surr) {
-        // a new load step starts with an empty fallback set
-        hipLaunchKernelGGL(macro_zero_ints, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_smask, (int64_t)h->nqp);
-        hipLaunchKernelGGL(macro_zero_int, dim3(1), dim3(64), 0, s, h->d_flag + 1, 1);
-    }
-    rve_opts mo = d.micro_opts;
-    const bool alt = d.scheme == FEHMM_ALTERNATING;
-    if (alt) {
-        mo.max_iter = 1;
-        mo.flags |= RVE_FLAG_OUTPUTS_AT_CAP;
-    }
-    double r0 = -1.0;
-    int it = 0;
-    int64_t micro = 0;
-    std::vector<int> hiters(h->nqp);
-    for (;;) {
-        hipLaunchKernelGGL(macro_gather_F, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_conn, h->nelem, h->d_u,
-                           h->geom, h->d_F);
-        if (h->surr) {
-            // surrogate answers where its indicator allows; the rest fall back to
-            // the RVE solve, listed on the device (no host round trip)
-            int st = rve_surrogate_eval(h->surr, h->d_F, h->d_P, h->d_A, h->d_ind, h->nqp, h->surr_prec, s);
-            if (st) return st;
-            hipLaunchKernelGGL(macro_merge_fallback, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_ind, h->d_smask,
-                               h->surr_thr, h->nqp, h->d_flag);
-            st = rve_surrogate_select(h->d_ind, h->nqp, 0.5f, h->d_sidx, h->d_scnt, s);
-            if (st) return st;
-            hipLaunchKernelGGL(macro_zero_ints, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_status,
-                               (int64_t)h->nqp);
-            hipLaunchKernelGGL(macro_zero_ints, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_iters,
-                               (int64_t)h->nqp);
-            st = rve_solve_batch_subset(h->batch, h->d_sidx, h->d_scnt, h->d_F, h->d_P, h->d_A, h->d_w, h->d_status,
-                                        h->d_iters, &mo, s);
-            if (st) return st;
-        } else {
-            int st = rve_solve_batch(h->batch, h->d_F, h->d_P, h->d_A, h->d_w, h->d_status, h->d_iters, &mo, s);
-            if (st) return st;
+    FH_HIP(hipMemcpyAsync(&h->d_state->step, &step, sizeof(int), hipMemcpyHostToDevice, s));
+    StepState hs{};
+    if (h->graph_on) {
+        // the whole load step (all max_macro_iter + 1 iterations, no-ops after
+        // convergence) as one graph, captured on first use
+        if (!h->gexec) {
+            FH_HIP(hipStreamSynchronize(s));
+            FH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            int e = enqueue_step(h, 0, d.max_macro_iter + 1, true);
+            hipGraph_t g = nullptr;
+            hipError_t ce = hipStreamEndCapture(s, &g);
+            if (e) {
+                if (g) (void)hipGraphDestroy(g);
+                return e;
+            }
+            if (ce != hipSuccess) return set_error(RVE_EHIP, std::string("fehmm_macro_step capture: ") +
+                                                                 hipGetErrorString(ce));
+            h->graph = g;
+            FH_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
         }
-        hipLaunchKernelGGL(macro_element, dim3(nblk(8 * (int64_t)h->nelem, 256)), dim3(256), 0, s, h->nelem,
-                           h->d_P, h->d_A, h->geom, h->d_ke, h->d_fe);
-        const int64_t nK = (int64_t)h->ndof * (h->bw + 1);
-        hipLaunchKernelGGL(macro_zero, dim3(nblk(nK, 256)), dim3(256), 0, s, h->d_K, nK);
-        hipLaunchKernelGGL(macro_zero, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_R, (int64_t)h->ndof);
-        for (int c = 0; c < 4; ++c) {
-            const int nel = (int)h->colour[c].size();
-            if (nel == 0) continue;
-            hipLaunchKernelGGL(macro_scatter, dim3(nblk(8 * (int64_t)nel, 256)), dim3(256), 0, s, h->d_col[c], nel,
-                               h->d_conn, h->d_ke, h->d_fe, h->bw, h->d_K, h->d_R);
-        }
-        hipLaunchKernelGGL(macro_bc, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_fixed, h->ndof, h->bw, h->d_K,
-                           h->d_R);
-        hipLaunchKernelGGL(macro_norm, dim3(1), dim3(256), 0, s, h->d_R, h->ndof, h->d_status, h->nqp, alt ? 1 : 0,
-                           h->d_norm);
-        double hn[2];
-        FH_HIP(hipMemcpyAsync(hn, h->d_norm, sizeof(hn), hipMemcpyDeviceToHost, s));
-        FH_HIP(hipMemcpyAsync(hiters.data(), h->d_iters, sizeof(int) * h->nqp, hipMemcpyDeviceToHost, s));
-        int32_t nfall = 0, grew[2] = {0, 0};
-        if (h->surr) {
-            FH_HIP(hipMemcpyAsync(&nfall, h->d_scnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            FH_HIP(hipMemcpyAsync(grew, h->d_flag, sizeof(grew), hipMemcpyDeviceToHost, s));
-        }
+        FH_HIP(hipGraphLaunch(h->gexec, s));
+        FH_HIP(hipMemcpyAsync(&hs, h->d_state, sizeof(hs), hipMemcpyDeviceToHost, s));
         FH_HIP(hipStreamSynchronize(s));
-        if (h->surr) {
-            I->fallback_points += nfall;
-            I->surrogate_points += h->nqp - nfall;
-            hipLaunchKernelGGL(macro_zero_int, dim3(1), dim3(64), 0, s, h->d_flag + 1, 1);
+    } else {
+        // eager: one host check of the device state per macro iteration
+        for (int it = 0; it <= d.max_macro_iter; ++it) {
+            int e = enqueue_step(h, it, it + 1, it == 0);
+            if (e) return e;
+            FH_HIP(hipMemcpyAsync(&hs, h->d_state, sizeof(hs), hipMemcpyDeviceToHost, s));
+            FH_HIP(hipStreamSynchronize(s));
+            if (hs.done) break;
         }
-        for (int q = 0; q < h->nqp; ++q) micro += hiters[q];
-        if (hn[1] > 0) {
-            I->status = FEHMM_STEP_RVE_FAILED;
-            I->failed_rves = (int)hn[1];
-            break;
-        }
-        const double rn = std::sqrt(hn[0]);
-        if (r0 < 0) r0 = rn;
-        I->res_hist[it] = r0 > 0 ? rn / r0 : 0.0;
-        // with the surrogate the stresses carry its FP32 rounding, so the macro
-        // Newton stops at surr_rtol, and only in an iteration whose indicator
-        // check (at the current state) added no fallback point
-        const double rtol = h->surr ? std::max(d.rtol_macro, h->surr_rtol) : d.rtol_macro;
-        if ((rn <= rtol * r0 || rn == 0.0) && !grew[1]) break;
-        if (it == d.max_macro_iter) {
-            I->status = FEHMM_STEP_NOCONV;
-            break;
-        }
-        hipLaunchKernelGGL(macro_zero_int, dim3(1), dim3(64), 0, s, h->d_flag, 1);
-        const int slots = (kPanel + h->bw + 63) / 64;  // panel rows per lane
-        const size_t lds = band_lds_bytes(h->bw);
-        if (slots <= 2)
-            hipLaunchKernelGGL(macro_band_solve_blocked<2>, dim3(1), dim3(kBandNT), lds, s, h->d_K, h->d_Kt, h->d_R,
-                               h->ndof, h->bw, h->d_du, h->d_flag);
-        else if (slots == 3)
-            hipLaunchKernelGGL(macro_band_solve_blocked<3>, dim3(1), dim3(kBandNT), lds, s, h->d_K, h->d_Kt, h->d_R,
-                               h->ndof, h->bw, h->d_du, h->d_flag);
-        else if (slots == 4)
-            hipLaunchKernelGGL(macro_band_solve_blocked<4>, dim3(1), dim3(kBandNT), lds, s, h->d_K, h->d_Kt, h->d_R,
-                               h->ndof, h->bw, h->d_du, h->d_flag);
-        else
-            hipLaunchKernelGGL(macro_band_solve, dim3(1), dim3(NTB), 0, s, h->d_K, h->d_R, h->ndof, h->bw, h->d_du,
-                               h->d_flag);
-        hipLaunchKernelGGL(macro_update, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_u, h->d_du, h->d_fixed,
-                           h->ndof);
-        ++it;
     }
-    I->macro_iters = it;
-    I->micro_iters = micro;
+    I->status = hs.status;
+    I->macro_iters = hs.it;
+    I->micro_iters = hs.micro;
+    I->failed_rves = hs.failed;
+    I->surrogate_points = hs.surrogate;
+    I->fallback_points = hs.fallback;
+    for (int k = 0; k <= hs.it && k < FEHMM_MAX_HIST; ++k) I->res_hist[k] = hs.hist[k];
     std::vector<double> u(h->ndof);
     FH_HIP(hipMemcpyAsync(u.data(), h->d_u, sizeof(double) * h->ndof, hipMemcpyDeviceToHost, s));
-    int flag = 0;
-    FH_HIP(hipMemcpyAsync(&flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     FH_HIP(hipStreamSynchronize(s));
     double um = 0.0;
     for (int v = 0; v < h->nnode; ++v) um = std::max(um, std::hypot(u[2 * v], u[2 * v + 1]));
     I->u_max = um;
-    if (flag && I->status == FEHMM_STEP_CONVERGED) I->status = FEHMM_STEP_NOCONV;
+    if (hs.band_flag && I->status == FEHMM_STEP_CONVERGED) I->status = FEHMM_STEP_NOCONV;
     return I->status == FEHMM_STEP_CONVERGED ? RVE_OK : RVE_EPARTIAL;
+}
+
+static void drop_graph(fehmm_s* h) {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+}
+
+int fehmm_set_graph(fehmm h, int32_t enable) {
+    if (!h || !h->alive) return set_error(RVE_EINVAL, "fehmm_set_graph: invalid handle");
+    h->graph_on = enable != 0;
+    if (!h->graph_on) drop_graph(h);
+    return RVE_OK;
 }
 
 int fehmm_set_surrogate(fehmm h, rve_surrogate sg, float threshold, int32_t precision, double macro_rtol) {
     if (!h || !h->alive) return set_error(RVE_EINVAL, "fehmm_set_surrogate: invalid handle");
+    drop_graph(h);  // the captured step embeds the old setting
     if (!sg) {
         h->surr = nullptr;
         return RVE_OK;

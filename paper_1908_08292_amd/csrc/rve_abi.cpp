@@ -144,6 +144,12 @@ int plan_device(PlanEntry* e) {
 
 int rve_internal_set_error(int code, const std::string& msg) { return fail(code, msg); }
 
+// rve_solve_batch(_subset) whose launch does nothing while *skip is set on the
+// device (the two-scale driver's graph-captured load steps)
+int rve_internal_solve(rve_batch b, const int32_t* subset, const int32_t* count, const double* F, double* P,
+                       double* A, double* w_state, int32_t* status, int32_t* iters, const rve_opts* opts,
+                       void* hip_stream, const int* skip);
+
 struct rve_mesh_s {
     int d = 0, n = 0, nphase = 0;
     std::vector<double> lame;
@@ -306,11 +312,28 @@ static void free_batch(rve_batch_s* b) {
     b->d_ws = nullptr;
 }
 
+// kernel attributes (dynamic LDS limits), set once per process before the first
+// launch -- at batch creation, so that no attribute call falls inside a graph
+// capture of a later solve
+static int ensure_prepared() {
+    static bool prepared = false;
+    if (!prepared) {
+        hipError_t pe = prepare_rve_solve();
+        if (pe != hipSuccess) return fail(RVE_EHIP, std::string("rve kernels: ") + hipGetErrorString(pe));
+        prepared = true;
+    }
+    return RVE_OK;
+}
+
 int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
     if (!meshes || !out || B <= 0) return fail(RVE_EINVAL, "rve_batch_create: invalid argument");
     *out = nullptr;
     for (int64_t r = 0; r < B; ++r)
         if (!meshes[r] || !meshes[r]->alive) return fail(RVE_EINVAL, "rve_batch_create: invalid mesh handle");
+    {
+        const int pst = ensure_prepared();
+        if (pst) return pst;
+    }
     const int d = meshes[0]->d;
     for (int64_t r = 0; r < B; ++r)
         if (meshes[r]->d != d) return fail(RVE_EUNSUPPORTED, "rve_batch_create: all meshes of a batch must share ndim");
@@ -438,7 +461,7 @@ int rve_batch_state_offsets(rve_batch b, int64_t* host_off) {
 
 static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* subset_count, const double* F,
                             double* P, double* A, double* w_state, int32_t* status, int32_t* iters,
-                            const rve_opts* opts, void* hip_stream) {
+                            const rve_opts* opts, void* hip_stream, const int* skip) {
     if (!b || !b->alive) return fail(RVE_EINVAL, "rve_solve_batch: invalid batch handle");
     if (!F || !P) return fail(RVE_EINVAL, "rve_solve_batch: F and P are required");
     rve_opts o;
@@ -448,12 +471,8 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
         return fail(RVE_EINVAL, "rve_solve_batch: options out of range");
     if (o.precision != RVE_PREC_FP64 && o.precision != RVE_PREC_FP32_IR)
         return fail(RVE_EINVAL, "rve_solve_batch: unknown precision");
-    static bool prepared = false;
-    if (!prepared) {
-        hipError_t pe = prepare_rve_solve();
-        if (pe != hipSuccess) return fail(RVE_EHIP, std::string("rve_solve_batch: ") + hipGetErrorString(pe));
-        prepared = true;
-    }
+    int pst = ensure_prepared();
+    if (pst) return pst;
     // FP32 factors apply to the 2D LDS-resident plans; other plans stay FP64
     const bool fp32 = o.precision == RVE_PREC_FP32_IR && b->d == 2;
     SolveArgs a{};
@@ -467,6 +486,7 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
     a.rve_atol = b->d_atol;
     a.order = subset ? subset : b->d_order;
     a.count_dev = subset ? subset_count : nullptr;
+    a.skip = skip;
     a.B = b->B;
     a.ws = b->d_ws;
     a.lay = b->lay;
@@ -501,14 +521,14 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
 
 int rve_solve_batch(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
                     int32_t* iters, const rve_opts* opts, void* hip_stream) {
-    return solve_batch_impl(b, nullptr, nullptr, F, P, A, w_state, status, iters, opts, hip_stream);
+    return solve_batch_impl(b, nullptr, nullptr, F, P, A, w_state, status, iters, opts, hip_stream, nullptr);
 }
 
 int rve_solve_batch_subset(rve_batch b, const int32_t* idx, const int32_t* count, const double* F, double* P,
                            double* A, double* w_state, int32_t* status, int32_t* iters, const rve_opts* opts,
                            void* hip_stream) {
     if (!idx || !count) return fail(RVE_EINVAL, "rve_solve_batch_subset: idx and count are required");
-    return solve_batch_impl(b, idx, count, F, P, A, w_state, status, iters, opts, hip_stream);
+    return solve_batch_impl(b, idx, count, F, P, A, w_state, status, iters, opts, hip_stream, nullptr);
 }
 
 int rve_solve_batch_sync(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
@@ -560,4 +580,10 @@ extern "C" int rve_plan_export(int32_t ndim, int32_t n, int64_t* sizes, int32_t*
             kcontrib[3 * q + 2] = P.kcontrib[q].lb;
         }
     return RVE_OK;
+}
+
+int rve_internal_solve(rve_batch b, const int32_t* subset, const int32_t* count, const double* F, double* P,
+                       double* A, double* w_state, int32_t* status, int32_t* iters, const rve_opts* opts,
+                       void* hip_stream, const int* skip) {
+    return solve_batch_impl(b, subset, count, F, P, A, w_state, status, iters, opts, hip_stream, skip);
 }

@@ -1110,6 +1110,7 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
                 a.count_dev ? (unsigned int)min((int64_t)max(*a.count_dev, 0), a.B) : (unsigned int)a.B;
             int r = -1;
             for (;;) {
+                if (a.skip && *a.skip) break;
                 const unsigned int idx = atomicAdd(a.counter, 1u);
                 if (idx >= nq) break;
                 const int cand = a.order[idx];
@@ -1180,7 +1181,7 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
         for (int t = threadIdx.x; t < ndof; t += NT) c.w[t] = (wst && t >= D) ? wst[t] : 0.0;
         __syncthreads();
         int status = 0, it = 0;
-        bool capped = false;
+        bool capped = false, restarted = false;
         if (!finite_in) status = 4;
         double r0 = 0.0;
         PROF_T0();
@@ -1189,7 +1190,20 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
             element_pass<D>(c, sm, c.w, 0, nullptr, nullptr);
             __syncthreads();
             PROF_MARK(PH_ELEM);
-            if (sm.flag) { status = 2; break; }
+            if (sm.flag) {
+                if (it == 0 && wst && !restarted) {
+                    // a stored fluctuation that folds an element under the new
+                    // Fbar is discarded: restart from w = 0 (J = det Fbar > 0)
+                    restarted = true;
+                    for (int t = threadIdx.x; t < ndof; t += NT) c.w[t] = 0.0;
+                    __syncthreads();
+                    if (threadIdx.x == 0) sm.flag = 0;
+                    __syncthreads();
+                    continue;
+                }
+                status = 2;
+                break;
+            }
             node_gather<D>(c, c.fe, 1, c.R, 1.0);
             __syncthreads();
             const double rn = sqrt(free_norm2<D>(c, sm, c.R));

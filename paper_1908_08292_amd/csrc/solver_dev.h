@@ -44,6 +44,7 @@ struct SolveArgs {
     const double* rve_atol;      // [B] default absolute tolerance
     const int32_t* order;        // [B] queue order (longest first), or a subset list
     const int32_t* count_dev;    // length of a subset list (device), or null for the whole batch
+    const int* skip;             // device flag: when set, the launch solves nothing (graph-captured steps)
     int64_t B;
     double* ws;
     SlotLayout lay;

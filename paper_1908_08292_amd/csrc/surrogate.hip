@@ -68,6 +68,7 @@ struct Args {
     double* A;
     float* ind;
     int64_t n;
+    const int* skip;        // device flag: when set, the launch does nothing
     const double* y0;       // [9] network outputs at the origin (Taylor terms)
     double* y0_out;         // when set: write the raw outputs of point 0 and stop
     const float* table;     // [GRID^3] indicator table or null
@@ -322,6 +323,7 @@ __global__ __launch_bounds__(NT, 1) void surr_tile_kernel(Args a) {
     __shared__ int valid[TP];
     __shared__ int64_t pid[TP];
 
+    if (MODE == MODE_EVAL && a.skip && *a.skip) return;
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, lr = l & 15, lg = l >> 4;
     const int64_t tile = blockIdx.x;
     // LDS: evaluation keeps one activation buffer (and its bf16 residual with
@@ -1027,8 +1029,19 @@ int rve_surrogate_get_params(rve_surrogate h, float* theta_host) {
     return RVE_OK;
 }
 
+int rve_internal_surrogate_eval(rve_surrogate h, const double* F, double* P, double* A, float* indicator, int64_t n,
+                                int32_t precision, void* hip_stream, const int* skip);
+
 int rve_surrogate_eval(rve_surrogate h, const double* F, double* P, double* A, float* indicator, int64_t n,
                        int32_t precision, void* hip_stream) {
+    return rve_internal_surrogate_eval(h, F, P, A, indicator, n, precision, hip_stream, nullptr);
+}
+
+}  // extern "C"
+
+// rve_surrogate_eval whose launch does nothing while *skip is set on the device
+int rve_internal_surrogate_eval(rve_surrogate h, const double* F, double* P, double* A, float* indicator, int64_t n,
+                                int32_t precision, void* hip_stream, const int* skip) {
     if (!h) return fail(RVE_EINVAL, "rve_surrogate_eval: NULL handle");
     if (n < 0 || n > (int64_t)TP * 0x7fffffff) return fail(RVE_EINVAL, "rve_surrogate_eval: bad n");
     if (n > 0 && (!F || !P)) return fail(RVE_EINVAL, "rve_surrogate_eval: F and P are required");
@@ -1042,6 +1055,7 @@ int rve_surrogate_eval(rve_surrogate h, const double* F, double* P, double* A, f
     a.ind = indicator;
     a.n = n;
     a.y0 = h->y0 + 9 * precision;
+    a.skip = skip;
     if (h->calibrated[precision]) {
         a.table = h->table + precision * GRID * GRID * GRID;
         for (int k = 0; k < 3; ++k) {
@@ -1051,6 +1065,8 @@ int rve_surrogate_eval(rve_surrogate h, const double* F, double* P, double* A, f
     }
     return launch_eval(h, a, (n + TP - 1) / TP, precision, (hipStream_t)hip_stream);
 }
+
+extern "C" {
 
 static int run_grad(rve_surrogate h, const double* F, const double* P, const double* A, const int32_t* idx,
                     int64_t count, const rve_train_opts& o, hipStream_t st) {

@@ -45,6 +45,7 @@ def lib():
         L.fehmm_get_state.argtypes = [vp, vp, vp]
         L.fehmm_set_state.argtypes = [vp, vp, vp]
         L.fehmm_set_surrogate.argtypes = [vp, vp, C.c_float, C.c_int32, C.c_double]
+        L.fehmm_set_graph.argtypes = [vp, C.c_int32]
         _setup_done = True
     return L
 
@@ -86,6 +87,10 @@ class Driver:
         rve.check(lib().fehmm_set_surrogate(self.h, surrogate.h if surrogate is not None else None,
                                             float(threshold), int(precision), float(macro_rtol)),
                   "fehmm_set_surrogate")
+
+    def set_graph(self, enable=True):
+        """Run each load step as one captured HIP graph (fehmm_set_graph)."""
+        rve.check(lib().fehmm_set_graph(self.h, 1 if enable else 0), "fehmm_set_graph")
 
     def u(self):
         out = np.zeros(self.ndof)

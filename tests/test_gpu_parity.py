@@ -178,3 +178,15 @@ def test_parity_fp32_ir_config1_sampled():
     assert np.all(out["status"] == 0), np.bincount(out["status"])
     idx = np.random.default_rng(2).choice(4096, 24, replace=False)
     compare_loose_iters(2, wl.n, wl.radius, wl.ratio, wl.F, out, idx=idx)
+
+
+def test_infeasible_warm_start_matches_oracle_cold_start():
+    """Warm starts that fold an element under the new Fbar are discarded on the
+    GPU as in the oracle: results and iteration counts equal the cold start."""
+    d, n, B = 2, 6, 8
+    F = workloads.draw_F(np.random.default_rng(31), B, d, 0.15)
+    w0 = np.zeros(B * d * n ** d)
+    for b in range(B):
+        w0[b * d * n ** d + 2 * 7] = 0.5  # node (1, 1) pushed past its right neighbours
+    out = run_gpu(d, np.full(B, n), np.full(B, 0.3), np.full(B, 10.0), F, w0=w0)
+    compare(d, np.full(B, n), np.full(B, 0.3), np.full(B, 10.0), F, out)

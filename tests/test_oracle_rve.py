@@ -304,3 +304,21 @@ def test_batch_equals_single():
         r = solve(d, n, phases[b], F[b])
         assert np.array_equal(out["P"][b], r["P"]) and np.array_equal(out["A"][b], r["A"])
         assert out["iters"][b] == r["iters"]
+
+
+def test_infeasible_warm_start_restarts_from_zero():
+    """A stored fluctuation that folds an element under the new Fbar is
+    discarded: the solve equals the cold start (the fluctuation field the
+    two-scale schemes carry between iterations is only a starting guess)."""
+    d, n = 2, 6
+    lame = oracle.two_phase_lame(10.0)
+    ph = oracle.phase_by_centroid(d, n, 0.3)
+    F = np.array([[1.1, 0.05], [-0.03, 0.95]])
+    w_bad = np.zeros(d * n ** d)
+    w_bad[2 * 7] = 0.5  # node (1, 1) pushed past its right neighbours
+    assert oracle.element(d, n, ph, lame, 1 + n * 1, F, w_bad)[0] == oracle.DETF
+    cold = oracle.rve_solve(d, n, ph, lame, F)
+    warm = oracle.rve_solve(d, n, ph, lame, F, w=w_bad)
+    assert cold["status"] == warm["status"] == oracle.OK
+    assert warm["iters"] == cold["iters"]
+    np.testing.assert_array_equal(warm["P"], cold["P"])
