@@ -156,6 +156,36 @@ int rve_solve_batch_subset(rve_batch b, const int32_t* idx, const int32_t* count
 int rve_solve_batch_sync(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
                          int32_t* iters, const rve_opts* opts, void* hip_stream);
 
+/* ---- autotuning -------------------------------------------------------------
+ * Choices that shape the solve of one mesh size: the leaf size of the nested
+ * dissection (largest leaf box, in nodes: front sizes and tree depth), the
+ * largest front that one wave factors on its own (small subtrees run
+ * wave-per-front, larger fronts use the whole workgroup), and the number of
+ * persistent workgroups of a batch.  rve_autotune times candidates on the
+ * caller's own deformation gradients and keeps the fastest for (ndim, n);
+ * meshes and batches created afterwards use it.  Results stay within the
+ * parity bar for any choice (only the elimination order changes). */
+typedef struct {
+    int32_t leaf;        /* 0: default (16 nodes in 2D, 27 in 3D) */
+    int32_t wave_max_m;  /* 0 .. 64; 64 is the default */
+    int32_t slots;       /* 0: default (min(B, 1024)) */
+    int32_t pad;
+    double ms;           /* measured time of the tuning batch (rve_autotune), else 0 */
+} rve_tuning;
+
+/* Times every candidate (leaf in {8, 16, 32} (2D) or {8, 27, 64} (3D), wave
+ * limit in {0, 32, 64} where fronts fit LDS, slots in {512, 1024}) with
+ * rve_solve_batch on nF RVEs of mesh m's microstructure driven by F (device,
+ * [nF][d^2]) and options o, keeps the fastest for (ndim, n) and returns it in
+ * best.  Host-blocking; allocates its own buffers. */
+int rve_autotune(rve_mesh m, const double* F, int64_t nF, const rve_opts* o, rve_tuning* best, void* hip_stream);
+/* Current choice for (ndim, n) (defaults when untuned); set installs one (e.g.
+ * saved from an earlier run); reset returns (ndim, n) -- or every size when
+ * n == 0 -- to the defaults.  Affect meshes and batches created afterwards. */
+int rve_tuning_get(int32_t ndim, int32_t n, rve_tuning* out);
+int rve_tuning_set(int32_t ndim, int32_t n, const rve_tuning* t);
+int rve_tuning_reset(int32_t ndim, int32_t n);
+
 /* Algorithmic work of the last plan for (ndim, n): floating-point operations of
  * one LDL^T factorization, nonzeros of L, front count and largest front. */
 int rve_plan_info(int32_t ndim, int32_t n, double* factor_flops, int64_t* nnz_L, int32_t* nfronts,

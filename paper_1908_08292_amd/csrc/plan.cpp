@@ -169,8 +169,10 @@ std::vector<std::vector<int>> postorder(const std::vector<std::vector<int>>& sup
 
 }  // namespace
 
-PlanHost build_plan(int d, int n) {
+PlanHost build_plan(int d, int n, const PlanParams& prm) {
     if (!(d == 2 || d == 3) || n < 2) throw std::runtime_error("unsupported mesh size");
+    if (prm.leaf < 0 || prm.wave_max_m < 0 || prm.wave_max_m > kWaveFrontMaxM)
+        throw std::runtime_error("plan parameters out of range");
     PlanHost P;
     P.d = d;
     P.n = n;
@@ -180,7 +182,7 @@ PlanHost build_plan(int d, int n) {
     P.nelem = nn;
     P.nfree = d * (nn - 1);
 
-    NDBuilder nd{d, n, d == 2 ? 16 : 27, {}};
+    NDBuilder nd{d, n, prm.leaf > 0 ? prm.leaf : (d == 2 ? 16 : 27), {}};
     Box root;
     for (int k = 0; k < 3; ++k) { root.lo[k] = 0; root.hi[k] = (k < d) ? n : 1; root.per[k] = k < d; }
     nd.rec(root);
@@ -374,7 +376,7 @@ PlanHost build_plan(int d, int n) {
         int maxh = 0;
         for (int s = 0; s < ns; ++s) {
             FrontHost& F = P.fronts[s];
-            F.wave = F.m <= kWaveFrontMaxM ? 1 : 0;
+            F.wave = F.m <= prm.wave_max_m ? 1 : 0;
             F.height = 0;
             for (int q = F.child_begin; q < F.child_end; ++q) {
                 const FrontHost& C = P.fronts[P.children[q]];

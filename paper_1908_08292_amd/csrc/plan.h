@@ -80,6 +80,12 @@ constexpr int64_t kLdsFrontBytes = 148 * 1024;
 constexpr int kWaveFrontMaxM = 64;
 
 // Builds the plan; throws std::runtime_error on unsupported (d, n).
-PlanHost build_plan(int d, int n);
+// structural parameters of a plan (the autotuner's plan-level knobs)
+struct PlanParams {
+    int leaf = 0;        // largest leaf box of the nested dissection (nodes); 0: 16 in 2D, 27 in 3D
+    int wave_max_m = kWaveFrontMaxM;  // largest front factored by one wave (0: none)
+};
+
+PlanHost build_plan(int d, int n, const PlanParams& prm = PlanParams{});
 
 }  // namespace fehmm

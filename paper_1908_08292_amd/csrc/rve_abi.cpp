@@ -10,6 +10,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/rve.h"
@@ -41,7 +42,10 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 // ---------------------------------------------------------------- plan cache
+using PlanKey = std::tuple<int, int, int, int>;  // d, n, leaf, wave_max_m
+
 struct PlanEntry {
+    PlanKey key;
     PlanHost host;
     DevPlan dev{};          // device pointers inside
     DevFront* d_fronts = nullptr;
@@ -63,7 +67,25 @@ struct PlanEntry {
 };
 
 std::mutex g_mu;
-std::map<std::pair<int, int>, std::unique_ptr<PlanEntry>> g_plans;
+std::map<PlanKey, std::unique_ptr<PlanEntry>> g_plans;
+// tuned choices per (d, n): plan parameters and persistent workgroups
+std::map<std::pair<int, int>, rve_tuning> g_tuning;
+
+PlanParams params_for(int d, int n) {
+    PlanParams p;
+    auto it = g_tuning.find(std::make_pair(d, n));
+    if (it != g_tuning.end()) {
+        p.leaf = it->second.leaf;
+        p.wave_max_m = it->second.wave_max_m;
+    }
+    return p;
+}
+
+int tuned_slots(int d, int n) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tuning.find(std::make_pair(d, n));
+    return it != g_tuning.end() ? it->second.slots : 0;
+}
 
 template <typename T>
 int upload(const std::vector<T>& v, T** out) {
@@ -81,17 +103,20 @@ void free_plan_dev(PlanEntry& e) {
     e.d_fronts = nullptr;
 }
 
+// the plan of (d, n) under the current tuning (default parameters if untuned)
 int get_plan(int d, int n, PlanEntry** out) {
     std::lock_guard<std::mutex> lk(g_mu);
-    auto key = std::make_pair(d, n);
+    const PlanParams prm = params_for(d, n);
+    const PlanKey key(d, n, prm.leaf, prm.wave_max_m);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         *out = it->second.get();
         return RVE_OK;
     }
     auto e = std::make_unique<PlanEntry>();
+    e->key = key;
     try {
-        e->host = build_plan(d, n);
+        e->host = build_plan(d, n, prm);
     } catch (const std::exception& ex) {
         return fail(RVE_EINVAL, std::string("plan: ") + ex.what());
     }
@@ -290,7 +315,7 @@ int rve_mesh_destroy(rve_mesh m) {
         std::lock_guard<std::mutex> lk(g_mu);
         if (--m->plan->refs == 0) {
             free_plan_dev(*m->plan);
-            g_plans.erase(std::make_pair(m->d, m->n));
+            g_plans.erase(m->plan->key);
         }
     }
     // the husk stays allocated so that a second destroy is detected
@@ -422,7 +447,8 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
     HIP_OR(hipMemGetInfo(&free_b, &total_b));
     const double slot_bytes = (double)L.stride * sizeof(double);
     int64_t cap = (int64_t)(0.5 * (double)free_b / slot_bytes);
-    int64_t nslots = std::min<int64_t>({B, (int64_t)1024, cap});
+    const int tslots = tuned_slots(d, meshes[0]->n);
+    int64_t nslots = std::min<int64_t>({B, tslots > 0 ? (int64_t)tslots : (int64_t)1024, cap});
     if (nslots < 1) return fail(RVE_ENOMEM, "rve_batch_create: not enough device memory for one workspace slot");
     b->nslots = (int)nslots;
     std::vector<DevPlan> dplans;
@@ -587,3 +613,130 @@ int rve_internal_solve(rve_batch b, const int32_t* subset, const int32_t* count,
                        void* hip_stream, const int* skip) {
     return solve_batch_impl(b, subset, count, F, P, A, w_state, status, iters, opts, hip_stream, skip);
 }
+
+extern "C" {
+
+int rve_tuning_get(int32_t ndim, int32_t n, rve_tuning* out) {
+    if (!out || !(ndim == 2 || ndim == 3) || n < 2) return fail(RVE_EINVAL, "rve_tuning_get: invalid argument");
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tuning.find(std::make_pair((int)ndim, (int)n));
+    if (it != g_tuning.end()) {
+        *out = it->second;
+    } else {
+        *out = rve_tuning{0, kWaveFrontMaxM, 0, 0, 0.0};
+    }
+    return RVE_OK;
+}
+
+int rve_tuning_set(int32_t ndim, int32_t n, const rve_tuning* t) {
+    if (!t || !(ndim == 2 || ndim == 3) || n < 2) return fail(RVE_EINVAL, "rve_tuning_set: invalid argument");
+    if (t->leaf < 0 || t->leaf > 4096 || t->wave_max_m < 0 || t->wave_max_m > kWaveFrontMaxM || t->slots < 0 ||
+        t->slots > 65536)
+        return fail(RVE_EINVAL, "rve_tuning_set: value out of range");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuning[std::make_pair((int)ndim, (int)n)] = *t;
+    return RVE_OK;
+}
+
+int rve_tuning_reset(int32_t ndim, int32_t n) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (n == 0) {
+        g_tuning.clear();
+    } else {
+        g_tuning.erase(std::make_pair((int)ndim, (int)n));
+    }
+    return RVE_OK;
+}
+
+int rve_autotune(rve_mesh m, const double* F, int64_t nF, const rve_opts* o, rve_tuning* best, void* hip_stream) {
+    if (!m || !m->alive || !F || nF < 1 || !best) return fail(RVE_EINVAL, "rve_autotune: invalid argument");
+    const int d = m->d, n = m->n, d2 = d * d;
+    hipStream_t st = (hipStream_t)hip_stream;
+    rve_tuning saved{};
+    bool had = false;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_tuning.find(std::make_pair(d, n));
+        if (it != g_tuning.end()) {
+            saved = it->second;
+            had = true;
+        }
+    }
+    const std::vector<int> leaves = d == 2 ? std::vector<int>{8, 16, 32} : std::vector<int>{8, 27, 64};
+    const std::vector<int> waves = {0, 32, 64};
+    const std::vector<int> slots = {512, 1024};
+    double *P = nullptr, *A = nullptr;
+    int32_t* status = nullptr;
+    HIP_OR(hipMalloc((void**)&P, sizeof(double) * d2 * nF));
+    HIP_OR(hipMalloc((void**)&A, sizeof(double) * d2 * d2 * nF));
+    HIP_OR(hipMalloc((void**)&status, sizeof(int32_t) * nF));
+    hipEvent_t e0, e1;
+    HIP_OR(hipEventCreate(&e0));
+    HIP_OR(hipEventCreate(&e1));
+    rve_tuning win{0, kWaveFrontMaxM, 0, 0, 1e300};
+    int err = RVE_OK;
+    for (int leaf : leaves) {
+        // the wave limit matters only where whole fronts fit LDS
+        bool lds = false;
+        try {
+            PlanParams pp;
+            pp.leaf = leaf;
+            lds = build_plan(d, n, pp).lds_path;
+        } catch (const std::exception& ex) {
+            err = fail(RVE_EINVAL, std::string("rve_autotune: ") + ex.what());
+            break;
+        }
+        for (int wave : waves) {
+            if (!lds && wave != kWaveFrontMaxM) continue;
+            for (int sl : slots) {
+                rve_tuning cand{leaf, wave, sl, 0, 0.0};
+                if ((err = rve_tuning_set(d, n, &cand))) break;
+                rve_mesh_desc md{};
+                md.ndim = d;
+                md.n = n;
+                md.nphase = m->nphase;
+                md.lame = m->lame.data();
+                md.phase = m->phase.data();
+                rve_mesh cm = nullptr;
+                if ((err = rve_mesh_create(&md, &cm))) break;
+                std::vector<rve_mesh> ms((size_t)nF, cm);
+                rve_batch cb = nullptr;
+                if ((err = rve_batch_create(ms.data(), nF, &cb))) {
+                    rve_mesh_destroy(cm);
+                    break;
+                }
+                float ms_best = 1e30f;
+                for (int rep = 0; rep < 2 && !err; ++rep) {  // first run warms up
+                    (void)hipEventRecord(e0, st);
+                    err = rve_solve_batch(cb, F, P, A, nullptr, status, nullptr, o, hip_stream);
+                    (void)hipEventRecord(e1, st);
+                    if (hipEventSynchronize(e1) != hipSuccess) err = fail(RVE_EHIP, "rve_autotune: solve failed");
+                    float t = 0.f;
+                    (void)hipEventElapsedTime(&t, e0, e1);
+                    if (rep == 1) ms_best = t;
+                }
+                rve_batch_destroy(cb);
+                rve_mesh_destroy(cm);
+                if (err) break;
+                if (ms_best < win.ms) win = rve_tuning{leaf, wave, sl, 0, (double)ms_best};
+            }
+            if (err) break;
+        }
+        if (err) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(P);
+    (void)hipFree(A);
+    (void)hipFree(status);
+    if (err) {
+        if (had) rve_tuning_set(d, n, &saved);
+        else rve_tuning_reset(d, n);
+        return err;
+    }
+    rve_tuning_set(d, n, &win);
+    *best = win;
+    return RVE_OK;
+}
+
+}  // extern "C"

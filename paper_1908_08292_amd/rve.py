@@ -37,6 +37,11 @@ class Opts(C.Structure):
                 ("det_backtrack", C.c_int32), ("flags", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("leaf", C.c_int32), ("wave_max_m", C.c_int32), ("slots", C.c_int32), ("pad", C.c_int32),
+                ("ms", C.c_double)]
+
+
 _lib = None
 
 
@@ -68,6 +73,10 @@ def lib():
         L.rve_strerror.argtypes = [C.c_int]
         L.rve_strerror.restype = C.c_char_p
         L.rve_last_error.argtypes = [C.c_char_p, C.c_size_t]
+        L.rve_autotune.argtypes = [vp, vp, i64, C.POINTER(Opts), C.POINTER(Tuning), vp]
+        L.rve_tuning_get.argtypes = [i32, i32, C.POINTER(Tuning)]
+        L.rve_tuning_set.argtypes = [i32, i32, C.POINTER(Tuning)]
+        L.rve_tuning_reset.argtypes = [i32, i32]
         _lib = L
     return _lib
 
@@ -108,6 +117,39 @@ def lame(E, nu):
 
 def two_phase_lame(ratio, E=1.0, nu=0.3):
     return np.array([lame(E, nu), lame(ratio * E, nu)], dtype=np.float64)
+
+
+def _tuning_dict(t):
+    return dict(leaf=t.leaf, wave_max_m=t.wave_max_m, slots=t.slots, ms=t.ms)
+
+
+def tuning_get(d, n):
+    t = Tuning()
+    check(lib().rve_tuning_get(d, n, C.byref(t)), "rve_tuning_get")
+    return _tuning_dict(t)
+
+
+def tuning_set(d, n, leaf=0, wave_max_m=64, slots=0):
+    t = Tuning(leaf, wave_max_m, slots, 0, 0.0)
+    check(lib().rve_tuning_set(d, n, C.byref(t)), "rve_tuning_set")
+
+
+def tuning_reset(d=0, n=0):
+    check(lib().rve_tuning_reset(d, n), "rve_tuning_reset")
+
+
+def autotune(mesh, F, opts=None, stream=None):
+    """Times the candidate plans / launch shapes on F (device float64 [nF, d^2])
+    and keeps the fastest for (mesh.d, mesh.n); returns the choice."""
+    import torch
+    if not isinstance(F, torch.Tensor) or not F.is_cuda or F.dtype != torch.float64 or not F.is_contiguous():
+        raise ValueError("F: expected a contiguous float64 GPU tensor")
+    nF = F.numel() // (mesh.d * mesh.d)
+    t = Tuning()
+    o = opts if opts is not None else default_opts()
+    check(lib().rve_autotune(mesh.h, _ptr(F), nF, C.byref(o), C.byref(t), C.c_void_p(stream) if stream else None),
+          "rve_autotune")
+    return _tuning_dict(t)
 
 
 def plan_info(d, n):

@@ -181,3 +181,39 @@ def test_surrogate_symbols_and_validation():
         S.Surrogate(bad)
     assert L.rve_surrogate_select(None, 10, 1e-3, None, None, None) == rve.RVE_EINVAL
     assert L.rve_surrogate_eval(None, None, None, None, None, 0, 1, None) == rve.RVE_EINVAL
+
+
+@pytest.mark.parametrize("d,n,leaf,wave", [(2, 8, 4, 64), (2, 16, 8, 32), (2, 16, 32, 0), (3, 4, 8, 64),
+                                            (3, 5, 64, 0)])
+def test_tuned_plans_drive_a_correct_multifrontal_solve(d, n, leaf, wave):
+    """Every plan the autotuner can choose (other leaf sizes of the dissection,
+    other wave-per-front limits) still eliminates the periodic system exactly."""
+    rve.tuning_set(d, n, leaf=leaf, wave_max_m=wave, slots=0)
+    try:
+        assert rve.tuning_get(d, n)["leaf"] == leaf
+        rng = np.random.default_rng(d * 1000 + n + leaf)
+        lame_tab = oracle.two_phase_lame(10.0)
+        phase = rng.integers(0, 2, n ** d).astype(np.uint8)
+        F = np.eye(d) + rng.uniform(-0.1, 0.1, (d, d))
+        w = rng.uniform(-0.02, 0.02, d * n ** d) / n
+        ke = [oracle.element(d, n, phase, lame_tab, e, F, w)[2] for e in range(n ** d)]
+        st, Rf, K, dw = oracle.debug_system(d, n, phase, lame_tab, F, w)
+        b = np.zeros(d * n ** d)
+        b[d:] = rng.normal(size=K.shape[0])
+        plan = rve.plan_export(d, n)
+        x = simulate_multifrontal(plan, d, n, ke, b)
+        ref = np.linalg.solve(K, b[d:])
+        assert np.abs(x[d:] - ref).max() < 1e-9 * np.abs(ref).max()
+    finally:
+        rve.tuning_reset(d, n)
+    assert rve.tuning_get(d, n) == dict(leaf=0, wave_max_m=64, slots=0, ms=0.0)
+
+
+def test_tuning_validation():
+    with pytest.raises(rve.RveError):
+        rve.tuning_set(2, 8, leaf=-1)
+    with pytest.raises(rve.RveError):
+        rve.tuning_set(2, 8, wave_max_m=65)
+    with pytest.raises(rve.RveError):
+        rve.tuning_get(4, 8)
+    assert "rve_autotune" in rve.declared_functions()

@@ -190,3 +190,22 @@ def test_infeasible_warm_start_matches_oracle_cold_start():
         w0[b * d * n ** d + 2 * 7] = 0.5  # node (1, 1) pushed past its right neighbours
     out = run_gpu(d, np.full(B, n), np.full(B, 0.3), np.full(B, 10.0), F, w0=w0)
     compare(d, np.full(B, n), np.full(B, 0.3), np.full(B, 10.0), F, out)
+
+
+def test_autotuned_plan_matches_oracle():
+    """The autotuner picks among plans and launch shapes; a batch built after it
+    still meets the parity bar with equal Newton iteration counts."""
+    torch = torch_cuda()
+    d, n, B = 2, 8, 256
+    F = workloads.draw_F(np.random.default_rng(41), B, d, 0.15)
+    mesh = rve.Mesh(d, n, rve.two_phase_lame(10.0), radius=0.25)
+    t = rve.autotune(mesh, torch.tensor(F.reshape(-1), device="cuda"))
+    try:
+        print("tuned:", t)
+        assert t["leaf"] in (8, 16, 32) and t["wave_max_m"] in (0, 32, 64) and t["slots"] in (512, 1024)
+        assert t["ms"] > 0
+        assert rve.tuning_get(d, n)["leaf"] == t["leaf"]
+        out = run_gpu(d, np.full(B, n), np.full(B, 0.25), np.full(B, 10.0), F)
+        compare(d, np.full(B, n), np.full(B, 0.25), np.full(B, 10.0), F, out, idx=range(0, B, 8))
+    finally:
+        rve.tuning_reset(d, n)
