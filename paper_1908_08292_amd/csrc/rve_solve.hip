@@ -849,6 +849,50 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* r
     }
 }
 
+// backward substitution of one small front (m <= 64) by one wave, lane j =
+// pivot j: the packed panel is staged in the wave's LDS slice S, the update
+// rows' solution values are loaded one per lane and broadcast by readlane, and
+// the pivot triangle is swept from the last pivot (no barrier)
+template <int D, int NRHS, typename T>
+__device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
+    const DevPlan& pl = *c.plan;
+    const int lane = threadIdx.x & 63;
+    const DevFront fr = pl.fronts[s];
+    const int m = fr.m, p = fr.p, mu = m - p;
+    const int32_t* rows = pl.rows + fr.rows_off;
+    const T* Lg = reinterpret_cast<const T*>(c.L + fr.L_off);
+    const double* Dg = c.L + fr.D_off;
+    const double* yg = c.L + fr.y_off;
+    const int lp = cpk(p, m);
+#pragma unroll 8
+    for (int t = lane; t < lp; t += 64) S[t] = Lg[t];
+    double v[NRHS], xs[NRHS];
+#pragma unroll
+    for (int q = 0; q < NRHS; ++q) {
+        v[q] = (lane < p) ? yg[(int64_t)q * p + lane] / Dg[lane] : 0.0;
+        xs[q] = (lane < mu) ? x[(int64_t)rows[p + lane] * NRHS + q] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // column `lane` of the panel is S[cj + i], i >= lane; lanes >= p read column 0
+    // (in bounds: p + i < m <= cpk(p, m)) and discard the value
+    const int jl = lane < p ? lane : 0;
+    const int cj = cpk(jl, m) - jl;
+    for (int i = 0; i < mu; ++i) {
+        const double l = (lane < p) ? (double)S[cj + p + i] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) v[q] -= l * readlane_d(xs[q], i);
+    }
+    for (int jj = p - 1; jj > 0; --jj) {
+        const double l = (lane < jj) ? (double)S[cj + jj] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) v[q] -= l * readlane_d(v[q], jj);
+    }
+    if (lane < p)
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) x[(int64_t)rows[lane] * NRHS + q] = v[q];
+    __builtin_amdgcn_wave_barrier();
+}
+
 // backward substitution L^T x = D^-1 y with NRHS columns; y is each front's
 // stored forward-substituted rhs, x (node-major [dof][NRHS], FP64) receives the
 // solution.  FP64 panels are staged in LDS; FP32 panels are read from global
@@ -856,13 +900,17 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* r
 // the last: the block triangle is solved in registers of wave 0 (readlane
 // chain), then all threads fold the block into the remaining pivots.
 template <int D, int NRHS, typename T>
-__device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* rl, double* x, int front_elems) {
+__device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* rl, double* x, int front_elems,
+                                         int wave_slice) {
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int NPART = (NRHS == 1) ? 3 : 1;
     for (int t = tid; t < D * NRHS; t += NT) x[t] = 0.0;  // pinned node
+    // large fronts (the top of the tree) with the whole workgroup, then the
+    // small subtrees wave by wave
     for (int s = pl.nfront - 1; s >= 0; --s) {
         const DevFront fr = pl.fronts[s];
+        if (fr.wave) continue;
         const int m = fr.m, p = fr.p;
         const int32_t* rows = pl.rows + fr.rows_off;
         const T* Lg = reinterpret_cast<const T*>(c.L + fr.L_off);
@@ -967,6 +1015,13 @@ __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* r
             const int j = t % p, q = t / p;
             x[(int64_t)rows[j] * NRHS + q] = v[t];
         }
+        __syncthreads();
+    }
+    // small subtrees: one front per wave, parents (greater height) first
+    for (int h = pl.nwave_h - 1; h >= 0; --h) {
+        T* S = F + (int64_t)wave * wave_slice;
+        for (int k = pl.wave_hbeg[h] + wave; k < pl.wave_hbeg[h + 1]; k += NWAVE)
+            backsolve_wave_front<D, NRHS, T>(c, pl.wave_list[k], S, x);
         __syncthreads();
     }
 }
@@ -1222,7 +1277,7 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
             else factorize_glb<D>(c, sm, 1);
             if (sm.flag) { status = 3; break; }
             PROF_RESET();
-            if (c.plan->lds_ok) backsolve_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, c.x, a.lds_front);
+            if (c.plan->lds_ok) backsolve_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, c.x, a.lds_front, a.wave_slice);
             else backsolve_glb<D>(c, sm);
             PROF_MARK(PH_BACK);
             if constexpr (IR) {
@@ -1234,7 +1289,7 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
                         const double rl2 = sqrt(free_norm2<D>(c, sm, ir1));
                         if (!(rl2 > a.ir_eta * rn)) break;
                         forward_lds<D, 1, T>(c, sm, dynF, ir1, a.lds_front);
-                        backsolve_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front);
+                        backsolve_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front, a.wave_slice);
                         for (int t = threadIdx.x; t < ndof; t += NT) c.x[t] += ir2[t];
                         __syncthreads();
                     }
@@ -1292,13 +1347,13 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
                     //   Abar = <A> - Y^T X - X^T r,  r = Y - K X,
                     // whose error is (X - X*)^T K (X - X*) (energy-norm error squared)
                     double* X = c.re;  // element Y no longer needed: [dof][D2]
-                    backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front);
+                    backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front, a.wave_slice);
                     for (int ref = 0;; ++ref) {
                         residual_ke<D, D2>(c, c.rhs, X, ir1);
                         __syncthreads();
                         if (ref == a.ir_max_tan) break;
                         forward_lds<D, D2, T>(c, sm, dynF, ir1, a.lds_front);
-                        backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front);
+                        backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front, a.wave_slice);
                         for (int t = threadIdx.x; t < ndof * D2; t += NT) X[t] += ir2[t];
                         __syncthreads();
                     }
