@@ -86,11 +86,12 @@ def kernel_source_hash():
     return hashlib.sha256(blob).hexdigest()[:16]
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, precision="fp64"):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary of this workload, scaled by the copy-kernel calibration; None when
     the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"rve_solve_kernel_{workload}.hbm.json")
+    tag = "" if precision == "fp64" else "_" + precision
+    path = os.path.join(ROOT, "profiles", f"rve_solve_kernel_{workload}{tag}.hbm.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -342,8 +343,9 @@ def main():
         "config": {"workload": meta["workload"], "rves": B, "dim": d, "elements_per_edge": meta["n"],
                    "precision": head, "newton_rtol": 1e-10,
                    "mean_newton_iters": float(res["iters"].mean()), "failed_rves": timed[head]["nbad"]},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(meta["workload"]),
+        "roofline": {"bound": "mfma" if head == "fp64" else "valu", "achieved": achieved,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(meta["workload"], head),
                      "kernel": f"rve_solve_kernel<{d}>", "flops_per_launch": flops,
                      "flops_counted": "LDL^T factorizations + triangular solves from the symbolic plan"},
     }
@@ -351,6 +353,7 @@ def main():
         t = timed["fp32ir"]
         out["mixed_precision"] = dict(value=B / (t["ms"] * 1e-3), unit="RVE solves/s", ms_per_step=t["ms"],
                                       speedup_vs_fp64=ms / t["ms"], failed_rves=t["nbad"],
+                                      traffic=measured_traffic(meta["workload"], "fp32ir"),
                                       mean_newton_iters=float(t["res"]["iters"].mean()),
                                       dtype="f32 factors (LDL^T, solves) + f64 residuals, refinement, "
                                             "norms, averages and condensation")
