@@ -677,7 +677,20 @@ __global__ __launch_bounds__(NT, 1) void surr_tile_kernel(Args a) {
     }
 }
 
-// sum of the tile slots; gradient = sum * inv_n; optional Adam update
+// first pass of the slot reduction: chunk c sums tiles c, c + nchunk, ...
+// (deterministic order) into chunk_sum[c][i]
+constexpr int kReduceChunks = 8;
+__global__ void reduce_chunks_kernel(const float* __restrict__ partial, int64_t ntiles, float* __restrict__ chunk_sum) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i > NPARAM) return;
+    float s = 0.f;
+#pragma unroll 4
+    for (int64_t t = c; t < ntiles; t += kReduceChunks) s += partial[t * (NPARAM + 1) + i];
+    chunk_sum[(int64_t)c * (NPARAM + 1) + i] = s;
+}
+
+// sum of the chunk sums; gradient = sum * inv_n; optional Adam update
 __global__ void reduce_adam_kernel(const float* __restrict__ partial, int64_t ntiles, float inv_n, float* theta, float* m,
                                    float* v, float* grad_out, float* loss_out, int do_adam, float lr, float b1, float b2,
                                    float eps, float bc1, float bc2) {
@@ -784,6 +797,7 @@ struct rve_surrogate_s {
     int32_t* idx = nullptr;
     int64_t idx_cap = 0;
     float* grad = nullptr;
+    float* chunk = nullptr;  // [kReduceChunks][NPARAM + 1] first-pass sums
     float* loss = nullptr;
     int64_t loss_cap = 0;
 };
@@ -895,6 +909,17 @@ int ensure_train_scratch(rve_surrogate h, int64_t tiles, int64_t nidx, int64_t n
     return RVE_OK;
 }
 
+// tile slots -> gradient (mean) -> optional Adam, in two deterministic passes
+int reduce_slots(rve_surrogate h, int64_t tiles, float inv_n, float* grad_out, float* loss_out, int do_adam, float lr,
+                 const rve_train_opts& o, float bc1, float bc2, hipStream_t st) {
+    const unsigned nb = (NPARAM + 1 + NT - 1) / NT;
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(nb, kReduceChunks), dim3(NT), 0, st, h->partial, tiles, h->chunk);
+    hipLaunchKernelGGL(reduce_adam_kernel, dim3(nb), dim3(NT), 0, st, h->chunk, (int64_t)std::min<int64_t>(tiles, kReduceChunks),
+                       inv_n, h->theta, h->m, h->v, grad_out, loss_out, do_adam, lr, o.beta1, o.beta2, o.eps, bc1, bc2);
+    SHIP(hipGetLastError());
+    return RVE_OK;
+}
+
 int check_train_opts(const rve_train_opts& o) {
     if (o.steps < 0 || o.batch < 1 || !(o.lr > 0) || !(o.lr_final > 0) || !(o.beta1 >= 0 && o.beta1 < 1) ||
         !(o.beta2 >= 0 && o.beta2 < 1) || !(o.eps > 0) || !(o.wP >= 0) || !(o.wA >= 0) || !(o.rhoP >= 0) ||
@@ -963,7 +988,8 @@ int rve_surrogate_create(const rve_surrogate_desc* d, rve_surrogate* out) {
         (he = hipMalloc((void**)&h->y0, sizeof(double) * 18)) != hipSuccess ||
         (he = hipMalloc((void**)&h->f_id, sizeof(double) * 4)) != hipSuccess ||
         (he = hipMalloc((void**)&h->table, sizeof(float) * 2 * GRID * GRID * GRID)) != hipSuccess ||
-        (he = hipMalloc((void**)&h->grad, sizeof(float) * NPARAM)) != hipSuccess) {
+        (he = hipMalloc((void**)&h->grad, sizeof(float) * NPARAM)) != hipSuccess ||
+        (he = hipMalloc((void**)&h->chunk, sizeof(float) * kReduceChunks * (NPARAM + 1))) != hipSuccess) {
         rve_surrogate_destroy(h);
         return fail(RVE_ENOMEM, std::string("rve_surrogate_create: ") + hipGetErrorString(he));
     }
@@ -997,6 +1023,7 @@ int rve_surrogate_destroy(rve_surrogate h) {
     (void)hipFree(h->f_id);
     (void)hipFree(h->table);
     (void)hipFree(h->grad);
+    (void)hipFree(h->chunk);
     (void)hipFree(h->partial);
     (void)hipFree(h->zsave);
     (void)hipFree(h->idx);
@@ -1111,9 +1138,8 @@ int rve_surrogate_loss_grad(rve_surrogate h, const double* F, const double* P, c
     SHIP(hipMemcpyAsync(h->idx, id.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
     e = run_grad(h, F, P, A, h->idx, n, o, st);
     if (e) return e;
-    hipLaunchKernelGGL(reduce_adam_kernel, dim3((NPARAM + 1 + NT - 1) / NT), dim3(NT), 0, st, h->partial, tiles,
-                       (float)(1.0 / n), h->theta, h->m, h->v, grad_dev, h->loss, 0, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f);
-    SHIP(hipGetLastError());
+    e = reduce_slots(h, tiles, (float)(1.0 / n), grad_dev, h->loss, 0, 0.f, o, 1.f, 1.f, st);
+    if (e) return e;
     float L = 0.f;
     SHIP(hipMemcpyAsync(&L, h->loss, sizeof(float), hipMemcpyDeviceToHost, st));
     SHIP(hipStreamSynchronize(st));
@@ -1182,10 +1208,8 @@ int rve_surrogate_train(rve_surrogate h, const double* F, const double* P, const
         const double lr = o.lr * std::pow(ratio, o.steps > 1 ? (double)s / (o.steps - 1) : 0.0);
         const float bc1 = (float)(1.0 - std::pow((double)o.beta1, (double)h->t));
         const float bc2 = (float)(1.0 - std::pow((double)o.beta2, (double)h->t));
-        hipLaunchKernelGGL(reduce_adam_kernel, dim3((NPARAM + 1 + NT - 1) / NT), dim3(NT), 0, st, h->partial, tiles,
-                           (float)(1.0 / batch), h->theta, h->m, h->v, (float*)nullptr, h->loss + s, 1, (float)lr,
-                           o.beta1, o.beta2, o.eps, bc1, bc2);
-        SHIP(hipGetLastError());
+        e = reduce_slots(h, tiles, (float)(1.0 / batch), nullptr, h->loss + s, 1, (float)lr, o, bc1, bc2, st);
+        if (e) return e;
         e = refresh(h, st);
         if (e) return e;
     }
