@@ -297,13 +297,115 @@ __device__ void node_gather(const RveCtx& c, const double* src, int nc, double* 
     }
 }
 
+// ---------------------------------------------------------------- LDS fronts
+// A front that fits in LDS is held there whole as a packed lower triangle,
+// column-major: entry (i, j), i >= j, at cpk(j, m) + i - j.  The first p columns
+// are the L panel and the trailing columns are exactly the packed update matrix,
+// so both leave the front with one contiguous copy each.
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ inline int cpk(int j, int m) { return j * m - ((j * (j - 1)) >> 1); }
+
+__device__ inline double readlane_d(double v, int l) {
+    union { double d; int i[2]; } u;
+    u.d = v;
+    u.i[0] = __builtin_amdgcn_readlane(u.i[0], l);
+    u.i[1] = __builtin_amdgcn_readlane(u.i[1], l);
+    return u.d;
+}
+
+// ---------------------------------------------------------------- global fronts
+// Plans whose fronts exceed LDS (3D from 5^3 up) keep each front in the slot's
+// global workspace: the m x p panel column-major (column j at Fp + j m, rows
+// i >= j used), the mu x mu update matrix U_s column-major (lower part used)
+// with its rhs rows.  The panel is factored in 16-column blocks, left-looking:
+// a block first receives the updates of all earlier blocks as one FP64 MFMA
+// GEMM, then wave 0 factors its 16 x 16 diagonal block in registers (readlane
+// broadcasts) and forms W = L11^-T D^-1, and the rows below become L21 = A21 W
+// on MFMA.  The Schur complement U_s -= L21 D L21^T is an MFMA SYRK over 32 x 32
+// blocks of four 16 x 16 tiles.
+
+// 16 x 16 diagonal block of a panel by wave 0: LDL^T with readlane broadcasts,
+// rhs of the block rows, W = L11^-T D^-1 (16 x 16, row-major) into W.  A(r, cc)
+// is the block entry (K + r, K + cc) at Ap[cc * ldA + r]; rhs column q of the
+// block rows at yv_base[q * ldy + r].
+__device__ inline void diag_block_wave(double* Ap, int ldA, double* Dd, const double* d0v, int kb, double* yv_base,
+                                       int ldy, int nrhs, double* W, int* flag) {
+    const int lane = threadIdx.x & 63;
+    const bool own = lane < kb;
+    double row[16];
+    double yv[kMaxNrhs];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) row[cc] = (own && cc < kb && cc <= lane) ? Ap[(int64_t)cc * ldA + lane] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxNrhs; ++q) yv[q] = (own && q < nrhs) ? yv_base[(int64_t)q * ldy + lane] : 0.0;
+    const double d0 = own ? d0v[lane] : 1.0;
+    double dpiv = 1.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j < kb) {
+            const double piv = readlane_d(row[j], j);
+            const double rp = 1.0 / piv;
+            if (lane == j) {
+                dpiv = piv;
+                if (!(fabs(piv) > 1e-14 * fabs(d0)) || !isfinite(piv)) *flag = 2;
+            }
+            const double l = (lane > j) ? row[j] * rp : 0.0;
+            const double lpv = l * piv;
+#pragma unroll
+            for (int cc = j + 1; cc < 16; ++cc) {
+                if (cc < kb) {
+                    const double lc = readlane_d(l, cc);
+                    if (cc <= lane) row[cc] -= lpv * lc;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kMaxNrhs; ++q) {
+                if (q < nrhs) {
+                    const double yj = readlane_d(yv[q], j);
+                    if (lane > j) yv[q] -= l * yj;
+                }
+            }
+            if (lane > j) row[j] = l;
+        }
+    }
+    double inv[16];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) inv[cc] = (cc == lane) ? 1.0 : 0.0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        if (e < kb) {
+            const double le = (lane > e) ? row[e] : 0.0;
+#pragma unroll
+            for (int cc = 0; cc <= e; ++cc) {
+                const double ie = readlane_d(inv[cc], e);
+                inv[cc] -= le * ie;
+            }
+        }
+    }
+    const double rdp = 1.0 / dpiv;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc)
+        if (lane < 16) W[cc * 16 + lane] = (own && cc < kb && cc <= lane) ? inv[cc] * rdp : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc)
+        if (own && cc < kb && cc <= lane) Ap[(int64_t)cc * ldA + lane] = (cc == lane) ? dpiv : row[cc];
+    if (own) Dd[lane] = dpiv;
+#pragma unroll
+    for (int q = 0; q < kMaxNrhs; ++q)
+        if (own && q < nrhs) yv_base[(int64_t)q * ldy + lane] = yv[q];
+}
+
 // Multifrontal LDL^T of K_ff with nrhs right-hand sides in c.rhs (node-major
 // [dof][nrhs]); forward substitution fused.  Returns via sm.flag = 2 on a
-// vanishing pivot.  Fronts in global memory (any size); update matrices dense.
+// vanishing pivot.  Fronts in global memory (any size).
 template <int D>
 __device__ void factorize_glb(const RveCtx& c, Smem& sm, int nrhs) {
     constexpr int NEN = 1 << D, ND = NEN * D;
     const DevPlan& pl = *c.plan;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* W = sm.red;  // 16 x 16
     for (int s = 0; s < pl.nfront; ++s) {
         const DevFront fr = pl.fronts[s];
         const int m = fr.m, p = fr.p, mu = m - p;
@@ -361,61 +463,135 @@ __device__ void factorize_glb(const RveCtx& c, Smem& sm, int nrhs) {
             }
             __syncthreads();
         }
-        // 4. LDL^T of the m x p panel (right-looking, unblocked), forward rhs
-        for (int j = 0; j < p; ++j) {
-            const double piv = Fp[(int64_t)j * m + j];
-            if (!(fabs(piv) > 1e-14 * fabs(Dg[j])) || !isfinite(piv)) {
-                if (threadIdx.x == 0) sm.flag = 2;
+        // 4. panel LDL^T in 16-column blocks (left-looking), forward rhs
+        for (int K = 0; K < p; K += 16) {
+            const int kb = min(16, p - K);
+            // (a) updates of all earlier columns: A(i, K + c) -= sum_{j<K} L(i, j) D(j) L(K + c, j)
+            if (K > 0) {
+                const int nt = (m - K + 15) >> 4;
+                for (int t0 = 2 * wave; t0 < nt; t0 += 2 * NWAVE) {
+                    dbl4 acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+                    const int cb = K + (lane & 15);
+                    for (int j0 = 0; j0 < K; j0 += 4) {
+                        const int j = j0 + (lane >> 4);
+                        const double* colj = Fp + (int64_t)j * m;
+                        const double dj = Dg[j];
+                        const double bv = ((lane & 15) < kb) ? colj[cb] : 0.0;
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            const int ra = K + 16 * (t0 + u) + (lane & 15);
+                            const double av = (ra < m) ? colj[ra] * dj : 0.0;
+                            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+                        }
+                    }
+                    const int cc = lane & 15;
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int rr = K + 16 * (t0 + u) + (lane >> 4) + 4 * v;
+                            if (t0 + u < nt && rr < m && cc < kb && rr >= K + cc)
+                                Fp[(int64_t)(K + cc) * m + rr] -= acc[u][v];
+                        }
+                }
+                __syncthreads();
             }
-            const double rp = 1.0 / piv;
-            const double* colj = Fp + (int64_t)j * m;
-            // trailing panel columns k in (j, p), rows i >= k
-            const int w = m - j - 1;
-            const int ncol = p - j - 1;
-            for (int t = threadIdx.x; t < w * ncol; t += NT) {
-                const int i = j + 1 + t % w, k = j + 1 + t / w;
-                if (i < k) continue;
-                Fp[(int64_t)k * m + i] -= colj[i] * colj[k] * rp;
-            }
-            for (int t = threadIdx.x; t < w * nrhs; t += NT) {
-                const int i = j + 1 + t % w, col = t / w;
-                const double l = colj[i] * rp;
-                const double yj = y[(int64_t)col * p + j];
-                if (i < p) y[(int64_t)col * p + i] -= l * yj;
-                else rus[(int64_t)col * mu + (i - p)] -= l * yj;
+            // (b) diagonal block and its rhs rows by wave 0
+            if (wave == 0) diag_block_wave(Fp + (int64_t)K * m + K, m, Dg + K, Dg + K, kb, y + K, p, nrhs, W, &sm.flag);
+            __syncthreads();
+            // (c) rows below: L21 = A21 W (MFMA)
+            const int R0 = K + kb;
+            {
+                const int nt = (m - R0 + 15) >> 4;
+                for (int t = wave; t < nt; t += NWAVE) {
+                    const int ra = R0 + 16 * t + (lane & 15);
+                    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int kk = 4 * ks + (lane >> 4);
+                        const double av = (kk < kb && ra < m) ? Fp[(int64_t)(K + kk) * m + ra] : 0.0;
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[kk * 16 + (lane & 15)], acc, 0, 0, 0);
+                    }
+                    const int cc = lane & 15;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int rr = R0 + 16 * t + (lane >> 4) + 4 * v;
+                        if (rr < m && cc < kb) Fp[(int64_t)(K + cc) * m + rr] = acc[v];
+                    }
+                }
             }
             __syncthreads();
-            for (int t = threadIdx.x; t < w; t += NT) Fp[(int64_t)j * m + j + 1 + t] *= rp;
-            if (threadIdx.x == 0) Dg[j] = piv;
-            // no barrier needed: the next step reads column j+1 (finished above)
-        }
-        __syncthreads();
-        // 5. Schur complement U_s -= L21 D L21^T
-        for (int t = threadIdx.x; t < mu * mu; t += NT) {
-            const int i = t % mu, k = t / mu;
-            if (i < k) continue;
-            double s = 0;
-            for (int j = 0; j < p; ++j) {
-                const double* cj = Fp + (int64_t)j * m + p;
-                s += cj[i] * Dg[j] * cj[k];
+            // (d) rhs of the rows below: b_i -= sum_c L(i, K + c) y(K + c)
+            for (int t = tid; t < (m - R0) * nrhs; t += NT) {
+                const int i = R0 + t % (m - R0), q = t / (m - R0);
+                double acc = 0.0;
+                for (int cc = 0; cc < kb; ++cc) acc += Fp[(int64_t)(K + cc) * m + i] * y[(int64_t)q * p + K + cc];
+                if (i < p) y[(int64_t)q * p + i] -= acc;
+                else rus[(int64_t)q * mu + (i - p)] -= acc;
             }
-            Us[t] -= s;
+            __syncthreads();
+        }
+        // 5. Schur complement U_s -= L21 D L21^T: 32 x 32 blocks (four MFMA tiles) of the lower triangle
+        {
+            const int n32 = (mu + 31) >> 5;
+            const int nblk = n32 * (n32 + 1) / 2;
+            for (int b = wave; b < nblk; b += NWAVE) {
+                int BI = 0, rem = b;
+                while (rem > BI) { rem -= BI + 1; ++BI; }
+                const int BJ = rem;
+                dbl4 acc[2][2] = {{{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}},
+                                  {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}}};
+                for (int j0 = 0; j0 < p; j0 += 4) {
+                    const int j = j0 + (lane >> 4);
+                    const bool jl = j < p;
+                    const double* colj = Fp + (int64_t)(jl ? j : 0) * m + p;
+                    const double dj = jl ? Dg[j] : 0.0;
+                    double av[2], bv[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int ri = 32 * BI + 16 * u + (lane & 15), rj = 32 * BJ + 16 * u + (lane & 15);
+                        av[u] = (jl && ri < mu) ? colj[ri] * dj : 0.0;
+                        bv[u] = (jl && rj < mu) ? colj[rj] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int w2 = 0; w2 < 2; ++w2)
+                            acc[u][w2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[w2], acc[u][w2], 0, 0, 0);
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int w2 = 0; w2 < 2; ++w2) {
+                        const int col = 32 * BJ + 16 * w2 + (lane & 15);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = 32 * BI + 16 * u + (lane >> 4) + 4 * v;
+                            if (row < mu && col <= row) Us[(int64_t)col * mu + row] -= acc[u][w2][v];
+                        }
+                    }
+            }
         }
         __syncthreads();
         // 6. push U_s (and its rhs part) on the stack
         if (mu > 0) {
             double* dst = c.U + fr.U_off;
-            for (int t = threadIdx.x; t < mu * mu + mu * nrhs; t += NT) dst[t] = Us[t];
+            for (int t = tid; t < mu * mu + mu * nrhs; t += NT) dst[t] = Us[t];
         }
         __syncthreads();
     }
 }
 
-// backward substitution L^T x = D^-1 y (nrhs = 1); x in node-major dof order
+// backward substitution L^T x = D^-1 y (nrhs = 1); x in node-major dof order.
+// Per front: the update rows' contribution (thread per pivot), then 16-pivot
+// blocks from the last: wave 0 solves the block triangle with readlane
+// broadcasts, all threads fold the block into the earlier pivots.
 template <int D>
 __device__ void backsolve_glb(const RveCtx& c, Smem& sm) {
     const DevPlan& pl = *c.plan;
-    for (int t = threadIdx.x; t < D; t += NT) c.x[t] = 0.0;  // pinned node
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int t = tid; t < D; t += NT) c.x[t] = 0.0;  // pinned node
+    __syncthreads();
     for (int s = pl.nfront - 1; s >= 0; --s) {
         const DevFront fr = pl.fronts[s];
         const int m = fr.m, p = fr.p;
@@ -423,40 +599,47 @@ __device__ void backsolve_glb(const RveCtx& c, Smem& sm) {
         const double* Fp = c.L + fr.L_off;
         const double* Dg = c.L + fr.D_off;
         double* y = c.L + fr.y_off;
-        for (int j = threadIdx.x; j < p; j += NT) {
+        for (int j = tid; j < p; j += NT) {
             double v = y[j] / Dg[j];
             const double* cj = Fp + (int64_t)j * m;
+#pragma unroll 4
             for (int i = p; i < m; ++i) v -= cj[i] * c.x[rows[i]];
             y[j] = v;
         }
         __syncthreads();
-        for (int jj = p - 1; jj > 0; --jj) {
-            const double xj = y[jj];
-            for (int j = threadIdx.x; j < jj; j += NT) y[j] -= Fp[(int64_t)j * m + jj] * xj;
+        const int nb = (p + 15) >> 4;
+        for (int bk = nb - 1; bk >= 0; --bk) {
+            const int K = 16 * bk, kb = min(16, p - K);
+            if (wave == 0) {
+                const bool own = lane < kb;
+                double Lr[16];
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc)
+                    Lr[cc] = (own && cc < kb && cc > lane) ? Fp[(int64_t)(K + lane) * m + K + cc] : 0.0;
+                double vv = own ? y[K + lane] : 0.0;
+#pragma unroll
+                for (int cc = 15; cc >= 0; --cc) {
+                    if (cc < kb) {
+                        const double xc = readlane_d(vv, cc);
+                        if (lane < cc) vv -= Lr[cc] * xc;
+                    }
+                }
+                if (own) y[K + lane] = vv;
+            }
+            __syncthreads();
+            for (int j = tid; j < K; j += NT) {
+                const double* cj = Fp + (int64_t)j * m + K;
+                double acc = y[j];
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc)
+                    if (cc < kb) acc -= cj[cc] * y[K + cc];
+                y[j] = acc;
+            }
             __syncthreads();
         }
-        for (int j = threadIdx.x; j < p; j += NT) c.x[rows[j]] = y[j];
+        for (int j = tid; j < p; j += NT) c.x[rows[j]] = y[j];
         __syncthreads();
     }
-}
-
-
-// ---------------------------------------------------------------- LDS fronts
-// A front that fits in LDS is held there whole as a packed lower triangle,
-// column-major: entry (i, j), i >= j, at cpk(j, m) + i - j.  The first p columns
-// are the L panel and the trailing columns are exactly the packed update matrix,
-// so both leave the front with one contiguous copy each.
-
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-__device__ inline int cpk(int j, int m) { return j * m - ((j * (j - 1)) >> 1); }
-
-__device__ inline double readlane_d(double v, int l) {
-    union { double d; int i[2]; } u;
-    u.d = v;
-    u.i[0] = __builtin_amdgcn_readlane(u.i[0], l);
-    u.i[1] = __builtin_amdgcn_readlane(u.i[1], l);
-    return u.d;
 }
 
 // Multifrontal LDL^T, fronts in LDS (F: packed front, rl: m x nrhs rhs rows).
