@@ -421,9 +421,13 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
         int64_t rl = 0;
         for (PlanEntry* p : plans)
             if (p->dev.lds_ok) rl = std::max(rl, p->rl_elems);
+        bool glb = false;
+        for (PlanEntry* p : plans) glb = glb || !p->dev.lds_ok;
         for (int k = 0; k < 2; ++k) {
             const int64_t es = k == 0 ? 8 : 4;
-            b->dyn_bytes[k] = (size_t)(std::max(b->lds_front[k] + rl, NWAVE_ * b->wave_slice) * es);
+            int64_t elems = std::max(b->lds_front[k] + rl, NWAVE_ * b->wave_slice);
+            if (glb) elems = std::max<int64_t>(elems, kTileLdsElems);  // global fronts: staged tile slabs
+            b->dyn_bytes[k] = (size_t)(elems * es);
         }
     }
     auto rnd = [](int64_t x) { return (x + 31) / 32 * 32; };
@@ -499,8 +503,7 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
         return fail(RVE_EINVAL, "rve_solve_batch: unknown precision");
     int pst = ensure_prepared();
     if (pst) return pst;
-    // FP32 factors apply to the 2D LDS-resident plans; other plans stay FP64
-    const bool fp32 = o.precision == RVE_PREC_FP32_IR && b->d == 2;
+    const bool fp32 = o.precision == RVE_PREC_FP32_IR;
     SolveArgs a{};
     a.plans = b->d_plans;
     a.rve_plan = b->d_rve_plan;

@@ -317,30 +317,64 @@ __device__ inline double readlane_d(double v, int l) {
 
 // ---------------------------------------------------------------- global fronts
 // Plans whose fronts exceed LDS (3D from 5^3 up) keep each front in the slot's
-// global workspace: the m x p panel column-major (column j at Fp + j m, rows
-// i >= j used), the mu x mu update matrix U_s column-major (lower part used)
-// with its rhs rows.  The panel is factored in 16-column blocks, left-looking:
-// a block first receives the updates of all earlier blocks as one FP64 MFMA
-// GEMM, then wave 0 factors its 16 x 16 diagonal block in registers (readlane
-// broadcasts) and forms W = L11^-T D^-1, and the rows below become L21 = A21 W
-// on MFMA.  The Schur complement U_s -= L21 D L21^T is an MFMA SYRK over 32 x 32
-// blocks of four 16 x 16 tiles.
+// global workspace in the factor type T: the m x p panel column-major (column j
+// at Fp + j m, rows i >= j used), its p pivots, and the mu x mu update matrix
+// U_s column-major (lower part used) followed by its FP64 rhs rows; the
+// forward-substituted rhs stays FP64.  The panel is factored left-looking in
+// 64-column blocks: a block first takes the updates of all columns left of it
+// as LDS-staged MFMA tiles, then each of its 16-column sub-blocks takes the
+// updates of the earlier sub-blocks, wave 0 factors the 16 x 16 diagonal block
+// in registers (readlane broadcasts) and forms W = L11^-T D^-1, and the rows
+// below become L21 = A21 W on MFMA.  The Schur complement U_s - L21 D L21^T
+// goes through the same tiles, straight onto the update stack.
 
-// 16 x 16 diagonal block of a panel by wave 0: LDL^T with readlane broadcasts,
-// rhs of the block rows, W = L11^-T D^-1 (16 x 16, row-major) into W.  A(r, cc)
-// is the block entry (K + r, K + cc) at Ap[cc * ldA + r]; rhs column q of the
-// block rows at yv_base[q * ldy + r].
-__device__ inline void diag_block_wave(double* Ap, int ldA, double* Dd, const double* d0v, int kb, double* yv_base,
-                                       int ldy, int nrhs, double* W, int* flag) {
+// MFMA 16 x 16 x 4 of the factor type: operand lanes A[l % 16][l / 16] and
+// B[l / 16][l % 16]; element v of lane l of the result is at column l % 16 and
+// row row(l, v) (FP64: l / 16 + 4 v; FP32: 4 (l / 16) + v; both verified by
+// in-bounds probes of the builtins)
+typedef float flt4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Mfma16;
+template <>
+struct Mfma16<double> {
+    typedef dbl4 V;
+    static __device__ inline V mma(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+    static __device__ inline V zero() { return V{0.0, 0.0, 0.0, 0.0}; }
+};
+template <>
+struct Mfma16<float> {
+    typedef flt4 V;
+    static __device__ inline V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+    static __device__ inline V zero() { return V{0.f, 0.f, 0.f, 0.f}; }
+};
+
+// FP64 rhs rows that follow an mu x mu matrix of T in an update region
+template <typename T>
+__device__ inline double* urhs(double* base, int mu) {
+    return base + ((int64_t)mu * mu * (int64_t)sizeof(T) + 7) / 8;
+}
+
+// 16 x 16 diagonal block of a panel by wave 0: LDL^T with readlane broadcasts
+// (FP64 arithmetic, stored in T), rhs of the block rows, W = L11^-T D^-1 (16 x
+// 16, row-major) into W.  A(r, cc) is the block entry (K + r, K + cc) at
+// Ap[cc * ldA + r]; rhs column q of the block rows at yv_base[q * ldy + r].
+template <typename T>
+__device__ inline void diag_block_wave(T* Ap, int ldA, T* Dd, const T* d0v, int kb, double* yv_base, int ldy,
+                                       int nrhs, T* W, int* flag) {
     const int lane = threadIdx.x & 63;
     const bool own = lane < kb;
     double row[16];
     double yv[kMaxNrhs];
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc) row[cc] = (own && cc < kb && cc <= lane) ? Ap[(int64_t)cc * ldA + lane] : 0.0;
+    for (int cc = 0; cc < 16; ++cc)
+        row[cc] = (own && cc < kb && cc <= lane) ? (double)Ap[(int64_t)cc * ldA + lane] : 0.0;
 #pragma unroll
     for (int q = 0; q < kMaxNrhs; ++q) yv[q] = (own && q < nrhs) ? yv_base[(int64_t)q * ldy + lane] : 0.0;
-    const double d0 = own ? d0v[lane] : 1.0;
+    const double d0 = own ? (double)d0v[lane] : 1.0;
     double dpiv = 1.0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -387,37 +421,219 @@ __device__ inline void diag_block_wave(double* Ap, int ldA, double* Dd, const do
     const double rdp = 1.0 / dpiv;
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc)
-        if (lane < 16) W[cc * 16 + lane] = (own && cc < kb && cc <= lane) ? inv[cc] * rdp : 0.0;
+        if (lane < 16) W[cc * 16 + lane] = (T)((own && cc < kb && cc <= lane) ? inv[cc] * rdp : 0.0);
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc)
-        if (own && cc < kb && cc <= lane) Ap[(int64_t)cc * ldA + lane] = (cc == lane) ? dpiv : row[cc];
-    if (own) Dd[lane] = dpiv;
+        if (own && cc < kb && cc <= lane) Ap[(int64_t)cc * ldA + lane] = (T)((cc == lane) ? dpiv : row[cc]);
+    if (own) Dd[lane] = (T)dpiv;
 #pragma unroll
     for (int q = 0; q < kMaxNrhs; ++q)
         if (own && q < nrhs) yv_base[(int64_t)q * ldy + lane] = yv[q];
 }
 
+// Rank-kdim update of the lower triangle of an nrows x ncols block through LDS:
+//   Cout(r, c) = Cin(r, c) - sum_{j < kdim} A(r, j) dv(j) A(c, j),   r >= c,
+// with A(r, j) at A[j lda + r] and C(r, c) at C[c ldc + r].  The block is
+// covered by kTileM x kTileN tiles (column tiles from the left, row tiles from
+// the diagonal down), all processed in one software pipeline: 16-column slabs
+// of A (scaled by dv) for the tile rows and columns are staged in LDS
+// (double-buffered, one barrier per slab) from two register sets, so each
+// slab's global loads are issued two slabs before its MFMAs run, across tile
+// boundaries too.  Loads are unconditional at clamped addresses; rows and
+// columns past the block only reach outputs that are never written, and
+// columns past kdim are zeroed through dv.  Each wave computes a 64 x 32
+// quarter of a tile as 4 x 2 MFMA tiles.  Every thread of the workgroup must
+// call it; it ends with a barrier.
+static_assert(kTileLdsElems == 2 * kTileSlab * (kTileStrideA + kTileStrideB), "tile_update LDS size");
+template <typename T>
+struct TileRegs {
+    T a[8], b[4], d[4];
+    int j0;  // first column of the slab
+};
+// global-address-space view of a workspace pointer: its loads count only on
+// the vector-memory counter, so the LDS waits before the MFMAs do not also wait
+// for prefetches in flight (generic pointers give flat loads, which count on both)
+template <typename T>
+__device__ inline const __attribute__((address_space(1))) T* as_global(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+// wave-uniform copies of values a non-inlined function receives in vector
+// registers: with them the compiler keeps loop bounds and addresses scalar, so
+// loops stay uniform and its wait counts across loop edges stay exact
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int64_t uni(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename P>
+__device__ inline P* uni(P* p) {
+    return (P*)(uintptr_t)uni((int64_t)(uintptr_t)p);
+}
+
+// walk of the tiles: column tiles c0 = 0, kTileN, ...; row tiles r0 = c0, c0 + kTileM, ...
+struct TileCursor {
+    int r0, c0;
+    __device__ inline void next(int nrows) {
+        r0 += kTileM;
+        if (r0 >= nrows) {
+            c0 += kTileN;
+            r0 = c0;
+        }
+    }
+};
+template <typename T>
+__device__ __attribute__((noinline)) void tiles_update(const T* A, const T* dv, int64_t lda, int kdim, const T* Cin,
+                                                       T* Cout, int64_t ldc, int nrows, int ncols, T* lds) {
+    typedef Mfma16<T> M;
+    A = uni(A);
+    dv = uni(dv);
+    lda = uni(lda);
+    kdim = uni(kdim);
+    Cin = uni(Cin);
+    Cout = uni(Cout);
+    ldc = uni(ldc);
+    nrows = uni(nrows);
+    ncols = uni(ncols);
+    lds = uni(lds);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = tid & 63, lj = (tid >> 6) * 4;
+    constexpr int BUF = kTileSlab * (kTileStrideA + kTileStrideB);
+    const auto* Ag = as_global(A);
+    const auto* dg = as_global(dv);
+    // slab count rounded up to even, so a pair of pipeline steps never spans
+    // two tiles and the loop body has no branch (a conditional prefetch would
+    // make the compiler wait for every load in flight before each LDS store)
+    const int ns = 2 * ((kdim + 2 * kTileSlab - 1) / (2 * kTileSlab));
+    // load side of the pipeline: tile and slab of the next load; once every
+    // slab is loaded it stays on the last one (loaded again, never computed)
+    TileCursor lc{0, 0};
+    int ls = 0;
+    auto load = [&](TileRegs<T>& R) {
+        const int j0 = kTileSlab * ls;
+        R.j0 = j0;
+        const int ra0 = min(lc.r0 + lr, nrows - 1), ra1 = min(lc.r0 + lr + 64, nrows - 1);
+        const int rb0 = min(lc.c0 + lr, ncols - 1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = min(j0 + lj + q, kdim - 1);
+            const auto* Aj = Ag + (int64_t)j * lda;
+            R.a[q] = Aj[ra0];
+            R.a[4 + q] = Aj[ra1];
+            R.b[q] = Aj[rb0];
+            R.d[q] = dg[j];
+        }
+        // advance with selects only: a branch here would split the loop body
+        // and make the compiler drain the loads in flight
+        const bool wrap = ls + 1 == ns;
+        const bool colwrap = lc.r0 + kTileM >= nrows;
+        const int nc0 = colwrap ? lc.c0 + kTileN : lc.c0;
+        const int nr0 = colwrap ? nc0 : lc.r0 + kTileM;
+        const bool more = nc0 < ncols;
+        lc.r0 = (wrap && more) ? nr0 : lc.r0;
+        lc.c0 = (wrap && more) ? nc0 : lc.c0;
+        ls = wrap ? (more ? 0 : ns - 1) : ls + 1;
+    };
+    auto store = [&](const TileRegs<T>& R, int buf) {
+        T* As = lds + buf * BUF;
+        T* Bs = As + kTileSlab * kTileStrideA;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T dq = R.j0 + lj + q < kdim ? R.d[q] : T(0);  // columns past kdim
+            As[(lj + q) * kTileStrideA + lr] = R.a[q] * dq;
+            As[(lj + q) * kTileStrideA + lr + 64] = R.a[4 + q] * dq;
+            Bs[(lj + q) * kTileStrideB + lr] = R.b[q];
+        }
+    };
+    typename M::V acc[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w2 = 0; w2 < 2; ++w2) acc[u][w2] = M::zero();
+    const int wr = 64 * (wave >> 1), wc = 32 * (wave & 1);
+    auto compute = [&](int buf) {
+        const T* As = lds + buf * BUF;
+        const T* Bs = As + kTileSlab * kTileStrideA;
+#pragma unroll
+        for (int ks = 0; ks < kTileSlab / 4; ++ks) {
+            const int kk = 4 * ks + (lane >> 4);
+            T av[4], bv[2];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[u] = As[kk * kTileStrideA + wr + 16 * u + (lane & 15)];
+#pragma unroll
+            for (int w2 = 0; w2 < 2; ++w2) bv[w2] = Bs[kk * kTileStrideB + wc + 16 * w2 + (lane & 15)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int w2 = 0; w2 < 2; ++w2) acc[u][w2] = M::mma(av[u], bv[w2], acc[u][w2]);
+        }
+    };
+    // one pipeline step: the next slab's loads are issued first, the MFMAs of
+    // LDS buffer buf run while they are in flight, and the slab is staged into
+    // the other buffer at the end (no load stays in flight across steps)
+    auto step = [&](int buf, TileRegs<T>& R) {
+        load(R);
+        __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
+        compute(buf);
+        store(R, buf ^ 1);
+        __syncthreads();
+    };
+    TileRegs<T> R0;
+    if (ns > 0) {  // kdim = 0: Cout = Cin
+        load(R0);
+        store(R0, 0);
+    }
+    __syncthreads();
+    for (TileCursor cc{0, 0}; cc.c0 < ncols; cc.next(nrows)) {
+        for (int s = 0; s < ns; s += 2) {
+            step(0, R0);
+            step(1, R0);
+        }
+        const int nr = nrows - cc.r0, nc = ncols - cc.c0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int w2 = 0; w2 < 2; ++w2) {
+                const int col = wc + 16 * w2 + (lane & 15);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = wr + 16 * u + M::row(lane, v);
+                    if (rr < nr && col < nc && cc.r0 + rr >= cc.c0 + col) {
+                        const int64_t o = (int64_t)(cc.c0 + col) * ldc + cc.r0 + rr;
+                        Cout[o] = Cin[o] - acc[u][w2][v];
+                    }
+                }
+                acc[u][w2] = M::zero();
+            }
+    }
+}
+
 // Multifrontal LDL^T of K_ff with nrhs right-hand sides in c.rhs (node-major
 // [dof][nrhs]); forward substitution fused.  Returns via sm.flag = 2 on a
-// vanishing pivot.  Fronts in global memory (any size).
-template <int D>
-__device__ void factorize_glb(const RveCtx& c, Smem& sm, int nrhs) {
+// vanishing pivot.  Fronts in global memory (any size) in the factor type T;
+// lds holds the staged slabs of tile_update.
+template <int D, typename T>
+__device__ __attribute__((noinline)) void factorize_glb(const RveCtx& c, Smem& sm, int nrhs, T* lds) {
+    typedef Mfma16<T> M;
     constexpr int NEN = 1 << D, ND = NEN * D;
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double* W = sm.red;  // 16 x 16
+    T* W = reinterpret_cast<T*>(sm.red);  // 16 x 16
+    PROF_T0();
     for (int s = 0; s < pl.nfront; ++s) {
         const DevFront fr = pl.fronts[s];
         const int m = fr.m, p = fr.p, mu = m - p;
         const int32_t* rows = pl.rows + fr.rows_off;
-        double* Fp = c.L + fr.L_off;
-        double* Dg = c.L + fr.D_off;
+        T* Fp = reinterpret_cast<T*>(c.L + fr.L_off);
+        T* Dg = reinterpret_cast<T*>(c.L + fr.D_off);
         double* y = c.L + fr.y_off;
-        double* Us = c.S;
-        double* rus = c.S + (int64_t)mu * mu;
+        T* Us = reinterpret_cast<T*>(c.S);
+        double* rus = urhs<T>(c.S, mu);
         // 1. zero the panel and the scratch update matrix, load the pivot rhs
-        for (int t = threadIdx.x; t < m * p; t += NT) Fp[t] = 0.0;
-        for (int t = threadIdx.x; t < mu * mu + mu * nrhs; t += NT) Us[t] = 0.0;
+        for (int t = threadIdx.x; t < m * p; t += NT) Fp[t] = T(0);
+        for (int t = threadIdx.x; t < mu * mu; t += NT) Us[t] = T(0);
+        for (int t = threadIdx.x; t < mu * nrhs; t += NT) rus[t] = 0.0;
         for (int t = threadIdx.x; t < p * nrhs; t += NT) {
             int j = t % p, col = t / p;
             y[t] = c.rhs[(int64_t)rows[j] * nrhs + col];
@@ -435,8 +651,8 @@ __device__ void factorize_glb(const RveCtx& c, Smem& sm, int nrhs) {
                 const KContrib cb = pl.kcontrib[kp.c_begin + q];
                 v += c.ke[((int64_t)cb.elem * ND + cb.lb * D + k) * ND + cb.la * D + l];
             }
-            Fp[(int64_t)col * m + r] = v;
-            if (r == col) Dg[col] = v;
+            Fp[(int64_t)col * m + r] = (T)v;
+            if (r == col) Dg[col] = (T)v;
         }
         __syncthreads();
         // 3. extend-add of the children's update matrices and rhs updates
@@ -444,15 +660,33 @@ __device__ void factorize_glb(const RveCtx& c, Smem& sm, int nrhs) {
             const DevFront ch = pl.fronts[pl.children[q]];
             const int mc = ch.m - ch.p;
             const int32_t* rel = pl.relind + ch.relind_off;
-            const double* Uc = c.U + ch.U_off;
-            const double* ruc = Uc + (int64_t)mc * mc;
-            for (int t = threadIdx.x; t < mc * mc; t += NT) {
-                const int i = t % mc, k = t / mc;
-                if (i < k) continue;
-                const int R = rel[i], C = rel[k];
-                const double v = Uc[t];
-                if (C < p) Fp[(int64_t)C * m + R] += v;
-                else Us[(int64_t)(C - p) * mu + (R - p)] += v;
+            const T* Uc = reinterpret_cast<const T*>(c.U + ch.U_off);
+            const double* ruc = urhs<T>(c.U + ch.U_off, mc);
+            // lower triangle, 8 columns per pass: a thread first issues the 8
+            // loads of its row, then the 8 read-modify-writes, so each pass costs
+            // two memory round trips instead of sixteen
+            for (int k0 = 0; k0 < mc; k0 += 8) {
+                int Ck[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) Ck[u] = rel[min(k0 + u, mc - 1)];
+                for (int i = k0 + threadIdx.x; i < mc; i += NT) {
+                    const int R = rel[i];
+                    T v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = Uc[(int64_t)min(k0 + u, mc - 1) * mc + i];
+                    T* dstp[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int C = Ck[u];
+                        dstp[u] = C < p ? Fp + (int64_t)C * m + R : Us + (int64_t)(C - p) * mu + (R - p);
+                    }
+                    T old[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) old[u] = (k0 + u < mc && i >= k0 + u) ? *dstp[u] : T(0);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (k0 + u < mc && i >= k0 + u) *dstp[u] = old[u] + v[u];
+                }
             }
             for (int t = threadIdx.x; t < mc * nrhs; t += NT) {
                 const int i = t % mc, col = t / mc;
@@ -463,148 +697,198 @@ __device__ void factorize_glb(const RveCtx& c, Smem& sm, int nrhs) {
             }
             __syncthreads();
         }
-        // 4. panel LDL^T in 16-column blocks (left-looking), forward rhs
-        for (int K = 0; K < p; K += 16) {
-            const int kb = min(16, p - K);
-            // (a) updates of all earlier columns: A(i, K + c) -= sum_{j<K} L(i, j) D(j) L(K + c, j)
-            if (K > 0) {
-                const int nt = (m - K + 15) >> 4;
-                for (int t0 = 2 * wave; t0 < nt; t0 += 2 * NWAVE) {
-                    dbl4 acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-                    const int cb = K + (lane & 15);
-                    for (int j0 = 0; j0 < K; j0 += 4) {
-                        const int j = j0 + (lane >> 4);
-                        const double* colj = Fp + (int64_t)j * m;
-                        const double dj = Dg[j];
-                        const double bv = ((lane & 15) < kb) ? colj[cb] : 0.0;
+        PROF_MARK(PH_ASM);
+        // 4. panel LDL^T in 64-column blocks (left-looking), forward rhs.  A
+        // block first takes the updates of all columns left of it as LDS tiles,
+        // then its four 16-column sub-blocks are factored in turn.
+        for (int K64 = 0; K64 < p; K64 += 64) {
+            const int kb64 = min(64, p - K64);
+            if (K64 > 0) {
+                T* Ct = Fp + (int64_t)K64 * m + K64;
+                tiles_update<T>(Fp + K64, Dg, m, K64, Ct, Ct, m, m - K64, kb64, lds);
+            }
+            for (int K = K64; K < K64 + kb64; K += 16) {
+                const int kb = min(16, p - K);
+                // (a) updates of the earlier columns of the block:
+                //     A(i, K + c) -= sum_{K64 <= j < K} L(i, j) D(j) L(K + c, j)
+                if (K > K64) {
+                    const int nt = (m - K + 15) >> 4;
+                    for (int t0 = 2 * wave; t0 < nt; t0 += 2 * NWAVE) {
+                        typename M::V acc[2] = {M::zero(), M::zero()};
+                        const int cb = K + (lane & 15);
+                        for (int j0 = K64; j0 < K; j0 += 4) {
+                            const int j = j0 + (lane >> 4);
+                            const T* colj = Fp + (int64_t)j * m;
+                            const T dj = Dg[j];
+                            const T bv = ((lane & 15) < kb) ? colj[cb] : T(0);
 #pragma unroll
-                        for (int u = 0; u < 2; ++u) {
-                            const int ra = K + 16 * (t0 + u) + (lane & 15);
-                            const double av = (ra < m) ? colj[ra] * dj : 0.0;
-                            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+                            for (int u = 0; u < 2; ++u) {
+                                const int ra = K + 16 * (t0 + u) + (lane & 15);
+                                const T av = (ra < m) ? colj[ra] * dj : T(0);
+                                acc[u] = M::mma(av, bv, acc[u]);
+                            }
                         }
-                    }
-                    const int cc = lane & 15;
+                        const int cc = lane & 15;
 #pragma unroll
-                    for (int u = 0; u < 2; ++u)
+                        for (int u = 0; u < 2; ++u)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int rr = K + 16 * (t0 + u) + M::row(lane, v);
+                                if (t0 + u < nt && rr < m && cc < kb && rr >= K + cc)
+                                    Fp[(int64_t)(K + cc) * m + rr] -= acc[u][v];
+                            }
+                    }
+                    __syncthreads();
+                }
+                PROF_MARK(PH_MFMA);
+                // (b) diagonal block and its rhs rows by wave 0
+                if (wave == 0)
+                    diag_block_wave<T>(Fp + (int64_t)K * m + K, m, Dg + K, Dg + K, kb, y + K, p, nrhs, W, &sm.flag);
+                __syncthreads();
+                PROF_MARK(PH_DIAG);
+                // (c) rows below: L21 = A21 W (MFMA)
+                const int R0 = K + kb;
+                {
+                    const int nt = (m - R0 + 15) >> 4;
+                    for (int t = wave; t < nt; t += NWAVE) {
+                        const int ra = R0 + 16 * t + (lane & 15);
+                        typename M::V acc = M::zero();
+#pragma unroll
+                        for (int ks = 0; ks < 4; ++ks) {
+                            const int kk = 4 * ks + (lane >> 4);
+                            const T av = (kk < kb && ra < m) ? Fp[(int64_t)(K + kk) * m + ra] : T(0);
+                            acc = M::mma(av, W[kk * 16 + (lane & 15)], acc);
+                        }
+                        const int cc = lane & 15;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            const int rr = K + 16 * (t0 + u) + (lane >> 4) + 4 * v;
-                            if (t0 + u < nt && rr < m && cc < kb && rr >= K + cc)
-                                Fp[(int64_t)(K + cc) * m + rr] -= acc[u][v];
+                            const int rr = R0 + 16 * t + M::row(lane, v);
+                            if (rr < m && cc < kb) Fp[(int64_t)(K + cc) * m + rr] = acc[v];
                         }
+                    }
                 }
                 __syncthreads();
-            }
-            // (b) diagonal block and its rhs rows by wave 0
-            if (wave == 0) diag_block_wave(Fp + (int64_t)K * m + K, m, Dg + K, Dg + K, kb, y + K, p, nrhs, W, &sm.flag);
-            __syncthreads();
-            // (c) rows below: L21 = A21 W (MFMA)
-            const int R0 = K + kb;
-            {
-                const int nt = (m - R0 + 15) >> 4;
-                for (int t = wave; t < nt; t += NWAVE) {
-                    const int ra = R0 + 16 * t + (lane & 15);
-                    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) {
-                        const int kk = 4 * ks + (lane >> 4);
-                        const double av = (kk < kb && ra < m) ? Fp[(int64_t)(K + kk) * m + ra] : 0.0;
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[kk * 16 + (lane & 15)], acc, 0, 0, 0);
-                    }
-                    const int cc = lane & 15;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int rr = R0 + 16 * t + (lane >> 4) + 4 * v;
-                        if (rr < m && cc < kb) Fp[(int64_t)(K + cc) * m + rr] = acc[v];
-                    }
+                // (d) rhs of the rows below: b_i -= sum_c L(i, K + c) y(K + c)
+                for (int t = tid; t < (m - R0) * nrhs; t += NT) {
+                    const int i = R0 + t % (m - R0), q = t / (m - R0);
+                    double acc = 0.0;
+                    for (int cc = 0; cc < kb; ++cc)
+                        acc += (double)Fp[(int64_t)(K + cc) * m + i] * y[(int64_t)q * p + K + cc];
+                    if (i < p) y[(int64_t)q * p + i] -= acc;
+                    else rus[(int64_t)q * mu + (i - p)] -= acc;
                 }
-            }
-            __syncthreads();
-            // (d) rhs of the rows below: b_i -= sum_c L(i, K + c) y(K + c)
-            for (int t = tid; t < (m - R0) * nrhs; t += NT) {
-                const int i = R0 + t % (m - R0), q = t / (m - R0);
-                double acc = 0.0;
-                for (int cc = 0; cc < kb; ++cc) acc += Fp[(int64_t)(K + cc) * m + i] * y[(int64_t)q * p + K + cc];
-                if (i < p) y[(int64_t)q * p + i] -= acc;
-                else rus[(int64_t)q * mu + (i - p)] -= acc;
-            }
-            __syncthreads();
-        }
-        // 5. Schur complement U_s -= L21 D L21^T: 32 x 32 blocks (four MFMA tiles) of the lower triangle
-        {
-            const int n32 = (mu + 31) >> 5;
-            const int nblk = n32 * (n32 + 1) / 2;
-            for (int b = wave; b < nblk; b += NWAVE) {
-                int BI = 0, rem = b;
-                while (rem > BI) { rem -= BI + 1; ++BI; }
-                const int BJ = rem;
-                dbl4 acc[2][2] = {{{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}},
-                                  {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}}};
-                for (int j0 = 0; j0 < p; j0 += 4) {
-                    const int j = j0 + (lane >> 4);
-                    const bool jl = j < p;
-                    const double* colj = Fp + (int64_t)(jl ? j : 0) * m + p;
-                    const double dj = jl ? Dg[j] : 0.0;
-                    double av[2], bv[2];
-#pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        const int ri = 32 * BI + 16 * u + (lane & 15), rj = 32 * BJ + 16 * u + (lane & 15);
-                        av[u] = (jl && ri < mu) ? colj[ri] * dj : 0.0;
-                        bv[u] = (jl && rj < mu) ? colj[rj] : 0.0;
-                    }
-#pragma unroll
-                    for (int u = 0; u < 2; ++u)
-#pragma unroll
-                        for (int w2 = 0; w2 < 2; ++w2)
-                            acc[u][w2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[w2], acc[u][w2], 0, 0, 0);
-                }
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int w2 = 0; w2 < 2; ++w2) {
-                        const int col = 32 * BJ + 16 * w2 + (lane & 15);
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int row = 32 * BI + 16 * u + (lane >> 4) + 4 * v;
-                            if (row < mu && col <= row) Us[(int64_t)col * mu + row] -= acc[u][w2][v];
-                        }
-                    }
+                __syncthreads();
+                PROF_MARK(PH_TRSM);
             }
         }
-        __syncthreads();
-        // 6. push U_s (and its rhs part) on the stack
+        // 5. Schur complement U = U_s - L21 D L21^T over the tiles of its lower
+        //    triangle, written straight onto the update stack with its rhs rows
         if (mu > 0) {
-            double* dst = c.U + fr.U_off;
-            for (int t = tid; t < mu * mu + mu * nrhs; t += NT) dst[t] = Us[t];
+            T* dst = reinterpret_cast<T*>(c.U + fr.U_off);
+            double* drhs = urhs<T>(c.U + fr.U_off, mu);
+            tiles_update<T>(Fp + p, Dg, m, p, Us, dst, mu, mu, mu, lds);
+            for (int t = tid; t < mu * nrhs; t += NT) drhs[t] = rus[t];
         }
         __syncthreads();
+        PROF_MARK(PH_OUT);
     }
 }
 
-// backward substitution L^T x = D^-1 y (nrhs = 1); x in node-major dof order.
-// Per front: the update rows' contribution (thread per pivot), then 16-pivot
-// blocks from the last: wave 0 solves the block triangle with readlane
-// broadcasts, all threads fold the block into the earlier pivots.
-template <int D>
-__device__ void backsolve_glb(const RveCtx& c, Smem& sm) {
+// forward substitution L y = b with stored global-memory factors, for a new
+// rhs b (node-major [dof][NRHS], FP64, overwritten): fronts in elimination
+// order; per front the pivot rows are solved in 16-pivot blocks (readlane
+// chain in wave 0) and folded into the rows below, whose update goes straight
+// into b at the rows' dofs (each is a pivot of a later front); the pivot part
+// is stored as the front's forward-substituted rhs for backsolve_glb.
+template <int D, int NRHS, typename T>
+__device__ __attribute__((noinline)) void forward_glb(const RveCtx& c, Smem& sm, double* b) {
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int t = tid; t < D; t += NT) c.x[t] = 0.0;  // pinned node
+    for (int s = 0; s < pl.nfront; ++s) {
+        const DevFront fr = pl.fronts[s];
+        const int m = fr.m, p = fr.p;
+        const int32_t* rows = pl.rows + fr.rows_off;
+        const T* Fp = reinterpret_cast<const T*>(c.L + fr.L_off);
+        double* y = c.L + fr.y_off;
+        for (int t = tid; t < p * NRHS; t += NT) {
+            const int j = t % p, q = t / p;
+            y[t] = b[(int64_t)rows[j] * NRHS + q];
+        }
+        __syncthreads();
+        for (int K = 0; K < p; K += 16) {
+            const int kb = min(16, p - K);
+            if (wave == 0) {
+                const bool own = lane < kb;
+                double Lr[16];
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc)
+                    Lr[cc] = (own && cc < kb && cc < lane) ? (double)Fp[(int64_t)(K + cc) * m + K + lane] : 0.0;
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) {
+                    double vv = own ? y[(int64_t)q * p + K + lane] : 0.0;
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc) {
+                        if (cc < kb) {
+                            const double yc = readlane_d(vv, cc);
+                            if (lane > cc) vv -= Lr[cc] * yc;
+                        }
+                    }
+                    if (own) y[(int64_t)q * p + K + lane] = vv;
+                }
+            }
+            __syncthreads();
+            for (int i = K + kb + tid; i < m; i += NT) {
+                double lk[16];
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc) lk[cc] = (cc < kb) ? (double)Fp[(int64_t)(K + cc) * m + i] : 0.0;
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc)
+                        if (cc < kb) acc += lk[cc] * y[(int64_t)q * p + K + cc];
+                    if (i < p) y[(int64_t)q * p + i] -= acc;
+                    else b[(int64_t)rows[i] * NRHS + q] -= acc;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// backward substitution L^T x = D^-1 y with global-memory factors; x
+// node-major [dof][NRHS].  Per front: the update rows' contribution (thread
+// per pivot), then 16-pivot blocks from the last: wave 0 solves the block
+// triangle with readlane broadcasts, all threads fold the block into the
+// earlier pivots.
+template <int D, int NRHS, typename T>
+__device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& sm, double* xo) {
+    const DevPlan& pl = *c.plan;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int t = tid; t < D * NRHS; t += NT) xo[t] = 0.0;  // pinned node
     __syncthreads();
     for (int s = pl.nfront - 1; s >= 0; --s) {
         const DevFront fr = pl.fronts[s];
         const int m = fr.m, p = fr.p;
         const int32_t* rows = pl.rows + fr.rows_off;
-        const double* Fp = c.L + fr.L_off;
-        const double* Dg = c.L + fr.D_off;
+        const T* Fp = reinterpret_cast<const T*>(c.L + fr.L_off);
+        const T* Dg = reinterpret_cast<const T*>(c.L + fr.D_off);
         double* y = c.L + fr.y_off;
         for (int j = tid; j < p; j += NT) {
-            double v = y[j] / Dg[j];
-            const double* cj = Fp + (int64_t)j * m;
+            const double rd = 1.0 / (double)Dg[j];
+            double v[NRHS];
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) v[q] = y[(int64_t)q * p + j] * rd;
+            const T* cj = Fp + (int64_t)j * m;
 #pragma unroll 4
-            for (int i = p; i < m; ++i) v -= cj[i] * c.x[rows[i]];
-            y[j] = v;
+            for (int i = p; i < m; ++i) {
+                const double l = (double)cj[i];
+                const double* xr = xo + (int64_t)rows[i] * NRHS;
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) v[q] -= l * xr[q];
+            }
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) y[(int64_t)q * p + j] = v[q];
         }
         __syncthreads();
         const int nb = (p + 15) >> 4;
@@ -615,29 +899,41 @@ __device__ void backsolve_glb(const RveCtx& c, Smem& sm) {
                 double Lr[16];
 #pragma unroll
                 for (int cc = 0; cc < 16; ++cc)
-                    Lr[cc] = (own && cc < kb && cc > lane) ? Fp[(int64_t)(K + lane) * m + K + cc] : 0.0;
-                double vv = own ? y[K + lane] : 0.0;
+                    Lr[cc] = (own && cc < kb && cc > lane) ? (double)Fp[(int64_t)(K + lane) * m + K + cc] : 0.0;
 #pragma unroll
-                for (int cc = 15; cc >= 0; --cc) {
-                    if (cc < kb) {
-                        const double xc = readlane_d(vv, cc);
-                        if (lane < cc) vv -= Lr[cc] * xc;
+                for (int q = 0; q < NRHS; ++q) {
+                    double vv = own ? y[(int64_t)q * p + K + lane] : 0.0;
+#pragma unroll
+                    for (int cc = 15; cc >= 0; --cc) {
+                        if (cc < kb) {
+                            const double xc = readlane_d(vv, cc);
+                            if (lane < cc) vv -= Lr[cc] * xc;
+                        }
                     }
+                    if (own) y[(int64_t)q * p + K + lane] = vv;
                 }
-                if (own) y[K + lane] = vv;
             }
             __syncthreads();
             for (int j = tid; j < K; j += NT) {
-                const double* cj = Fp + (int64_t)j * m + K;
-                double acc = y[j];
+                const T* cj = Fp + (int64_t)j * m + K;
+                double lk[16];
 #pragma unroll
-                for (int cc = 0; cc < 16; ++cc)
-                    if (cc < kb) acc -= cj[cc] * y[K + cc];
-                y[j] = acc;
+                for (int cc = 0; cc < 16; ++cc) lk[cc] = (cc < kb) ? (double)cj[cc] : 0.0;
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) {
+                    double acc = y[(int64_t)q * p + j];
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc)
+                        if (cc < kb) acc -= lk[cc] * y[(int64_t)q * p + K + cc];
+                    y[(int64_t)q * p + j] = acc;
+                }
             }
             __syncthreads();
         }
-        for (int j = tid; j < p; j += NT) c.x[rows[j]] = y[j];
+        for (int t = tid; t < p * NRHS; t += NT) {
+            const int j = t % p, q = t / p;
+            xo[(int64_t)rows[j] * NRHS + q] = y[(int64_t)q * p + j];
+        }
         __syncthreads();
     }
 }
@@ -1457,25 +1753,28 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
             for (int t = threadIdx.x; t < ndof; t += NT) c.rhs[t] = -c.R[t];
             __syncthreads();
             if (c.plan->lds_ok) factorize_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
-            else factorize_glb<D>(c, sm, 1);
+            else factorize_glb<D, T>(c, sm, 1, dynF);
             if (sm.flag) { status = 3; break; }
             PROF_RESET();
             if (c.plan->lds_ok) backsolve_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, c.x, a.lds_front, a.wave_slice);
-            else backsolve_glb<D>(c, sm);
+            else backsolve_glb<D, 1, T>(c, sm, c.x);
             PROF_MARK(PH_BACK);
             if constexpr (IR) {
                 // refinement against the FP64 tangent: dx = K32^-1 (b - K64 x)
-                if (c.plan->lds_ok) {
-                    for (int ref = 0; ref < a.ir_max; ++ref) {
-                        residual_ke<D, 1>(c, c.rhs, c.x, ir1);
-                        __syncthreads();
-                        const double rl2 = sqrt(free_norm2<D>(c, sm, ir1));
-                        if (!(rl2 > a.ir_eta * rn)) break;
+                for (int ref = 0; ref < a.ir_max; ++ref) {
+                    residual_ke<D, 1>(c, c.rhs, c.x, ir1);
+                    __syncthreads();
+                    const double rl2 = sqrt(free_norm2<D>(c, sm, ir1));
+                    if (!(rl2 > a.ir_eta * rn)) break;
+                    if (c.plan->lds_ok) {
                         forward_lds<D, 1, T>(c, sm, dynF, ir1, a.lds_front);
                         backsolve_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front, a.wave_slice);
-                        for (int t = threadIdx.x; t < ndof; t += NT) c.x[t] += ir2[t];
-                        __syncthreads();
+                    } else {
+                        forward_glb<D, 1, T>(c, sm, ir1);
+                        backsolve_glb<D, 1, T>(c, sm, ir2);
                     }
+                    for (int t = threadIdx.x; t < ndof; t += NT) c.x[t] += ir2[t];
+                    __syncthreads();
                 }
             }
             // step with det F backtracking
@@ -1521,22 +1820,30 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
                 node_gather<D>(c, c.re, D2, c.rhs, 1.0);
                 __syncthreads();
                 if (c.plan->lds_ok) factorize_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
-                else factorize_glb<D>(c, sm, D2);
+                else factorize_glb<D, T>(c, sm, D2, dynF);
                 if (sm.flag) {
                     status = 3;
-                } else if (IR && c.plan->lds_ok) {
+                } else if (IR) {
                     // X ~ K^-1 Y from the FP32 factors, refined ir_max_tan times against
                     // the FP64 tangent; then the stationary (second-order) form
                     //   Abar = <A> - Y^T X - X^T r,  r = Y - K X,
                     // whose error is (X - X*)^T K (X - X*) (energy-norm error squared)
                     double* X = c.re;  // element Y no longer needed: [dof][D2]
-                    backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front, a.wave_slice);
+                    if (c.plan->lds_ok)
+                        backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front, a.wave_slice);
+                    else
+                        backsolve_glb<D, D2, T>(c, sm, X);
                     for (int ref = 0;; ++ref) {
                         residual_ke<D, D2>(c, c.rhs, X, ir1);
                         __syncthreads();
                         if (ref == a.ir_max_tan) break;
-                        forward_lds<D, D2, T>(c, sm, dynF, ir1, a.lds_front);
-                        backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front, a.wave_slice);
+                        if (c.plan->lds_ok) {
+                            forward_lds<D, D2, T>(c, sm, dynF, ir1, a.lds_front);
+                            backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front, a.wave_slice);
+                        } else {
+                            forward_glb<D, D2, T>(c, sm, ir1);
+                            backsolve_glb<D, D2, T>(c, sm, ir2);
+                        }
                         for (int t = threadIdx.x; t < ndof * D2; t += NT) X[t] += ir2[t];
                         __syncthreads();
                     }
@@ -1605,8 +1912,8 @@ int lds_static_bytes() { return (int)sizeof(Smem); }
 
 // dynamic LDS limits are raised once per process, outside any stream capture
 hipError_t prepare_rve_solve() {
-    const void* ks[3] = {(const void*)rve_solve_kernel<2, double>, (const void*)rve_solve_kernel<2, float>,
-                         (const void*)rve_solve_kernel<3, double>};
+    const void* ks[4] = {(const void*)rve_solve_kernel<2, double>, (const void*)rve_solve_kernel<2, float>,
+                         (const void*)rve_solve_kernel<3, double>, (const void*)rve_solve_kernel<3, float>};
     for (const void* k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            kLdsBytesMax - (int)sizeof(Smem));
@@ -1621,6 +1928,8 @@ hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, bo
         hipLaunchKernelGGL((rve_solve_kernel<2, float>), dim3(nslots), dim3(NT), dyn_bytes, stream, a);
     else if (a.dim == 2)
         hipLaunchKernelGGL((rve_solve_kernel<2, double>), dim3(nslots), dim3(NT), dyn_bytes, stream, a);
+    else if (fp32)
+        hipLaunchKernelGGL((rve_solve_kernel<3, float>), dim3(nslots), dim3(NT), dyn_bytes, stream, a);
     else
         hipLaunchKernelGGL((rve_solve_kernel<3, double>), dim3(nslots), dim3(NT), dyn_bytes, stream, a);
     return hipGetLastError();

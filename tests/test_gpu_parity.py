@@ -180,6 +180,24 @@ def test_parity_fp32_ir_config1_sampled():
     compare_loose_iters(2, wl.n, wl.radius, wl.ratio, wl.F, out, idx=idx)
 
 
+@pytest.mark.parametrize("n", [2, 3, 4, 6])
+def test_parity_fp32_ir_3d(n):
+    """3D plans keep their fronts in global memory; FP32 factors there go
+    through the FP32 MFMA tiles and the same FP64 refinement."""
+    B = 6
+    wl = workloads.rve3d(B, sizes=(n,), seed=1600 + n)
+    print(f"case fp32+ir 3d n={n} B={B}", flush=True)
+    out = run_gpu(3, wl.n, wl.radius, wl.ratio, wl.F, opts=rve.default_opts(precision=rve.PREC_FP32_IR))
+    compare_loose_iters(3, wl.n, wl.radius, wl.ratio, wl.F, out)
+
+
+def test_parity_fp32_ir_3d_uneven_batch():
+    wl = workloads.rve3d(6, sizes=(6, 8), seed=1601)
+    print(f"case fp32+ir 3d uneven n={list(wl.n)}", flush=True)
+    out = run_gpu(3, wl.n, wl.radius, wl.ratio, wl.F, opts=rve.default_opts(precision=rve.PREC_FP32_IR))
+    compare_loose_iters(3, wl.n, wl.radius, wl.ratio, wl.F, out)
+
+
 def test_infeasible_warm_start_matches_oracle_cold_start():
     """Warm starts that fold an element under the new Fbar are discarded on the
     GPU as in the oracle: results and iteration counts equal the cold start."""
