@@ -434,20 +434,20 @@ __device__ inline void diag_block_wave(T* Ap, int ldA, T* Dd, const T* d0v, int 
 // Rank-kdim update of the lower triangle of an nrows x ncols block through LDS:
 //   Cout(r, c) = Cin(r, c) - sum_{j < kdim} A(r, j) dv(j) A(c, j),   r >= c,
 // with A(r, j) at A[j lda + r] and C(r, c) at C[c ldc + r].  The block is
-// covered by kTileM x kTileN tiles (column tiles from the left, row tiles from
-// the diagonal down), all processed in one software pipeline: 16-column slabs
-// of A (scaled by dv) for the tile rows and columns are staged in LDS
-// (double-buffered, one barrier per slab) from two register sets, so each
-// slab's global loads are issued two slabs before its MFMAs run, across tile
-// boundaries too.  Loads are unconditional at clamped addresses; rows and
-// columns past the block only reach outputs that are never written, and
-// columns past kdim are zeroed through dv.  Each wave computes a 64 x 32
-// quarter of a tile as 4 x 2 MFMA tiles.  Every thread of the workgroup must
-// call it; it ends with a barrier.
-static_assert(kTileLdsElems == 2 * kTileSlab * (kTileStrideA + kTileStrideB), "tile_update LDS size");
-template <typename T>
+// covered by kTileM x TN tiles (column tiles from the left, row tiles from the
+// diagonal down), all processed in one software pipeline: 16-column slabs of A
+// (scaled by dv) for the tile rows and columns are staged in LDS
+// (double-buffered, one barrier per slab); each step issues the next slab's
+// global loads first, runs the MFMAs of the current slab while they are in
+// flight, and stages the next slab at its end.  Loads are unconditional at
+// clamped addresses; rows and columns past the block only reach outputs that
+// are never written, and columns past kdim are zeroed through dv.  Each wave
+// computes a 64 x TN/2 quarter of a tile as 4 x TN/32 MFMA tiles.  Every
+// thread of the workgroup must call it; it ends with a barrier.
+static_assert(kTileLdsElems == 2 * kTileSlab * 2 * kTileStride, "tile update LDS size");
+template <typename T, int TN>
 struct TileRegs {
-    T a[8], b[4], d[4];
+    T a[8], b[TN / 16], d[4];
     int j0;  // first column of the slab
 };
 // global-address-space view of a workspace pointer: its loads count only on
@@ -472,21 +472,25 @@ __device__ inline P* uni(P* p) {
     return (P*)(uintptr_t)uni((int64_t)(uintptr_t)p);
 }
 
-// walk of the tiles: column tiles c0 = 0, kTileN, ...; row tiles r0 = c0, c0 + kTileM, ...
+// walk of the tiles: column tiles c0 = 0, TN, ...; row tiles r0 = c0, c0 + kTileM, ...
+template <int TN>
 struct TileCursor {
     int r0, c0;
     __device__ inline void next(int nrows) {
         r0 += kTileM;
         if (r0 >= nrows) {
-            c0 += kTileN;
+            c0 += TN;
             r0 = c0;
         }
     }
 };
-template <typename T>
+template <typename T, int TN>
 __device__ __attribute__((noinline)) void tiles_update(const T* A, const T* dv, int64_t lda, int kdim, const T* Cin,
                                                        T* Cout, int64_t ldc, int nrows, int ncols, T* lds) {
+    static_assert(TN == 64 || TN == 128, "tile width");
     typedef Mfma16<T> M;
+    constexpr int NB = TN / 64;   // B rows per loader thread and column
+    constexpr int WT = TN / 32;   // MFMA column tiles per wave
     A = uni(A);
     dv = uni(dv);
     lda = uni(lda);
@@ -495,97 +499,99 @@ __device__ __attribute__((noinline)) void tiles_update(const T* A, const T* dv, 
     Cout = uni(Cout);
     ldc = uni(ldc);
     nrows = uni(nrows);
-    ncols = uni(ncols);
-    lds = uni(lds);
+    ncols = uni(ncols);  // (lds stays as passed: its LDS address space is inferred from the caller)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = tid & 63, lj = (tid >> 6) * 4;
-    constexpr int BUF = kTileSlab * (kTileStrideA + kTileStrideB);
+    constexpr int BUF = kTileSlab * 2 * kTileStride;
     const auto* Ag = as_global(A);
     const auto* dg = as_global(dv);
-    // slab count rounded up to even, so a pair of pipeline steps never spans
-    // two tiles and the loop body has no branch (a conditional prefetch would
-    // make the compiler wait for every load in flight before each LDS store)
+    // slab count rounded up to even: slabs past kdim are zeros
     const int ns = 2 * ((kdim + 2 * kTileSlab - 1) / (2 * kTileSlab));
     // load side of the pipeline: tile and slab of the next load; once every
     // slab is loaded it stays on the last one (loaded again, never computed)
-    TileCursor lc{0, 0};
+    TileCursor<TN> lc{0, 0};
     int ls = 0;
-    auto load = [&](TileRegs<T>& R) {
+    auto load = [&](TileRegs<T, TN>& R) {
         const int j0 = kTileSlab * ls;
         R.j0 = j0;
         const int ra0 = min(lc.r0 + lr, nrows - 1), ra1 = min(lc.r0 + lr + 64, nrows - 1);
-        const int rb0 = min(lc.c0 + lr, ncols - 1);
+        int rb[NB];
+#pragma unroll
+        for (int h = 0; h < NB; ++h) rb[h] = min(lc.c0 + lr + 64 * h, ncols - 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int j = min(j0 + lj + q, kdim - 1);
             const auto* Aj = Ag + (int64_t)j * lda;
             R.a[q] = Aj[ra0];
             R.a[4 + q] = Aj[ra1];
-            R.b[q] = Aj[rb0];
+#pragma unroll
+            for (int h = 0; h < NB; ++h) R.b[4 * h + q] = Aj[rb[h]];
             R.d[q] = dg[j];
         }
         // advance with selects only: a branch here would split the loop body
         // and make the compiler drain the loads in flight
         const bool wrap = ls + 1 == ns;
         const bool colwrap = lc.r0 + kTileM >= nrows;
-        const int nc0 = colwrap ? lc.c0 + kTileN : lc.c0;
+        const int nc0 = colwrap ? lc.c0 + TN : lc.c0;
         const int nr0 = colwrap ? nc0 : lc.r0 + kTileM;
         const bool more = nc0 < ncols;
         lc.r0 = (wrap && more) ? nr0 : lc.r0;
         lc.c0 = (wrap && more) ? nc0 : lc.c0;
         ls = wrap ? (more ? 0 : ns - 1) : ls + 1;
     };
-    auto store = [&](const TileRegs<T>& R, int buf) {
+    auto store = [&](const TileRegs<T, TN>& R, int buf) {
         T* As = lds + buf * BUF;
-        T* Bs = As + kTileSlab * kTileStrideA;
+        T* Bs = As + kTileSlab * kTileStride;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const T dq = R.j0 + lj + q < kdim ? R.d[q] : T(0);  // columns past kdim
-            As[(lj + q) * kTileStrideA + lr] = R.a[q] * dq;
-            As[(lj + q) * kTileStrideA + lr + 64] = R.a[4 + q] * dq;
-            Bs[(lj + q) * kTileStrideB + lr] = R.b[q];
+            As[(lj + q) * kTileStride + lr] = R.a[q] * dq;
+            As[(lj + q) * kTileStride + lr + 64] = R.a[4 + q] * dq;
+#pragma unroll
+            for (int h = 0; h < NB; ++h) Bs[(lj + q) * kTileStride + lr + 64 * h] = R.b[4 * h + q];
         }
     };
-    typename M::V acc[4][2];
+    typename M::V acc[4][WT];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int w2 = 0; w2 < 2; ++w2) acc[u][w2] = M::zero();
-    const int wr = 64 * (wave >> 1), wc = 32 * (wave & 1);
+        for (int w2 = 0; w2 < WT; ++w2) acc[u][w2] = M::zero();
+    const int wr = 64 * (wave >> 1), wc = (TN / 2) * (wave & 1);
     auto compute = [&](int buf) {
         const T* As = lds + buf * BUF;
-        const T* Bs = As + kTileSlab * kTileStrideA;
+        const T* Bs = As + kTileSlab * kTileStride;
 #pragma unroll
         for (int ks = 0; ks < kTileSlab / 4; ++ks) {
             const int kk = 4 * ks + (lane >> 4);
-            T av[4], bv[2];
+            T av[4], bv[WT];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) av[u] = As[kk * kTileStrideA + wr + 16 * u + (lane & 15)];
+            for (int u = 0; u < 4; ++u) av[u] = As[kk * kTileStride + wr + 16 * u + (lane & 15)];
 #pragma unroll
-            for (int w2 = 0; w2 < 2; ++w2) bv[w2] = Bs[kk * kTileStrideB + wc + 16 * w2 + (lane & 15)];
+            for (int w2 = 0; w2 < WT; ++w2) bv[w2] = Bs[kk * kTileStride + wc + 16 * w2 + (lane & 15)];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int w2 = 0; w2 < 2; ++w2) acc[u][w2] = M::mma(av[u], bv[w2], acc[u][w2]);
+                for (int w2 = 0; w2 < WT; ++w2) acc[u][w2] = M::mma(av[u], bv[w2], acc[u][w2]);
         }
     };
     // one pipeline step: the next slab's loads are issued first, the MFMAs of
     // LDS buffer buf run while they are in flight, and the slab is staged into
     // the other buffer at the end (no load stays in flight across steps)
-    auto step = [&](int buf, TileRegs<T>& R) {
+    auto step = [&](int buf, TileRegs<T, TN>& R) {
         load(R);
         __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
         compute(buf);
+        __builtin_amdgcn_sched_barrier(0);  // and the staging (which waits for it) behind them
         store(R, buf ^ 1);
         __syncthreads();
     };
-    TileRegs<T> R0;
+    TileRegs<T, TN> R0;
     if (ns > 0) {  // kdim = 0: Cout = Cin
         load(R0);
         store(R0, 0);
     }
     __syncthreads();
-    for (TileCursor cc{0, 0}; cc.c0 < ncols; cc.next(nrows)) {
+    for (TileCursor<TN> cc{0, 0}; cc.c0 < ncols; cc.next(nrows)) {
         for (int s = 0; s < ns; s += 2) {
             step(0, R0);
             step(1, R0);
@@ -594,7 +600,7 @@ __device__ __attribute__((noinline)) void tiles_update(const T* A, const T* dv, 
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int w2 = 0; w2 < 2; ++w2) {
+            for (int w2 = 0; w2 < WT; ++w2) {
                 const int col = wc + 16 * w2 + (lane & 15);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -620,19 +626,27 @@ __device__ __attribute__((noinline)) void factorize_glb(const RveCtx& c, Smem& s
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     T* W = reinterpret_cast<T*>(sm.red);  // 16 x 16
+    nrhs = uni(nrhs);
+    double* const cL = uni(c.L);
+    double* const cU = uni(c.U);
+    double* const cS = uni(c.S);
     PROF_T0();
-    for (int s = 0; s < pl.nfront; ++s) {
+    const int nfront = uni(pl.nfront);
+    for (int s = 0; s < nfront; ++s) {
         const DevFront fr = pl.fronts[s];
-        const int m = fr.m, p = fr.p, mu = m - p;
-        const int32_t* rows = pl.rows + fr.rows_off;
-        T* Fp = reinterpret_cast<T*>(c.L + fr.L_off);
-        T* Dg = reinterpret_cast<T*>(c.L + fr.D_off);
-        double* y = c.L + fr.y_off;
-        T* Us = reinterpret_cast<T*>(c.S);
-        double* rus = urhs<T>(c.S, mu);
-        // 1. zero the panel and the scratch update matrix, load the pivot rhs
-        for (int t = threadIdx.x; t < m * p; t += NT) Fp[t] = T(0);
-        for (int t = threadIdx.x; t < mu * mu; t += NT) Us[t] = T(0);
+        const int m = uni(fr.m), p = uni(fr.p), mu = m - p;
+        const int32_t* rows = uni(pl.rows + fr.rows_off);
+        T* Fp = reinterpret_cast<T*>(cL + uni(fr.L_off));
+        T* Dg = reinterpret_cast<T*>(cL + uni(fr.D_off));
+        double* y = cL + uni(fr.y_off);
+        T* Us = reinterpret_cast<T*>(cS);
+        double* rus = urhs<T>(cS, mu);
+        // 1. zero the parts that are read later (the panel on and below its
+        //    diagonal, the lower triangle of U_s), load the pivot rhs
+        for (int j = wave; j < p; j += NWAVE)
+            for (int i = j + lane; i < m; i += 64) Fp[(int64_t)j * m + i] = T(0);
+        for (int k = wave; k < mu; k += NWAVE)
+            for (int i = k + lane; i < mu; i += 64) Us[(int64_t)k * mu + i] = T(0);
         for (int t = threadIdx.x; t < mu * nrhs; t += NT) rus[t] = 0.0;
         for (int t = threadIdx.x; t < p * nrhs; t += NT) {
             int j = t % p, col = t / p;
@@ -705,7 +719,7 @@ __device__ __attribute__((noinline)) void factorize_glb(const RveCtx& c, Smem& s
             const int kb64 = min(64, p - K64);
             if (K64 > 0) {
                 T* Ct = Fp + (int64_t)K64 * m + K64;
-                tiles_update<T>(Fp + K64, Dg, m, K64, Ct, Ct, m, m - K64, kb64, lds);
+                tiles_update<T, 64>(Fp + K64, Dg, m, K64, Ct, Ct, m, m - K64, kb64, lds);
             }
             for (int K = K64; K < K64 + kb64; K += 16) {
                 const int kb = min(16, p - K);
@@ -716,16 +730,28 @@ __device__ __attribute__((noinline)) void factorize_glb(const RveCtx& c, Smem& s
                     for (int t0 = 2 * wave; t0 < nt; t0 += 2 * NWAVE) {
                         typename M::V acc[2] = {M::zero(), M::zero()};
                         const int cb = K + (lane & 15);
-                        for (int j0 = K64; j0 < K; j0 += 4) {
-                            const int j = j0 + (lane >> 4);
-                            const T* colj = Fp + (int64_t)j * m;
-                            const T dj = Dg[j];
-                            const T bv = ((lane & 15) < kb) ? colj[cb] : T(0);
+                        // at most 48 earlier columns in the block: unrolled to 12
+                        // k-steps so that all operand loads are issued together
+                        T av[12][2], bv[12];
 #pragma unroll
-                            for (int u = 0; u < 2; ++u) {
-                                const int ra = K + 16 * (t0 + u) + (lane & 15);
-                                const T av = (ra < m) ? colj[ra] * dj : T(0);
-                                acc[u] = M::mma(av, bv, acc[u]);
+                        for (int q = 0; q < 12; ++q) {
+                            const int j = min(K64 + 4 * q + (lane >> 4), K - 1);
+                            const T* colj = Fp + (int64_t)j * m;
+                            bv[q] = colj[min(cb, m - 1)];
+                            const T dj = Dg[j];
+#pragma unroll
+                            for (int u = 0; u < 2; ++u)
+                                av[q][u] = colj[min(K + 16 * (t0 + u) + (lane & 15), m - 1)] * dj;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 12; ++q) {
+                            if (K64 + 4 * q < K) {
+                                const bool okb = (lane & 15) < kb;
+#pragma unroll
+                                for (int u = 0; u < 2; ++u) {
+                                    const bool oka = K + 16 * (t0 + u) + (lane & 15) < m;
+                                    acc[u] = M::mma(oka ? av[q][u] : T(0), okb ? bv[q] : T(0), acc[u]);
+                                }
                             }
                         }
                         const int cc = lane & 15;
@@ -772,8 +798,9 @@ __device__ __attribute__((noinline)) void factorize_glb(const RveCtx& c, Smem& s
                 for (int t = tid; t < (m - R0) * nrhs; t += NT) {
                     const int i = R0 + t % (m - R0), q = t / (m - R0);
                     double acc = 0.0;
-                    for (int cc = 0; cc < kb; ++cc)
-                        acc += (double)Fp[(int64_t)(K + cc) * m + i] * y[(int64_t)q * p + K + cc];
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc)
+                        if (cc < kb) acc += (double)Fp[(int64_t)(K + cc) * m + i] * y[(int64_t)q * p + K + cc];
                     if (i < p) y[(int64_t)q * p + i] -= acc;
                     else rus[(int64_t)q * mu + (i - p)] -= acc;
                 }
@@ -784,9 +811,9 @@ __device__ __attribute__((noinline)) void factorize_glb(const RveCtx& c, Smem& s
         // 5. Schur complement U = U_s - L21 D L21^T over the tiles of its lower
         //    triangle, written straight onto the update stack with its rhs rows
         if (mu > 0) {
-            T* dst = reinterpret_cast<T*>(c.U + fr.U_off);
-            double* drhs = urhs<T>(c.U + fr.U_off, mu);
-            tiles_update<T>(Fp + p, Dg, m, p, Us, dst, mu, mu, mu, lds);
+            T* dst = reinterpret_cast<T*>(cU + uni(fr.U_off));
+            double* drhs = urhs<T>(cU + uni(fr.U_off), mu);
+            tiles_update<T, 128>(Fp + p, Dg, m, p, Us, dst, mu, mu, mu, lds);
             for (int t = tid; t < mu * nrhs; t += NT) drhs[t] = rus[t];
         }
         __syncthreads();
@@ -804,12 +831,15 @@ template <int D, int NRHS, typename T>
 __device__ __attribute__((noinline)) void forward_glb(const RveCtx& c, Smem& sm, double* b) {
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int s = 0; s < pl.nfront; ++s) {
+    double* const cL = uni(c.L);
+    b = uni(b);
+    const int nfront = uni(pl.nfront);
+    for (int s = 0; s < nfront; ++s) {
         const DevFront fr = pl.fronts[s];
-        const int m = fr.m, p = fr.p;
-        const int32_t* rows = pl.rows + fr.rows_off;
-        const T* Fp = reinterpret_cast<const T*>(c.L + fr.L_off);
-        double* y = c.L + fr.y_off;
+        const int m = uni(fr.m), p = uni(fr.p);
+        const int32_t* rows = uni(pl.rows + fr.rows_off);
+        const T* Fp = reinterpret_cast<const T*>(cL + uni(fr.L_off));
+        double* y = cL + uni(fr.y_off);
         for (int t = tid; t < p * NRHS; t += NT) {
             const int j = t % p, q = t / p;
             y[t] = b[(int64_t)rows[j] * NRHS + q];
@@ -867,13 +897,15 @@ __device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& s
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int t = tid; t < D * NRHS; t += NT) xo[t] = 0.0;  // pinned node
     __syncthreads();
-    for (int s = pl.nfront - 1; s >= 0; --s) {
+    double* const cL = uni(c.L);
+    xo = uni(xo);
+    for (int s = uni(pl.nfront) - 1; s >= 0; --s) {
         const DevFront fr = pl.fronts[s];
-        const int m = fr.m, p = fr.p;
-        const int32_t* rows = pl.rows + fr.rows_off;
-        const T* Fp = reinterpret_cast<const T*>(c.L + fr.L_off);
-        const T* Dg = reinterpret_cast<const T*>(c.L + fr.D_off);
-        double* y = c.L + fr.y_off;
+        const int m = uni(fr.m), p = uni(fr.p);
+        const int32_t* rows = uni(pl.rows + fr.rows_off);
+        const T* Fp = reinterpret_cast<const T*>(cL + uni(fr.L_off));
+        const T* Dg = reinterpret_cast<const T*>(cL + uni(fr.D_off));
+        double* y = cL + uni(fr.y_off);
         for (int j = tid; j < p; j += NT) {
             const double rd = 1.0 / (double)Dg[j];
             double v[NRHS];

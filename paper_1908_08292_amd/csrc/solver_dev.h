@@ -70,11 +70,11 @@ struct SolveArgs {
 // LDS available to the front buffer (packed front + m x d^2 rhs rows)
 constexpr int kLdsBytesMax = 160 * 1024;
 
-// tiles of the global-front updates: kTileM x kTileN outputs per pass, staged
-// 16-column slabs of A (kTileM rows) and B (kTileN rows) in two LDS buffers;
-// row strides 144 and 80 (= 16 mod 32) put the four lane groups of an MFMA
-// operand read on distinct LDS banks
-constexpr int kTileM = 128, kTileN = 64, kTileSlab = 16, kTileStrideA = 144, kTileStrideB = 80;
-constexpr int kTileLdsElems = 2 * kTileSlab * (kTileStrideA + kTileStrideB);
+// tiles of the global-front updates: kTileM rows x (64 or 128) columns per
+// pass; two LDS buffers of a 16-column slab of A (kTileM rows) and B (up to
+// 128 rows), row stride 144 elements (= 16 mod 32: the four lane groups of an
+// MFMA operand read hit distinct LDS banks)
+constexpr int kTileM = 128, kTileSlab = 16, kTileStride = 144;
+constexpr int kTileLdsElems = 2 * kTileSlab * 2 * kTileStride;
 
 }  // namespace fehmm
