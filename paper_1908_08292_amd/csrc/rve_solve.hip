@@ -660,10 +660,16 @@ __device__ __attribute__((noinline)) void factorize_glb(const RveCtx& c, Smem& s
             const int k = (t % (D * D)) / D, l = t % D;
             const int r = kp.row_node * D + k, col = kp.col_node * D + l;
             if (r < col) continue;
+            // at most 2^d elements share a node pair: every contribution's loads
+            // are issued together (clamped, zeros selected; the sum order is kept)
+            KContrib cbs[NEN];
+#pragma unroll
+            for (int q = 0; q < NEN; ++q) cbs[q] = pl.kcontrib[kp.c_begin + min(q, kp.c_count - 1)];
             double v = 0;
-            for (int q = 0; q < kp.c_count; ++q) {
-                const KContrib cb = pl.kcontrib[kp.c_begin + q];
-                v += c.ke[((int64_t)cb.elem * ND + cb.lb * D + k) * ND + cb.la * D + l];
+#pragma unroll
+            for (int q = 0; q < NEN; ++q) {
+                const double kv = c.ke[((int64_t)cbs[q].elem * ND + cbs[q].lb * D + k) * ND + cbs[q].la * D + l];
+                v += (q < kp.c_count) ? kv : 0.0;
             }
             Fp[(int64_t)col * m + r] = (T)v;
             if (r == col) Dg[col] = (T)v;
@@ -977,6 +983,61 @@ __device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& s
 // A[l%16][l/16], B[l/16][l%16], D row = l/16 + 4 v, col = l%16).
 
 
+// Original entries of an LDS front from the element matrices (one gather level)
+// and the extend-add of a child's packed update matrix: four strides of the
+// list per pass, every index load first, then every value load (clamped
+// addresses, zeros selected), then the stores, so a pass costs one or two
+// memory round trips for four strides of entries.  first / stride: the
+// caller's lane (wave-level) or thread (workgroup-level) numbering.
+template <int NEN, typename T>
+__device__ inline void gather_original(const DevPlan& pl, const double* ke, int a0, int a1, int first, int stride,
+                                       T* F, int m, double* Dg) {
+    for (int t0 = a0 + first; t0 < a1; t0 += 4 * stride) {
+        int rc[4], src[4][NEN];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = min(t0 + u * stride, a1 - 1);
+            rc[u] = pl.asm_rc[t];
+#pragma unroll
+            for (int q = 0; q < NEN; ++q) src[u][q] = pl.asm_src[(int64_t)t * NEN + q];
+        }
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[u] = 0.0;
+#pragma unroll
+            for (int q = 0; q < NEN; ++q) {
+                const double kv = ke[max(src[u][q], 0)];
+                v[u] += (src[u][q] >= 0) ? kv : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (t0 + u * stride < a1) {
+                const int r = rc[u] >> 16, col = rc[u] & 0xffff;
+                F[cpk(col, m) + r - col] = v[u];
+                if (r == col) Dg[col] = v[u];
+            }
+        }
+    }
+}
+template <typename T>
+__device__ inline void extend_add_packed(const int32_t* ea, const T* Uc, int nu, int first, int stride, T* F) {
+    for (int t0 = first; t0 < nu; t0 += 4 * stride) {
+        int e[4];
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = min(t0 + u * stride, nu - 1);
+            e[u] = ea[t];
+            v[u] = Uc[t];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t0 + u * stride < nu) F[e[u]] += v[u];
+    }
+}
+
 // One small front (m <= 64) processed by a single wave: lane i owns front row i.
 // Assembly as in the workgroup path, then a right-looking LDL^T sweep over the
 // p pivots done in place in LDS (the wave's slice); within a wave LDS accesses
@@ -999,18 +1060,7 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
         rl[t] = (i < p) ? c.rhs[(int64_t)rows[i] * NRHS + col] : 0.0;
     }
     __builtin_amdgcn_wave_barrier();
-    for (int t = fr.asm_begin + lane; t < fr.asm_end; t += 64) {
-        const int rc = pl.asm_rc[t];
-        int src[NEN];
-#pragma unroll
-        for (int q = 0; q < NEN; ++q) src[q] = pl.asm_src[(int64_t)t * NEN + q];
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < NEN; ++q) v += (src[q] >= 0) ? c.ke[src[q]] : 0.0;
-        const int r = rc >> 16, col = rc & 0xffff;
-        F[cpk(col, m) + r - col] = v;
-        if (r == col) Dg[col] = v;
-    }
+    gather_original<NEN>(pl, c.ke, fr.asm_begin, fr.asm_end, lane, 64, F, m, Dg);
     __builtin_amdgcn_wave_barrier();
     for (int q = fr.child_begin; q < fr.child_end; ++q) {
         const DevFront ch = pl.fronts[pl.children[q]];
@@ -1020,7 +1070,7 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
         const int nu = cpk(mc, mc);
         const T* ruc = Uc + nu;
         const int32_t* ea = pl.ea_dst + ch.ea_off;
-        for (int t = lane; t < nu; t += 64) F[ea[t]] += Uc[t];
+        extend_add_packed(ea, Uc, nu, lane, 64, F);
         for (int t = lane; t < mc * NRHS; t += 64) {
             const int i = t % mc, col = t / mc;
             rl[col * m + rel[i]] += ruc[(int64_t)col * mc + i];
@@ -1222,18 +1272,7 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* r
         }
         __syncthreads();
         // original entries: one gather level, every source load in flight at once
-        for (int t = fr.asm_begin + tid; t < fr.asm_end; t += NT) {
-            const int rc = pl.asm_rc[t];
-            int src[NEN];
-#pragma unroll
-            for (int q = 0; q < NEN; ++q) src[q] = pl.asm_src[(int64_t)t * NEN + q];
-            double v = 0.0;
-#pragma unroll
-            for (int q = 0; q < NEN; ++q) v += (src[q] >= 0) ? c.ke[src[q]] : 0.0;
-            const int r = rc >> 16, col = rc & 0xffff;
-            F[cpk(col, m) + r - col] = v;
-            if (r == col) Dg[col] = v;
-        }
+        gather_original<NEN>(pl, c.ke, fr.asm_begin, fr.asm_end, tid, NT, F, m, Dg);
         __syncthreads();
         for (int q = fr.child_begin; q < fr.child_end; ++q) {
             const DevFront ch = pl.fronts[pl.children[q]];
@@ -1243,7 +1282,7 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* r
             const int nu = cpk(mc, mc);
             const T* ruc = Uc + nu;
             const int32_t* ea = pl.ea_dst + ch.ea_off;
-            for (int t = tid; t < nu; t += NT) F[ea[t]] += Uc[t];
+            extend_add_packed(ea, Uc, nu, tid, NT, F);
             for (int t = tid; t < mc * nrhs; t += NT) {
                 const int i = t % mc, col = t / mc;
                 rl[col * m + rel[i]] += ruc[(int64_t)col * mc + i];
