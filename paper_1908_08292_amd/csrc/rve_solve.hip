@@ -1021,6 +1021,19 @@ __device__ inline void gather_original(const DevPlan& pl, const double* ke, int 
         }
     }
 }
+// global -> LDS copy, eight strides per pass: all loads first, then all stores
+// (the compiler does not move a load past a store that may alias it)
+template <typename T>
+__device__ inline void copy_in(T* dst, const T* src, int n, int first, int stride) {
+    for (int t0 = first; t0 < n; t0 += 8 * stride) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[min(t0 + u * stride, n - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (t0 + u * stride < n) dst[t0 + u * stride] = v[u];
+    }
+}
 template <typename T>
 __device__ inline void extend_add_packed(const int32_t* ea, const T* Uc, int nu, int first, int stride, T* F) {
     for (int t0 = first; t0 < nu; t0 += 4 * stride) {
@@ -1414,8 +1427,7 @@ __device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
     const double* Dg = c.L + fr.D_off;
     const double* yg = c.L + fr.y_off;
     const int lp = cpk(p, m);
-#pragma unroll 8
-    for (int t = lane; t < lp; t += 64) S[t] = Lg[t];
+    copy_in(S, Lg, lp, lane, 64);
     double v[NRHS], xs[NRHS];
 #pragma unroll
     for (int q = 0; q < NRHS; ++q) {
@@ -1470,14 +1482,14 @@ __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* r
         const T* Lp;
         double* vb;
         if constexpr (sizeof(T) == sizeof(double)) {
-            for (int t = tid; t < lp; t += NT) F[t] = Lg[t];
+            copy_in(F, Lg, lp, tid, NT);
             Lp = F;
             vb = reinterpret_cast<double*>(rl);
         } else {
             // FP32 panel staged after the FP64 scratch when both fit the front region
             const int vneed = 2 * (m * NRHS + 3 * p);
             if (vneed + lp <= front_elems) {
-                for (int t = tid; t < lp; t += NT) F[vneed + t] = Lg[t];
+                copy_in(F + vneed, Lg, lp, tid, NT);
                 Lp = F + vneed;
             } else {
                 Lp = Lg;
@@ -1597,7 +1609,7 @@ __device__ __noinline__ void forward_lds(const RveCtx& c, Smem& sm, T* F, double
             const int lp = cpk(p, m);
             if (vneed + lp <= front_elems) {
                 T* Ls = F + vneed;
-                for (int t = tid; t < lp; t += NT) Ls[t] = Lp[t];
+                copy_in(Ls, Lp, lp, tid, NT);
                 Lp = Ls;
             }
         }
