@@ -984,10 +984,10 @@ __device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& s
 
 
 // Original entries of an LDS front from the element matrices (one gather level)
-// and the extend-add of a child's packed update matrix: four strides of the
-// list per pass, every index load first, then every value load (clamped
-// addresses, zeros selected), then the stores, so a pass costs one or two
-// memory round trips for four strides of entries.  first / stride: the
+// and the extend-add of a child's packed update matrix: four (gather) or eight
+// (extend-add) strides of the list per pass, every index load first, then every
+// value load (clamped addresses, zeros selected), then the stores, so a pass
+// costs one or two memory round trips for all its strides.  first / stride: the
 // caller's lane (wave-level) or thread (workgroup-level) numbering.
 template <int NEN, typename T>
 __device__ inline void gather_original(const DevPlan& pl, const double* ke, int a0, int a1, int first, int stride,
@@ -1036,17 +1036,18 @@ __device__ inline void copy_in(T* dst, const T* src, int n, int first, int strid
 }
 template <typename T>
 __device__ inline void extend_add_packed(const int32_t* ea, const T* Uc, int nu, int first, int stride, T* F) {
-    for (int t0 = first; t0 < nu; t0 += 4 * stride) {
-        int e[4];
-        T v[4];
+    constexpr int U = 8;
+    for (int t0 = first; t0 < nu; t0 += U * stride) {
+        int e[U];
+        T v[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int t = min(t0 + u * stride, nu - 1);
             e[u] = ea[t];
             v[u] = Uc[t];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < U; ++u)
             if (t0 + u * stride < nu) F[e[u]] += v[u];
     }
 }
