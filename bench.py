@@ -162,7 +162,7 @@ def time_solves(s, opts, stream, steps, warmup):
 
 
 def surrogate_bench(macro_steps):
-    """configs[4]: the surrogate of the 64 x 64 plate problem's RVE."""
+    """The surrogate of the 64 x 64 plate problem's 16 x 16 RVE: training, evaluation, audit, macro steps."""
     import torch
 
     from paper_1908_08292_amd import api, fehmm, rve, surrogate
@@ -292,8 +292,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the RVE batch would be sharded by macro elements "
-              "across GPUs; see DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (the RVE batch would be sharded by macro elements "
+              "across GPUs); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -48,7 +48,7 @@ extern "C" {
 #define RVE_EINVAL (-1)       /* bad argument (NULL, size, range, destroyed handle) */
 #define RVE_ENOMEM (-2)       /* host or device allocation failed */
 #define RVE_EHIP (-3)         /* a HIP runtime call failed */
-#define RVE_EUNSUPPORTED (-4) /* valid request this build does not support */
+#define RVE_EUNSUPPORTED (-4) /* valid request this library does not support */
 
 /* ---- per-RVE status -------------------------------------------------------- */
 #define RVE_S_CONVERGED 0
