@@ -426,8 +426,11 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
         for (int k = 0; k < 2; ++k) {
             const int64_t es = k == 0 ? 8 : 4;
             int64_t elems = std::max(b->lds_front[k] + rl, NWAVE_ * b->wave_slice);
-            if (glb) elems = std::max<int64_t>(elems, kTileLdsElems);  // global fronts: staged tile slabs
-            b->dyn_bytes[k] = (size_t)(elems * es);
+            int64_t bytes = elems * es;
+            // global fronts: staged tile slabs, FP64-sized in both kernels (the
+            // condensation factorization of global-front plans is FP64)
+            if (glb) bytes = std::max<int64_t>(bytes, (int64_t)kTileLdsElems * 8);
+            b->dyn_bytes[k] = (size_t)bytes;
         }
     }
     auto rnd = [](int64_t x) { return (x + 31) / 32 * 32; };

@@ -1903,31 +1903,26 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
                 __syncthreads();
                 node_gather<D>(c, c.re, D2, c.rhs, 1.0);
                 __syncthreads();
+                // the condensation factorization: in the factor type for LDS plans
+                // (whose LDS budget is sized for it), in FP64 for global-front plans
+                // (direct Schur form below, no refinement needed)
                 if (c.plan->lds_ok) factorize_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
-                else factorize_glb<D, T>(c, sm, D2, dynF);
+                else factorize_glb<D, double>(c, sm, D2, dynRaw);
                 if (sm.flag) {
                     status = 3;
-                } else if (IR) {
+                } else if (IR && c.plan->lds_ok) {
                     // X ~ K^-1 Y from the FP32 factors, refined ir_max_tan times against
                     // the FP64 tangent; then the stationary (second-order) form
                     //   Abar = <A> - Y^T X - X^T r,  r = Y - K X,
                     // whose error is (X - X*)^T K (X - X*) (energy-norm error squared)
                     double* X = c.re;  // element Y no longer needed: [dof][D2]
-                    if (c.plan->lds_ok)
-                        backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front, a.wave_slice);
-                    else
-                        backsolve_glb<D, D2, T>(c, sm, X);
+                    backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front, a.wave_slice);
                     for (int ref = 0;; ++ref) {
                         residual_ke<D, D2>(c, c.rhs, X, ir1);
                         __syncthreads();
                         if (ref == a.ir_max_tan) break;
-                        if (c.plan->lds_ok) {
-                            forward_lds<D, D2, T>(c, sm, dynF, ir1, a.lds_front);
-                            backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front, a.wave_slice);
-                        } else {
-                            forward_glb<D, D2, T>(c, sm, ir1);
-                            backsolve_glb<D, D2, T>(c, sm, ir2);
-                        }
+                        forward_lds<D, D2, T>(c, sm, dynF, ir1, a.lds_front);
+                        backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front, a.wave_slice);
                         for (int t = threadIdx.x; t < ndof * D2; t += NT) X[t] += ir2[t];
                         __syncthreads();
                     }
