@@ -198,6 +198,29 @@ def test_parity_fp32_ir_3d_uneven_batch():
     compare_loose_iters(3, wl.n, wl.radius, wl.ratio, wl.F, out)
 
 
+def test_parity_3d_12cubed_both_precisions():
+    """Two 12^3 RVEs (fronts up to 1221 rows: many 128 x 128 tiles, several
+    64-column panel blocks, multi-tile Schur complements) in FP64 and with FP32
+    factors, against one oracle solve each (about 20 s per RVE on one core)."""
+    wl = workloads.rve3d(2, sizes=(12,), seed=1800)
+    print("case 3d n=12 B=2, fp64 and fp32+ir", flush=True)
+    out64 = run_gpu(3, wl.n, wl.radius, wl.ratio, wl.F)
+    out32 = run_gpu(3, wl.n, wl.radius, wl.ratio, wl.F, opts=rve.default_opts(precision=rve.PREC_FP32_IR))
+    for b in range(2):
+        ref = run_oracle(3, 12, wl.radius[b], wl.ratio[b], wl.F[b])
+        mu_max = oracle.two_phase_lame(wl.ratio[b])[:, 1].max()
+        for out, exact_iters in ((out64, True), (out32, False)):
+            assert out["status"][b] == ref["status"] == 0
+            if exact_iters:
+                assert out["iters"][b] == ref["iters"]
+            else:
+                assert abs(int(out["iters"][b]) - ref["iters"]) <= 1
+            eP = rel(out["P"][b], ref["P"], 1e-12 * mu_max)
+            eA = rel(out["A"][b], ref["A"], 1e-12 * mu_max)
+            print(f"  rve {b} {'fp64' if exact_iters else 'fp32+ir'}: P rel {eP:.2e}, A rel {eA:.2e}", flush=True)
+            assert eP <= P_TOL and eA <= A_TOL
+
+
 def test_infeasible_warm_start_matches_oracle_cold_start():
     """Warm starts that fold an element under the new Fbar are discarded on the
     GPU as in the oracle: results and iteration counts equal the cold start."""
