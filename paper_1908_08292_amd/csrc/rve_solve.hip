@@ -1091,103 +1091,57 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
         }
         __builtin_amdgcn_wave_barrier();
     }
-    T* W = rl + m * NRHS;  // 16 x 16 scratch of this wave's slice
     for (int K = 0; K < p; K += 16) {
         const int kb = min(16, p - K);
-        // diagonal block: lane r < kb holds row r; readlane broadcast of pivots/multipliers
+        // the 16 columns of the block by elimination on every front row at once
+        // (lane = row, rows below the block included): readlane broadcasts of
+        // the pivot and of the block rows' multipliers; the rows below leave
+        // with their L entries and forward-substituted rhs
         {
-            const bool ownr = lane < kb;
+            const int r = lane;
+            const bool act = r >= K && r < m;
             double row[16];
             double yv[NRHS];
 #pragma unroll
             for (int cc = 0; cc < 16; ++cc)
-                row[cc] = (ownr && cc < kb && cc <= lane) ? F[cpk(K + cc, m) + lane - cc] : 0.0;
+                row[cc] = (act && cc < kb && K + cc <= r) ? (double)F[cpk(K + cc, m) + r - K - cc] : 0.0;
 #pragma unroll
-            for (int q = 0; q < NRHS; ++q) yv[q] = ownr ? rl[q * m + K + lane] : 0.0;
-            const double d0 = ownr ? Dg[K + lane] : 1.0;
-            double dpiv = 1.0;
+            for (int q = 0; q < NRHS; ++q) yv[q] = act ? rl[q * m + r] : 0.0;
+            const double d0 = (act && r < K + kb) ? Dg[r] : 1.0;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 if (j < kb) {
-                    const double piv = readlane_d(row[j], j);
+                    const double piv = readlane_d(row[j], K + j);
                     const double rp = 1.0 / piv;
-                    if (lane == j) {
-                        dpiv = piv;
-                        if (!(fabs(piv) > 1e-14 * fabs(d0)) || !isfinite(piv)) sm.flag = 2;
-                    }
-                    const double l = (lane > j) ? row[j] * rp : 0.0;
+                    if (r == K + j && (!(fabs(piv) > 1e-14 * fabs(d0)) || !isfinite(piv))) sm.flag = 2;
+                    const bool below = act && r > K + j;
+                    const double l = below ? row[j] * rp : 0.0;
                     const double lpv = l * piv;
 #pragma unroll
                     for (int cc = j + 1; cc < 16; ++cc) {
                         if (cc < kb) {
-                            const double lc = readlane_d(l, cc);
-                            if (cc <= lane) row[cc] -= lpv * lc;
+                            const double lc = readlane_d(l, K + cc);
+                            if (act && K + cc <= r) row[cc] -= lpv * lc;
                         }
                     }
 #pragma unroll
                     for (int q = 0; q < NRHS; ++q) {
-                        const double yj = readlane_d(yv[q], j);
-                        if (lane > j) yv[q] -= l * yj;
+                        const double yj = readlane_d(yv[q], K + j);
+                        if (below) yv[q] -= l * yj;
                     }
-                    if (lane > j) row[j] = l;
+                    if (below) row[j] = l;
                 }
             }
-            double inv[16];
-#pragma unroll
-            for (int cc = 0; cc < 16; ++cc) inv[cc] = (cc == lane) ? 1.0 : 0.0;
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                if (e < kb) {
-                    const double le = (lane > e) ? row[e] : 0.0;
-#pragma unroll
-                    for (int cc = 0; cc <= e; ++cc) {
-                        const double ie = readlane_d(inv[cc], e);
-                        inv[cc] -= le * ie;
-                    }
-                }
-            }
-            const double rdp = 1.0 / dpiv;
 #pragma unroll
             for (int cc = 0; cc < 16; ++cc)
-                if (lane < 16) W[cc * 16 + lane] = (ownr && cc < kb && cc <= lane) ? inv[cc] * rdp : 0.0;
-#pragma unroll
-            for (int cc = 0; cc < 16; ++cc)
-                if (ownr && cc < kb && cc <= lane) F[cpk(K + cc, m) + lane - cc] = (cc == lane) ? dpiv : row[cc];
+                if (act && cc < kb && K + cc <= r) F[cpk(K + cc, m) + r - K - cc] = (T)row[cc];
 #pragma unroll
             for (int q = 0; q < NRHS; ++q)
-                if (ownr) rl[q * m + K + lane] = yv[q];
+                if (act) rl[q * m + r] = yv[q];
         }
         __builtin_amdgcn_wave_barrier();
-        // rows below: L = F W (MFMA), then their rhs
         const int R0 = K + kb;
         const int nRT = (m - R0 + 15) >> 4;
-        for (int tr = 0; tr < nRT; ++tr) {
-            const int ra = R0 + 16 * tr + (lane & 15);
-            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int kk = 4 * ks + (lane >> 4);
-                const double av = (kk < kb && ra < m) ? F[cpk(K + kk, m) + ra - K - kk] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[kk * 16 + (lane & 15)], acc, 0, 0, 0);
-            }
-            const int cc = lane & 15;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int rr = R0 + 16 * tr + (lane >> 4) + 4 * v;
-                if (rr < m && cc < kb) F[cpk(K + cc, m) + rr - K - cc] = acc[v];
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int rr = R0 + lane; rr < m; rr += 64) {
-#pragma unroll
-            for (int q = 0; q < NRHS; ++q) {
-                double v = rl[q * m + rr];
-#pragma unroll
-                for (int c2 = 0; c2 < 16; ++c2)
-                    if (c2 < kb) v -= F[cpk(K + c2, m) + rr - K - c2] * rl[q * m + K + c2];
-                rl[q * m + rr] = v;
-            }
-        }
         // trailing lower triangle -= L D L^T (MFMA), two independent tiles in flight
         const int nT = nRT;
         const int ntile = nT * (nT + 1) / 2;
