@@ -66,7 +66,7 @@ typedef struct {
                                the reverse pass multiplies plain bf16 operands */
 } rve_train_opts;
 
-/* Fills defaults: steps 40000, batch 3840, lr 2e-3 -> 2e-5, Adam (0.9, 0.999,
+/* Fills defaults: steps 80000, batch 3840, lr 2e-3 -> 2e-5, Adam (0.9, 0.999,
  * 1e-8), wP 1, wA 0.1, rhoP 1e-3, rhoA 1e-3, seed 1, precision BF16X3. */
 void rve_train_opts_default(rve_train_opts* o);
 
@@ -103,9 +103,9 @@ int rve_surrogate_train(rve_surrogate h, const double* F, const double* P, const
 
 /* Calibrates the indicator at one precision from n judged points (P from
  * rve_solve_batch): relative stress error |P_s - P|_F / |P|_F on a grid of
- * 8^3 cells over the bounding box of the points' x, each cell reporting the
- * largest error found in it and its 26 neighbours (+inf with fewer than 2
- * points in the cell).  Host-blocking. */
+ * 8^3 cells over the bounding box of the points' x, each cell reporting 1.25
+ * times the largest error found in it and its 26 neighbours (+inf with fewer
+ * than 2 points in the cell).  Host-blocking. */
 int rve_surrogate_calibrate(rve_surrogate h, const double* F, const double* P, int64_t n, int32_t precision,
                             void* hip_stream);
 

@@ -49,6 +49,7 @@ constexpr int OFF_W1 = 0, OFF_B1 = 384, OFF_W2 = 512, OFF_B2 = 512 + 16384;
 constexpr int OFF_W3 = OFF_B2 + 128, OFF_B3 = OFF_W3 + 16384, OFF_W4 = OFF_B3 + 128;
 static_assert(OFF_W4 + 128 == NPARAM, "parameter layout");
 constexpr int GRID = 8;                // indicator cells per input axis
+constexpr double kIndicatorMargin = 1.25;  // indicator = margin x the largest calibration error nearby
 constexpr int TRAIN_PTS = 15;          // data points per training tile (+ the origin)
 
 enum { MODE_EVAL = 0, MODE_TRAIN = 1 };
@@ -935,7 +936,7 @@ extern "C" {
 
 void rve_train_opts_default(rve_train_opts* o) {
     if (!o) return;
-    o->steps = 40000;
+    o->steps = 80000;
     o->batch = 3840;
     o->lr = 2e-3f;
     o->lr_final = 2e-5f;
@@ -1290,7 +1291,8 @@ int rve_surrogate_calibrate(rve_surrogate h, const double* F, const double* P, i
                             if (e0 < 0 || e1 < 0 || e2 < 0 || e0 >= GRID || e1 >= GRID || e2 >= GRID) continue;
                             m = std::max(m, cmax[(e0 * GRID + e1) * GRID + e2]);
                         }
-                tab[cell] = (float)m;
+                // margin for points worse than any calibration point nearby
+                tab[cell] = (float)(kIndicatorMargin * m);
             }
     SHIP(hipMemcpy(h->table + precision * NC, tab.data(), sizeof(float) * NC, hipMemcpyHostToDevice));
     for (int k = 0; k < 3; ++k) {

@@ -166,7 +166,7 @@ def test_surrogate_symbols_and_validation():
         assert hasattr(L, nm), nm
     assert "rve_solve_batch_subset" in rve.declared_functions()
     o = S.train_opts()
-    assert o.steps == 40000 and o.batch == 3840 and o.precision == S.BF16X3
+    assert o.steps == 80000 and o.batch == 3840 and o.precision == S.BF16X3
     assert abs(o.lr - 2e-3) < 1e-9 and abs(o.beta2 - 0.999) < 1e-7
     # argument checks run before any device call
     with pytest.raises(rve.RveError) as e:
