@@ -30,6 +30,8 @@ Prints one JSON line.  Options:
                            against RVE solves, and macro steps/s of the 64 x 64
                            plate with a hole, nested, plain FP64 vs surrogate with
                            fallback at indicator 1e-3
+  --no-3d                  skip the uneven 3D block (with a 2D workload): 1024 RVEs
+                           of 8^3 / 12^3 / 16^3, one timed launch per precision
 """
 import argparse
 import json
@@ -42,7 +44,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector = FP64 matrix (dense)
+PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 (vector and matrix)
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 MFMA
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
@@ -277,6 +279,41 @@ def macro_bench(nsteps3):
     return res
 
 
+def rve3d_block(precs, steps=1, warmup=1):
+    """The uneven 3D batch (1024 RVEs of 8^3 / 12^3 / 16^3, cost-ordered queue) in
+    each precision: one timed launch after one warm-up, with its roofline."""
+    import torch
+    from paper_1908_08292_amd import api, rve
+    wl, meta = make_workload("rve3d_mixed")
+    batch, meshes = api.build_batch(3, wl.n, wl.radius, wl.ratio)
+    s = api.Solver(batch, want_A=True, keep_state=False)
+    s.set_F(wl.F)
+    stream = torch.cuda.current_stream()
+    out = {"workload": meta["workload"], "rves": meta["B"]}
+    for p in precs:
+        opts = rve.default_opts(precision=rve.PREC_FP32_IR if p == "fp32ir" else rve.PREC_FP64)
+        print(f"[bench] {meta['workload']} {p}: warmup {warmup}, steps {steps}", file=sys.stderr, flush=True)
+        ms = time_solves(s, opts, stream, steps, warmup)
+        res = s.results()
+        flops = algorithmic_flops(rve, 3, wl.n, res["iters"])
+        achieved = flops / (ms * 1e-3) / 1e12
+        peak = PEAK_FP64_TFLOPS if p == "fp64" else PEAK_FP32_TFLOPS
+        out[p] = {"value": meta["B"] / (ms * 1e-3), "unit": "RVE solves/s", "ms_per_step": ms,
+                  "failed_rves": int((res["status"] != 0).sum()),
+                  "mean_newton_iters": float(res["iters"].mean()),
+                  "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                               "frac": achieved / peak, "traffic": measured_traffic(meta["workload"], p)}}
+        print(f"[bench] {p}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    if "fp64" in out and "fp32ir" in out:
+        out["fp32ir"]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32ir"]["ms_per_step"]
+    del s
+    batch.destroy()
+    for m in meshes:
+        m.destroy()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +327,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32ir", "both"], default="both")
     ap.add_argument("--macro-steps", type=int, default=4)
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: runs on one GPU only (the RVE batch would be sharded by macro elements "
@@ -358,6 +396,8 @@ def main():
                                       mean_newton_iters=float(t["res"]["iters"].mean()),
                                       dtype="f32 factors (LDL^T, solves) + f64 residuals, refinement, "
                                             "norms, averages and condensation")
+    if not args.no_3d and d == 2:
+        out["rve3d_uneven"] = rve3d_block(precs)
     if args.macro:
         out["macro"] = macro_bench(args.macro_steps)
     if not args.no_surrogate and d == 2:
