@@ -1489,7 +1489,27 @@ __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* r
             }
         }
         __syncthreads();
-        const int nb = (p + 15) >> 4;
+        if (p <= 64) {
+            // the pivot triangle by wave 0 alone, lane = pivot, from the last pivot
+            // (readlane broadcasts of the finished values, no barrier)
+            if (wave == 0) {
+                const int jl = lane < p ? lane : 0;
+                const T* colj = Lp + cpk(jl, m) - jl;  // L(i, lane) = colj[i], i >= lane
+                double vv[NRHS];
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) vv[q] = lane < p ? v[q * p + lane] : 0.0;
+                for (int i = p - 1; i > 0; --i) {
+                    const double l = (lane < i) ? (double)colj[i] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < NRHS; ++q) vv[q] -= l * readlane_d(vv[q], i);
+                }
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q)
+                    if (lane < p) v[q * p + lane] = vv[q];
+            }
+            __syncthreads();
+        }
+        const int nb = p <= 64 ? 0 : (p + 15) >> 4;
         for (int bk = nb - 1; bk >= 0; --bk) {
             const int K = 16 * bk, kb = min(16, p - K);
             if (wave == 0) {
