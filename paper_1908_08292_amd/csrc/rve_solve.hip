@@ -1594,7 +1594,39 @@ __device__ __noinline__ void forward_lds(const RveCtx& c, Smem& sm, T* F, double
             vb[t] = (i < p) ? b[(int64_t)rows[i] * NRHS + q] : 0.0;
         }
         __syncthreads();
-        for (int K = 0; K < p; K += 16) {
+        if (p <= 64) {
+            // the pivot triangle by wave 0 alone (lane = pivot row, readlane
+            // broadcasts of the finished values), then every row below folds in
+            // all p pivots in one pass
+            if (wave == 0) {
+                double vv[NRHS];
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) vv[q] = lane < p ? vb[q * m + lane] : 0.0;
+                for (int j = 0; j < p - 1; ++j) {
+                    const double l = (lane > j && lane < p) ? (double)Lp[cpk(j, m) + lane - j] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < NRHS; ++q) vv[q] -= l * readlane_d(vv[q], j);
+                }
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q)
+                    if (lane < p) vb[q * m + lane] = vv[q];
+            }
+            __syncthreads();
+            for (int i = p + tid; i < m; i += NT) {
+                double acc[NRHS];
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) acc[q] = vb[q * m + i];
+                for (int j = 0; j < p; ++j) {
+                    const double l = (double)Lp[cpk(j, m) + i - j];
+#pragma unroll
+                    for (int q = 0; q < NRHS; ++q) acc[q] -= l * vb[q * m + j];
+                }
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) vb[q * m + i] = acc[q];
+            }
+            __syncthreads();
+        }
+        for (int K = 0; K < (p <= 64 ? 0 : p); K += 16) {
             const int kb = min(16, p - K);
             if (wave == 0) {
                 const bool own = lane < kb;
