@@ -539,6 +539,16 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
     const int k = fp32 ? 1 : 0;
     a.lds_front = (int32_t)b->lds_front[k];
     a.wave_slice = (int32_t)b->wave_slice;
+    size_t dyn = b->dyn_bytes[k];
+    // FP32 factors: where the FP64 front region keeps two workgroups per CU (the
+    // register limit), the condensation factorization runs in FP64 and the direct
+    // Schur form replaces the refined FP32 solves
+    a.tan64 = 0;
+    a.lds_front64 = (int32_t)b->lds_front[0];
+    if (fp32 && (int64_t)b->dyn_bytes[0] + lds_static_bytes() <= kLdsBytesMax / 2) {
+        a.tan64 = 1;
+        dyn = std::max(dyn, b->dyn_bytes[0]);
+    }
     // FP32 factors: a Newton step is refined only when ||b - K64 x|| > 1e-2 ||b||
     // (inexact Newton; convergence is judged on the FP64 residual); the tangent
     // gets one refinement sweep and the second-order form
@@ -546,7 +556,7 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
     a.ir_max_tan = 1;
     a.ir_eta = 1e-2;
     a.ir_eta_tan = 0.0;
-    hipError_t e = launch_rve_solve(a, b->nslots, b->dyn_bytes[k], fp32, (hipStream_t)hip_stream);
+    hipError_t e = launch_rve_solve(a, b->nslots, dyn, fp32, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(RVE_EHIP, std::string("rve_solve_batch launch: ") + hipGetErrorString(e));
     return RVE_OK;
 }

@@ -1909,14 +1909,19 @@ __global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
                 __syncthreads();
                 node_gather<D>(c, c.re, D2, c.rhs, 1.0);
                 __syncthreads();
-                // the condensation factorization: in the factor type for LDS plans
-                // (whose LDS budget is sized for it), in FP64 for global-front plans
-                // (direct Schur form below, no refinement needed)
-                if (c.plan->lds_ok) factorize_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
-                else factorize_glb<D, double>(c, sm, D2, dynRaw);
+                // the condensation factorization: FP64 (direct Schur form below, no
+                // refinement) for global-front plans and for LDS plans whose FP64
+                // front region keeps the occupancy; otherwise in the factor type
+                const bool tan64 = !IR || !c.plan->lds_ok || a.tan64;
+                if (!c.plan->lds_ok)
+                    factorize_glb<D, double>(c, sm, D2, dynRaw);
+                else if (IR && a.tan64)
+                    factorize_lds<D, D2, double>(c, sm, dynRaw, dynRaw + a.lds_front64, a.wave_slice);
+                else
+                    factorize_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
                 if (sm.flag) {
                     status = 3;
-                } else if (IR && c.plan->lds_ok) {
+                } else if (!tan64) {
                     // X ~ K^-1 Y from the FP32 factors, refined ir_max_tan times against
                     // the FP64 tangent; then the stationary (second-order) form
                     //   Abar = <A> - Y^T X - X^T r,  r = Y - K X,
