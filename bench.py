@@ -79,7 +79,7 @@ def algorithmic_flops(rve, d, n_arr, iters):
     return total
 
 
-KERNEL_SOURCES = ["rve_solve.hip", "plan.cpp", "plan.h", "solver_dev.h", "mesh_common.h"]
+KERNEL_SOURCES = ["rve_solve.hip", "rve_solve512.hip", "plan.cpp", "plan.h", "solver_dev.h", "mesh_common.h"]
 
 
 def kernel_source_hash():

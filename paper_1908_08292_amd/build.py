@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librve.so")
-SOURCES = ["plan.cpp", "rve_abi.cpp", "rve_solve.hip", "fehmm.hip", "surrogate.hip"]
+SOURCES = ["plan.cpp", "rve_abi.cpp", "rve_solve.hip", "rve_solve512.hip", "fehmm.hip", "surrogate.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

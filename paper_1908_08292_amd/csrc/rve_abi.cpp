@@ -18,10 +18,18 @@
 #include "solver_dev.h"
 
 namespace fehmm {
+// the solver compiled with 256-thread (four-wave) and 512-thread (eight-wave) workgroups
+namespace nt256 {
 hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, bool fp32, hipStream_t stream);
 hipError_t prepare_rve_solve();
 int lds_static_bytes();
-constexpr int NWAVE_ = 4;  // waves per workgroup of the solve kernel
+}
+namespace nt512 {
+hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, bool fp32, hipStream_t stream);
+hipError_t prepare_rve_solve();
+int lds_static_bytes();
+}
+constexpr int NWAVE_ = 4;  // waves per workgroup of the default solver
 }
 
 using namespace fehmm;
@@ -161,7 +169,7 @@ int plan_device(PlanEntry* e) {
                          (int64_t)sizeof(double);
     e->lds_bytes = need;
     // (one thread per front row in the pivot sweep: m <= 256; the plan decides)
-    e->dev.lds_ok = (P.lds_path && need + lds_static_bytes() + 1024 <= kLdsBytesMax) ? 1 : 0;
+    e->dev.lds_ok = (P.lds_path && need + nt256::lds_static_bytes() + 1024 <= kLdsBytesMax) ? 1 : 0;
     return RVE_OK;
 }
 
@@ -191,6 +199,10 @@ struct rve_batch_s {
     int64_t lds_front[2] = {0, 0};  // front region of the dynamic LDS (FP64 / FP32 elements)
     int64_t wave_slice = 0;         // elements per wave slice
     size_t dyn_bytes[2] = {0, 0};
+    // per precision: launch the eight-wave solver (2D LDS plans whose fronts leave
+    // room for one four-wave workgroup per CU only) with its dynamic LDS size
+    bool wide[2] = {false, false};
+    size_t dyn_bytes_wide[2] = {0, 0};
     SlotLayout lay{};
     std::vector<int64_t> state_off;
     // device
@@ -343,7 +355,8 @@ static void free_batch(rve_batch_s* b) {
 static int ensure_prepared() {
     static bool prepared = false;
     if (!prepared) {
-        hipError_t pe = prepare_rve_solve();
+        hipError_t pe = nt256::prepare_rve_solve();
+        if (pe == hipSuccess) pe = nt512::prepare_rve_solve();
         if (pe != hipSuccess) return fail(RVE_EHIP, std::string("rve kernels: ") + hipGetErrorString(pe));
         prepared = true;
     }
@@ -431,6 +444,10 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
             // condensation factorization of global-front plans is FP64)
             if (glb) bytes = std::max<int64_t>(bytes, (int64_t)kTileLdsElems * 8);
             b->dyn_bytes[k] = (size_t)bytes;
+            const int64_t wide_bytes = std::max(b->lds_front[k] + rl, 2 * NWAVE_ * b->wave_slice) * es;
+            b->wide[k] = d == 2 && !glb && bytes + nt256::lds_static_bytes() > kLdsBytesMax / 2 &&
+                         wide_bytes + nt512::lds_static_bytes() + 1024 <= kLdsBytesMax;
+            b->dyn_bytes_wide[k] = (size_t)wide_bytes;
         }
     }
     auto rnd = [](int64_t x) { return (x + 31) / 32 * 32; };
@@ -539,13 +556,14 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
     const int k = fp32 ? 1 : 0;
     a.lds_front = (int32_t)b->lds_front[k];
     a.wave_slice = (int32_t)b->wave_slice;
-    size_t dyn = b->dyn_bytes[k];
+    const bool wide = b->wide[k];
+    size_t dyn = wide ? b->dyn_bytes_wide[k] : b->dyn_bytes[k];
     // FP32 factors: where the FP64 front region keeps two workgroups per CU (the
     // register limit), the condensation factorization runs in FP64 and the direct
     // Schur form replaces the refined FP32 solves
     a.tan64 = 0;
     a.lds_front64 = (int32_t)b->lds_front[0];
-    if (fp32 && (int64_t)b->dyn_bytes[0] + lds_static_bytes() <= kLdsBytesMax / 2) {
+    if (fp32 && !wide && (int64_t)b->dyn_bytes[0] + nt256::lds_static_bytes() <= kLdsBytesMax / 2) {
         a.tan64 = 1;
         dyn = std::max(dyn, b->dyn_bytes[0]);
     }
@@ -556,7 +574,8 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
     a.ir_max_tan = 1;
     a.ir_eta = 1e-2;
     a.ir_eta_tan = 0.0;
-    hipError_t e = launch_rve_solve(a, b->nslots, dyn, fp32, (hipStream_t)hip_stream);
+    hipError_t e = wide ? nt512::launch_rve_solve(a, b->nslots, dyn, fp32, (hipStream_t)hip_stream)
+                        : nt256::launch_rve_solve(a, b->nslots, dyn, fp32, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(RVE_EHIP, std::string("rve_solve_batch launch: ") + hipGetErrorString(e));
     return RVE_OK;
 }

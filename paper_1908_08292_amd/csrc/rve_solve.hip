@@ -1,7 +1,8 @@
 // rve_solve.hip -- persistent batched periodic-RVE solver for gfx950.
 //
-// One workgroup (256 threads, four wave64) owns one workspace slot and pulls
-// RVE ids from a device queue until the batch is exhausted.  Per RVE it runs the
+// One workgroup (256 threads, four wave64; or 512 threads, eight wave64, when
+// compiled with FEHMM_NT=512 into namespace fehmm::nt512) owns one workspace
+// slot and pulls RVE ids from a device queue until the batch is exhausted.  Per RVE it runs the
 // micro Newton iteration of Sec. 3.3 (residual, tangent, linear solve, update;
 // the PBC form in which G^T dLambda = 0), then the post-convergence outputs:
 // Pbar = <P> (eq. Average-of-P-and-F) and the tangent transfer of Sec. 3.2 for
@@ -31,10 +32,17 @@
 #include "mesh_common.h"
 #include "solver_dev.h"
 
-namespace fehmm {
+#ifndef FEHMM_NT
+#define FEHMM_NT 256
+#define FEHMM_VARIANT nt256
+#endif
 
-constexpr int NT = 256;
+namespace fehmm {
+namespace FEHMM_VARIANT {
+
+constexpr int NT = FEHMM_NT;
 constexpr int NWAVE = NT / 64;
+static_assert(NT == 256 || NT == 512, "workgroup size");
 
 // Optional per-phase clock accounting (slot 0, thread 0), compiled in only
 // with -DFEHMM_PHASE_PROF=1; the default build records nothing.
@@ -625,6 +633,13 @@ __device__ __attribute__((noinline)) void factorize_glb(const RveCtx& c, Smem& s
     constexpr int NEN = 1 << D, ND = NEN * D;
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if constexpr (NWAVE != 4) {
+        // the global-front tiles are laid out for four waves; the host launches
+        // the eight-wave solver for LDS plans only, and anything else fails here
+        if (tid == 0) sm.flag = 2;
+        __syncthreads();
+        return;
+    }
     T* W = reinterpret_cast<T*>(sm.red);  // 16 x 16
     nrhs = uni(nrhs);
     double* const cL = uni(c.L);
@@ -1718,7 +1733,7 @@ __device__ double free_norm2(const RveCtx& c, Smem& sm, const double* R) {
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(NT, 2) void rve_solve_kernel(SolveArgs a) {
+__global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
     __shared__ Smem sm;
     extern __shared__ double dynRaw[];
     T* dynF = reinterpret_cast<T*>(dynRaw);
@@ -2025,16 +2040,30 @@ hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, bo
     return hipGetLastError();
 }
 
+}  // namespace FEHMM_VARIANT
 }  // namespace fehmm
 
 #if FEHMM_PHASE_PROF
-extern "C" int rve_debug_phase_clocks(unsigned long long* out, int reset) {
-    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(fehmm::g_phase), sizeof(unsigned long long) * fehmm::PH_N) != hipSuccess)
+#define FEHMM_CAT2(a, b) a##_##b
+#define FEHMM_CAT(a, b) FEHMM_CAT2(a, b)
+extern "C" int FEHMM_CAT(rve_debug_phase_clocks, FEHMM_VARIANT)(unsigned long long* out, int reset) {
+    namespace V = fehmm::FEHMM_VARIANT;
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(V::g_phase), sizeof(unsigned long long) * V::PH_N) != hipSuccess)
         return -3;
     if (reset) {
-        unsigned long long z[fehmm::PH_N] = {0};
-        if (hipMemcpyToSymbol(HIP_SYMBOL(fehmm::g_phase), z, sizeof(z)) != hipSuccess) return -3;
+        unsigned long long z[V::PH_N] = {0};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(V::g_phase), z, sizeof(z)) != hipSuccess) return -3;
     }
     return 0;
 }
+#if FEHMM_NT == 256
+// the phase clocks of both workgroup sizes, summed
+extern "C" int rve_debug_phase_clocks_nt512(unsigned long long* out, int reset);
+extern "C" int rve_debug_phase_clocks(unsigned long long* out, int reset) {
+    unsigned long long b[fehmm::nt256::PH_N];
+    if (rve_debug_phase_clocks_nt256(out, reset) || rve_debug_phase_clocks_nt512(b, reset)) return -3;
+    for (int i = 0; i < fehmm::nt256::PH_N; ++i) out[i] += b[i];
+    return 0;
+}
+#endif
 #endif

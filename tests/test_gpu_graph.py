@@ -16,12 +16,22 @@ def torch_cuda():
     return torch
 
 
+def uneven(d):
+    if d == 3:
+        return workloads.rve3d(8, sizes=(4, 6, 8), seed=1700)
+    # 32 x 32 FP64 fronts: the eight-wave solver
+    wl = workloads.rve2d(48, seed=1701)
+    wl.n[:] = np.resize(np.array([8, 16, 32], np.int32), 48)
+    return wl
+
+
+@pytest.mark.parametrize("d", [2, 3])
 @pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
-def test_uneven_3d_batch_graph_replays_match_eager(prec):
+def test_uneven_batch_graph_replays_match_eager(d, prec):
     torch = torch_cuda()
-    wl = workloads.rve3d(8, sizes=(4, 6, 8), seed=1700)
-    print(f"case graph replay, 3d uneven n={list(wl.n)}, {prec}", flush=True)
-    batch, meshes = api.build_batch(3, wl.n, wl.radius, wl.ratio)
+    wl = uneven(d)
+    print(f"case graph replay, {d}d uneven n={list(wl.n)}, {prec}", flush=True)
+    batch, meshes = api.build_batch(d, wl.n, wl.radius, wl.ratio)
     s = api.Solver(batch, keep_state=False)
     s.set_F(wl.F)
     o = rve.default_opts(precision=rve.PREC_FP32_IR if prec == "fp32ir" else rve.PREC_FP64)

@@ -87,6 +87,18 @@ def test_parity_3d_uneven_batch():
     compare(3, wl.n, wl.radius, wl.ratio, wl.F, out)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_parity_2d_uneven_batch(prec):
+    """Sizes 5, 12 and 32 in one batch: the launch is sized for the 32 x 32
+    fronts (in FP64 the eight-wave solver), the smaller RVEs run in it too."""
+    wl = workloads.rve2d(6, seed=602)
+    wl.n[:] = [32, 5, 12, 32, 12, 5]
+    print(f"case 2d uneven n={list(wl.n)} {prec}", flush=True)
+    o = rve.default_opts(precision=rve.PREC_FP32_IR if prec == "fp32ir" else rve.PREC_FP64)
+    out = run_gpu(2, wl.n, wl.radius, wl.ratio, wl.F, opts=o)
+    (compare if prec == "fp64" else compare_loose_iters)(2, wl.n, wl.radius, wl.ratio, wl.F, out)
+
+
 def test_warm_start_round_trip():
     wl = workloads.rve2d(4, n=8, seed=700)
     print("case warm start", flush=True)
