@@ -385,6 +385,7 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
             }
             if (F.wave) {
                 maxh = std::max(maxh, F.height);
+                // packed front, rhs rows, original diagonal (m <= 64) within the 256 spare
                 P.wave_slice = std::max<int64_t>(P.wave_slice, (int64_t)F.m * (F.m + 1) / 2 + (int64_t)F.m * d * d + 256);
             }
         }

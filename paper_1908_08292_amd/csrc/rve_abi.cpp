@@ -164,7 +164,7 @@ int plan_device(PlanEntry* e) {
     for (const FrontHost& fr : P.fronts) scratch = std::max<int64_t>(scratch, (int64_t)fr.m * (P.d * P.d + 3));
     e->front_elems[0] = std::max<int64_t>(mm * (mm + 1) / 2, scratch);
     e->front_elems[1] = std::max<int64_t>(mm * (mm + 1) / 2, 2 * scratch);
-    e->rl_elems = mm * P.d * P.d;
+    e->rl_elems = mm * (P.d * P.d + 1);  // rhs rows, then the original diagonal
     const int64_t need = std::max<int64_t>(e->front_elems[0] + e->rl_elems, NWAVE_ * P.wave_slice) *
                          (int64_t)sizeof(double);
     e->lds_bytes = need;

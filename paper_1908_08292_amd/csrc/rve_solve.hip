@@ -1003,10 +1003,12 @@ __device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& s
 // (extend-add) strides of the list per pass, every index load first, then every
 // value load (clamped addresses, zeros selected), then the stores, so a pass
 // costs one or two memory round trips for all its strides.  first / stride: the
-// caller's lane (wave-level) or thread (workgroup-level) numbering.
+// caller's lane (wave-level) or thread (workgroup-level) numbering.  D0 (LDS)
+// receives the original diagonal of the pivot columns, the scale of the
+// vanishing-pivot test.
 template <int NEN, typename T>
 __device__ inline void gather_original(const DevPlan& pl, const double* ke, int a0, int a1, int first, int stride,
-                                       T* F, int m, double* Dg) {
+                                       T* F, int m, T* D0) {
     for (int t0 = a0 + first; t0 < a1; t0 += 4 * stride) {
         int rc[4], src[4][NEN];
 #pragma unroll
@@ -1031,7 +1033,7 @@ __device__ inline void gather_original(const DevPlan& pl, const double* ke, int 
             if (t0 + u * stride < a1) {
                 const int r = rc[u] >> 16, col = rc[u] & 0xffff;
                 F[cpk(col, m) + r - col] = v[u];
-                if (r == col) Dg[col] = v[u];
+                if (r == col) D0[col] = v[u];
             }
         }
     }
@@ -1069,8 +1071,9 @@ __device__ inline void extend_add_packed(const int32_t* ea, const T* Uc, int nu,
 
 // One small front (m <= 64) processed by a single wave: lane i owns front row i.
 // Assembly as in the workgroup path, then a right-looking LDL^T sweep over the
-// p pivots done in place in LDS (the wave's slice); within a wave LDS accesses
-// complete in issue order, so no barrier is needed between pivots.
+// p pivots done in place in LDS (the wave's slice: front, rhs rows, original
+// diagonal); within a wave LDS accesses complete in issue order, so no barrier
+// is needed between pivots.
 template <int D, int NRHS, typename T>
 __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
     const DevPlan& pl = *c.plan;
@@ -1089,7 +1092,8 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
         rl[t] = (i < p) ? c.rhs[(int64_t)rows[i] * NRHS + col] : 0.0;
     }
     __builtin_amdgcn_wave_barrier();
-    gather_original<NEN>(pl, c.ke, fr.asm_begin, fr.asm_end, lane, 64, F, m, Dg);
+    T* const D0 = rl + m * NRHS;
+    gather_original<NEN>(pl, c.ke, fr.asm_begin, fr.asm_end, lane, 64, F, m, D0);
     __builtin_amdgcn_wave_barrier();
     for (int q = fr.child_begin; q < fr.child_end; ++q) {
         const DevFront ch = pl.fronts[pl.children[q]];
@@ -1122,7 +1126,7 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
                 row[cc] = (act && cc < kb && K + cc <= r) ? (double)F[cpk(K + cc, m) + r - K - cc] : 0.0;
 #pragma unroll
             for (int q = 0; q < NRHS; ++q) yv[q] = act ? rl[q * m + r] : 0.0;
-            const double d0 = (act && r < K + kb) ? Dg[r] : 1.0;
+            const double d0 = (act && r < K + kb) ? (double)D0[r] : 1.0;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 if (j < kb) {
@@ -1255,7 +1259,8 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* r
         }
         __syncthreads();
         // original entries: one gather level, every source load in flight at once
-        gather_original<NEN>(pl, c.ke, fr.asm_begin, fr.asm_end, tid, NT, F, m, Dg);
+        T* const D0 = rl + m * nrhs;  // original diagonal, after the rhs rows
+        gather_original<NEN>(pl, c.ke, fr.asm_begin, fr.asm_end, tid, NT, F, m, D0);
         __syncthreads();
         for (int q = fr.child_begin; q < fr.child_end; ++q) {
             const DevFront ch = pl.fronts[pl.children[q]];
@@ -1288,7 +1293,7 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* r
                 r[cc] = (own && cc < kb && K + cc <= i) ? F[cpk(K + cc, m) + i - K - cc] : 0.0;
 #pragma unroll
             for (int q = 0; q < NRHS; ++q) b[q] = own ? rl[q * m + i] : 0.0;
-            const double d0 = (own && i < K + kb) ? Dg[i] : 1.0;
+            const double d0 = (own && i < K + kb) ? (double)D0[i] : 1.0;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 if (j < kb) {
