@@ -202,6 +202,15 @@ int rve_plan_info(int32_t ndim, int32_t n, double* factor_flops, int64_t* nnz_L,
 int rve_plan_export(int32_t ndim, int32_t n, int64_t* sizes, int32_t* fronts, int32_t* rows, int32_t* relind,
                     int32_t* children, int32_t* kpair, int32_t* kcontrib);
 
+/* Processing schedule of the (ndim, n) plan's LDS path, for tooling and tests
+ * (host only).  *nsteps receives the number of workgroup-front steps (0 when
+ * the fronts live in global memory); steps, if non-NULL, receives [nsteps][2]
+ * = (front, second front processed beside it on the other half of the
+ * workgroup, or -1) in processing order; wave, if non-NULL, receives one flag
+ * per front (elimination order): 1 for the fronts eliminated one per wave
+ * before the workgroup fronts. */
+int rve_plan_schedule(int32_t ndim, int32_t n, int64_t* nsteps, int32_t* steps, int32_t* wave);
+
 /* ---- errors ------------------------------------------------------------------ */
 const char* rve_strerror(int code);
 /* Copies the calling thread's last error message (NUL-terminated) into buf. */

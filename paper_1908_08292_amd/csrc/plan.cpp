@@ -396,6 +396,38 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
         }
         P.wave_hbeg.push_back((int32_t)P.wave_list.size());
         P.wave_slice = (P.wave_slice + 31) / 32 * 32;
+        // workgroup fronts by height (children first).  Two of one height are
+        // independent; with equal p and child counts they pass the same barriers,
+        // so they can share a step when each has at most 128 rows (one thread per
+        // row in half of a 256-thread workgroup) and both fit the front region.
+        const int64_t mm = P.max_m, region = mm * (mm + 1) / 2 + mm * (d * d + 1);
+        int hmax = 0;
+        for (const FrontHost& F : P.fronts) hmax = std::max(hmax, F.height);
+        for (int h = 0; h <= hmax; ++h) {
+            std::vector<int> lst;
+            for (int s = 0; s < ns; ++s)
+                if (!P.fronts[s].wave && P.fronts[s].height == h) lst.push_back(s);
+            std::vector<char> used(lst.size(), 0);
+            for (size_t a = 0; a < lst.size(); ++a) {
+                if (used[a]) continue;
+                used[a] = 1;
+                const FrontHost& A = P.fronts[lst[a]];
+                int partner = -1;
+                for (size_t b = a + 1; b < lst.size() && A.m <= 128; ++b) {
+                    const FrontHost& Bf = P.fronts[lst[b]];
+                    const int64_t need = (int64_t)A.m * (A.m + 1) / 2 + (int64_t)Bf.m * (Bf.m + 1) / 2 +
+                                         (int64_t)(A.m + Bf.m) * (d * d + 1);
+                    if (!used[b] && Bf.m <= 128 && Bf.p == A.p &&
+                        Bf.child_end - Bf.child_begin == A.child_end - A.child_begin && need <= region) {
+                        partner = lst[b];
+                        used[b] = 1;
+                        break;
+                    }
+                }
+                P.wg_steps.push_back(lst[a]);
+                P.wg_steps.push_back(partner);
+            }
+        }
     }
     return P;
 }

@@ -65,6 +65,10 @@ struct PlanHost {
     // fronts processed wave-per-front before the workgroup fronts, grouped by
     // height (all fronts of one height are independent)
     std::vector<int32_t> wave_list, wave_hbeg;
+    // the other (workgroup) fronts in processing order, two entries per step:
+    // {s, -1} one front on the whole workgroup, {s, s2} two independent fronts
+    // (equal height, pivot and child counts) side by side on its two halves
+    std::vector<int32_t> wg_steps;
     int64_t wave_slice = 0;    // doubles of one wave's LDS slice (packed front + rhs rows)
     bool lds_path = false;     // every front fits the LDS front buffer
     int64_t L_size = 0;        // doubles of L + D + y storage

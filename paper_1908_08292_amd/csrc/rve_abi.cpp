@@ -67,6 +67,7 @@ struct PlanEntry {
     int32_t* d_ea_dst = nullptr;
     int32_t* d_wave_list = nullptr;
     int32_t* d_wave_hbeg = nullptr;
+    int32_t* d_wg_steps = nullptr;
     int refs = 0;
     int device = -1;
     int64_t lds_bytes = 0;            // FP64 fronts: dynamic LDS bytes
@@ -107,7 +108,7 @@ void free_plan_dev(PlanEntry& e) {
     (void)hipFree(e.d_fronts); (void)hipFree(e.d_rows); (void)hipFree(e.d_relind);
     (void)hipFree(e.d_children); (void)hipFree(e.d_kpair); (void)hipFree(e.d_kcontrib);
     (void)hipFree(e.d_asm_rc); (void)hipFree(e.d_asm_src); (void)hipFree(e.d_ea_dst);
-    (void)hipFree(e.d_wave_list); (void)hipFree(e.d_wave_hbeg);
+    (void)hipFree(e.d_wave_list); (void)hipFree(e.d_wave_hbeg); (void)hipFree(e.d_wg_steps);
     e.d_fronts = nullptr;
 }
 
@@ -147,14 +148,16 @@ int plan_device(PlanEntry* e) {
         (st = upload(P.children, &e->d_children)) || (st = upload(P.kpair, &e->d_kpair)) ||
         (st = upload(P.kcontrib, &e->d_kcontrib)) || (st = upload(P.asm_rc, &e->d_asm_rc)) ||
         (st = upload(P.asm_src, &e->d_asm_src)) || (st = upload(P.ea_dst, &e->d_ea_dst)) ||
-        (st = upload(P.wave_list, &e->d_wave_list)) || (st = upload(P.wave_hbeg, &e->d_wave_hbeg))) {
+        (st = upload(P.wave_list, &e->d_wave_list)) || (st = upload(P.wave_hbeg, &e->d_wave_hbeg)) ||
+        (st = upload(P.wg_steps, &e->d_wg_steps))) {
         free_plan_dev(*e);
         return st;
     }
     e->dev = DevPlan{P.d, P.n, P.nnode, P.nelem, (int32_t)P.fronts.size(), 0,
                      e->d_fronts, e->d_rows, e->d_relind, e->d_children, e->d_kpair, e->d_kcontrib,
                      e->d_asm_rc, e->d_asm_src, e->d_ea_dst, e->d_wave_list, e->d_wave_hbeg,
-                     (int32_t)P.wave_hbeg.size() - 1, (int32_t)P.wave_slice};
+                     (int32_t)P.wave_hbeg.size() - 1, (int32_t)P.wave_slice, e->d_wg_steps,
+                     (int32_t)(P.wg_steps.size() / 2)};
     if (P.wave_hbeg.empty()) e->dev.nwave_h = 0;
     // whole fronts in LDS when the largest packed front plus its rhs rows fit;
     // the front region also hosts the FP64 scratch of the triangular solves
@@ -606,6 +609,19 @@ int rve_solve_batch_sync(rve_batch b, const double* F, double* P, double* A, dou
 }
 
 }  // extern "C"
+
+extern "C" int rve_plan_schedule(int32_t ndim, int32_t n, int64_t* nsteps, int32_t* steps, int32_t* wave) {
+    PlanEntry* e = nullptr;
+    int st = get_plan(ndim, n, &e);
+    if (st) return st;
+    const PlanHost& P = e->host;
+    if (!nsteps) return fail(RVE_EINVAL, "rve_plan_schedule: nsteps is required");
+    *nsteps = P.lds_path ? (int64_t)(P.wg_steps.size() / 2) : 0;
+    if (steps && P.lds_path) std::memcpy(steps, P.wg_steps.data(), P.wg_steps.size() * sizeof(int32_t));
+    if (wave)
+        for (size_t s = 0; s < P.fronts.size(); ++s) wave[s] = P.lds_path ? P.fronts[s].wave : 0;
+    return RVE_OK;
+}
 
 extern "C" int rve_plan_export(int32_t ndim, int32_t n, int64_t* sizes, int32_t* fronts, int32_t* rows,
                                int32_t* relind, int32_t* children, int32_t* kpair, int32_t* kcontrib) {

@@ -69,7 +69,7 @@ __device__ unsigned long long g_phase[PH_N];
 #endif
 
 struct Smem {
-    double pub[2][18 + kMaxNrhs];  // pivot publication (double-buffered)
+    double pub[2][2][18 + kMaxNrhs];  // pivot publication per workgroup half (double-buffered)
     double red[NWAVE * 81];
     double dN[8 * 8 * 3];    // [gp][a][k]
     double Fbar[9];
@@ -1225,6 +1225,162 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
     __builtin_amdgcn_wave_barrier();
 }
 
+// One workgroup front s on threads gt = 0..GT-1 and waves gw = 0..nw-1 (the
+// whole workgroup, or one half of it beside a second front): assembly into the
+// packed front F and rhs rows rl (original diagonal after them), 16-pivot blocks
+// (row-owner sweep, one barrier per pivot, publication in pub; trailing lower
+// triangle on MFMA), then L, D, y and the update matrix out.  Every barrier is
+// workgroup-wide: fronts sharing a step have equal pivot and child counts, so
+// both halves pass the same sequence of barriers.
+template <int D, int NRHS, typename T>
+__device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, int gt, int GT, int gw, int nw,
+                                double (*pub)[18 + kMaxNrhs]) {
+    constexpr int nrhs = NRHS;
+    constexpr int NEN = 1 << D;
+    const DevPlan& pl = *c.plan;
+    const int lane = threadIdx.x & 63;
+    PROF_T0();
+    const DevFront fr = pl.fronts[s];
+    const int m = fr.m, p = fr.p, mu = m - p;
+    const int32_t* rows = pl.rows + fr.rows_off;
+    T* Lg = reinterpret_cast<T*>(c.L + fr.L_off);
+    double* Dg = c.L + fr.D_off;
+    double* yg = c.L + fr.y_off;
+    const int tot = cpk(m, m);
+    for (int t = gt; t < tot; t += GT) F[t] = 0.0;
+    for (int t = gt; t < m * nrhs; t += GT) {
+        const int i = t % m, col = t / m;
+        rl[t] = (i < p) ? c.rhs[(int64_t)rows[i] * nrhs + col] : 0.0;
+    }
+    __syncthreads();
+    // original entries: one gather level, every source load in flight at once
+    T* const D0 = rl + m * nrhs;  // original diagonal, after the rhs rows
+    gather_original<NEN>(pl, c.ke, fr.asm_begin, fr.asm_end, gt, GT, F, m, D0);
+    __syncthreads();
+    for (int q = fr.child_begin; q < fr.child_end; ++q) {
+        const DevFront ch = pl.fronts[pl.children[q]];
+        const int mc = ch.m - ch.p;
+        const int32_t* rel = pl.relind + ch.relind_off;
+        const T* Uc = reinterpret_cast<const T*>(c.U + ch.U_off);
+        const int nu = cpk(mc, mc);
+        const T* ruc = Uc + nu;
+        const int32_t* ea = pl.ea_dst + ch.ea_off;
+        extend_add_packed(ea, Uc, nu, gt, GT, F);
+        for (int t = gt; t < mc * nrhs; t += GT) {
+            const int i = t % mc, col = t / mc;
+            rl[col * m + rel[i]] += ruc[(int64_t)col * mc + i];
+        }
+        __syncthreads();
+    }
+    PROF_MARK(PH_ASM);
+    for (int K = 0; K < p; K += 16) {
+        const int kb = min(16, p - K);
+        // ---- pivot block sweep: each front row below K is owned by one thread
+        // that keeps its 16 block entries in registers; at pivot j the owners of
+        // the block rows publish pivot, reciprocal, column-j entries and the
+        // forward-substituted rhs (double-buffered, one barrier per pivot)
+        const int i = K + gt;
+        const bool own = i < m;
+        double r[16];
+        double b[NRHS];
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc)
+            r[cc] = (own && cc < kb && K + cc <= i) ? F[cpk(K + cc, m) + i - K - cc] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) b[q] = own ? rl[q * m + i] : 0.0;
+        const double d0 = (own && i < K + kb) ? (double)D0[i] : 1.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (j < kb) {
+                double* P = pub[j & 1];  // [0] piv, [1] 1/piv, [2..17] g, [18..] y
+                if (i == K + j) {
+                    const double piv = r[j];
+                    if (!(fabs(piv) > 1e-14 * fabs(d0)) || !isfinite(piv)) sm.flag = 2;
+                    P[0] = piv;
+                    P[1] = 1.0 / piv;
+#pragma unroll
+                    for (int q = 0; q < NRHS; ++q) P[18 + q] = b[q];
+                } else if (i > K + j && i < K + kb) {
+                    P[2 + i - K] = r[j];
+                }
+                __syncthreads();
+                if (own && i > K + j) {
+                    const double l = r[j] * P[1];
+#pragma unroll
+                    for (int cc = j + 1; cc < 16; ++cc)
+                        if (cc < kb && K + cc <= i) r[cc] -= l * P[2 + cc];
+                    r[j] = l;
+#pragma unroll
+                    for (int q = 0; q < NRHS; ++q) b[q] -= l * P[18 + q];
+                }
+            }
+        }
+        if (own) {
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc)
+                if (cc < kb && K + cc <= i) F[cpk(K + cc, m) + i - K - cc] = r[cc];
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) rl[q * m + i] = b[q];
+        }
+        __syncthreads();
+        PROF_MARK(PH_DIAG);
+        // ---- trailing lower triangle (rows, cols >= T0) -= L D L^T with MFMA
+        const int T0 = K + kb;
+        const int nT = (m - T0 + 15) >> 4;
+        const int ntile = nT * (nT + 1) / 2;
+        for (int tix = gw; tix < ntile; tix += nw) {
+            int I = 0, rem = tix;
+            while (rem > I) { rem -= I + 1; ++I; }
+            const int J = rem;
+            const int ra = T0 + 16 * I + (lane & 15), rb = T0 + 16 * J + (lane & 15);
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int kk = 4 * ks + (lane >> 4);
+                const int kc = K + kk;
+                double a = 0.0, bb = 0.0;
+                if (kk < kb) {
+                    const int base = cpk(kc, m) - kc;
+                    const double dk = F[base + kc];
+                    if (ra < m) a = F[base + ra] * dk;
+                    if (rb < m) bb = F[base + rb];
+                }
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+            }
+            const int cc = T0 + 16 * J + (lane & 15);
+            if (cc < m) {
+                const int base = cpk(cc, m) - cc;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = T0 + 16 * I + (lane >> 4) + 4 * v;
+                    if (rr < m && rr >= cc) F[base + rr] -= acc[v];
+                }
+            }
+        }
+        __syncthreads();
+        PROF_MARK(PH_MFMA);
+    }
+    // L panel, D, y; update matrix (packed) and its rhs onto the stack
+    const int lp = cpk(p, m);
+    for (int t = gt; t < lp; t += GT) Lg[t] = F[t];
+    for (int t = gt; t < p; t += GT) Dg[t] = F[cpk(t, m)];
+    for (int t = gt; t < p * nrhs; t += GT) {
+        const int j = t % p, col = t / p;
+        yg[t] = rl[col * m + j];
+    }
+    if (mu > 0) {
+        T* dst = reinterpret_cast<T*>(c.U + fr.U_off);
+        const int usz = tot - lp;
+        for (int t = gt; t < usz; t += GT) dst[t] = F[lp + t];
+        for (int t = gt; t < mu * nrhs; t += GT) {
+            const int i = t % mu, col = t / mu;
+            dst[usz + t] = rl[col * m + p + i];
+        }
+    }
+    __syncthreads();
+    PROF_MARK(PH_OUT);
+}
+
 template <int D, int NRHS, typename T>
 __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* rl, int wave_slice) {
     constexpr int nrhs = NRHS;
@@ -1243,147 +1399,18 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* r
         __syncthreads();
     }
     PROF_MARK(PH_TRSM);
-    for (int s = 0; s < pl.nfront; ++s) {
-        const DevFront fr = pl.fronts[s];
-        if (fr.wave) continue;
-        const int m = fr.m, p = fr.p, mu = m - p;
-        const int32_t* rows = pl.rows + fr.rows_off;
-        T* Lg = reinterpret_cast<T*>(c.L + fr.L_off);
-        double* Dg = c.L + fr.D_off;
-        double* yg = c.L + fr.y_off;
-        const int tot = cpk(m, m);
-        for (int t = tid; t < tot; t += NT) F[t] = 0.0;
-        for (int t = tid; t < m * nrhs; t += NT) {
-            const int i = t % m, col = t / m;
-            rl[t] = (i < p) ? c.rhs[(int64_t)rows[i] * nrhs + col] : 0.0;
-        }
-        __syncthreads();
-        // original entries: one gather level, every source load in flight at once
-        T* const D0 = rl + m * nrhs;  // original diagonal, after the rhs rows
-        gather_original<NEN>(pl, c.ke, fr.asm_begin, fr.asm_end, tid, NT, F, m, D0);
-        __syncthreads();
-        for (int q = fr.child_begin; q < fr.child_end; ++q) {
-            const DevFront ch = pl.fronts[pl.children[q]];
-            const int mc = ch.m - ch.p;
-            const int32_t* rel = pl.relind + ch.relind_off;
-            const T* Uc = reinterpret_cast<const T*>(c.U + ch.U_off);
-            const int nu = cpk(mc, mc);
-            const T* ruc = Uc + nu;
-            const int32_t* ea = pl.ea_dst + ch.ea_off;
-            extend_add_packed(ea, Uc, nu, tid, NT, F);
-            for (int t = tid; t < mc * nrhs; t += NT) {
-                const int i = t % mc, col = t / mc;
-                rl[col * m + rel[i]] += ruc[(int64_t)col * mc + i];
-            }
-            __syncthreads();
-        }
-        PROF_MARK(PH_ASM);
-        for (int K = 0; K < p; K += 16) {
-            const int kb = min(16, p - K);
-            // ---- pivot block sweep: each front row below K is owned by one thread
-            // that keeps its 16 block entries in registers; at pivot j the owners of
-            // the block rows publish pivot, reciprocal, column-j entries and the
-            // forward-substituted rhs (double-buffered, one barrier per pivot)
-            const int i = K + tid;
-            const bool own = i < m;
-            double r[16];
-            double b[NRHS];
-#pragma unroll
-            for (int cc = 0; cc < 16; ++cc)
-                r[cc] = (own && cc < kb && K + cc <= i) ? F[cpk(K + cc, m) + i - K - cc] : 0.0;
-#pragma unroll
-            for (int q = 0; q < NRHS; ++q) b[q] = own ? rl[q * m + i] : 0.0;
-            const double d0 = (own && i < K + kb) ? (double)D0[i] : 1.0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                if (j < kb) {
-                    double* P = sm.pub[j & 1];  // [0] piv, [1] 1/piv, [2..17] g, [18..] y
-                    if (i == K + j) {
-                        const double piv = r[j];
-                        if (!(fabs(piv) > 1e-14 * fabs(d0)) || !isfinite(piv)) sm.flag = 2;
-                        P[0] = piv;
-                        P[1] = 1.0 / piv;
-#pragma unroll
-                        for (int q = 0; q < NRHS; ++q) P[18 + q] = b[q];
-                    } else if (i > K + j && i < K + kb) {
-                        P[2 + i - K] = r[j];
-                    }
-                    __syncthreads();
-                    if (own && i > K + j) {
-                        const double l = r[j] * P[1];
-#pragma unroll
-                        for (int cc = j + 1; cc < 16; ++cc)
-                            if (cc < kb && K + cc <= i) r[cc] -= l * P[2 + cc];
-                        r[j] = l;
-#pragma unroll
-                        for (int q = 0; q < NRHS; ++q) b[q] -= l * P[18 + q];
-                    }
-                }
-            }
-            if (own) {
-#pragma unroll
-                for (int cc = 0; cc < 16; ++cc)
-                    if (cc < kb && K + cc <= i) F[cpk(K + cc, m) + i - K - cc] = r[cc];
-#pragma unroll
-                for (int q = 0; q < NRHS; ++q) rl[q * m + i] = b[q];
-            }
-            __syncthreads();
-            PROF_MARK(PH_DIAG);
-            // ---- trailing lower triangle (rows, cols >= T0) -= L D L^T with MFMA
-            const int T0 = K + kb;
-            const int nT = (m - T0 + 15) >> 4;
-            const int ntile = nT * (nT + 1) / 2;
-            for (int tix = wave; tix < ntile; tix += NWAVE) {
-                int I = 0, rem = tix;
-                while (rem > I) { rem -= I + 1; ++I; }
-                const int J = rem;
-                const int ra = T0 + 16 * I + (lane & 15), rb = T0 + 16 * J + (lane & 15);
-                dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    const int kk = 4 * ks + (lane >> 4);
-                    const int kc = K + kk;
-                    double a = 0.0, bb = 0.0;
-                    if (kk < kb) {
-                        const int base = cpk(kc, m) - kc;
-                        const double dk = F[base + kc];
-                        if (ra < m) a = F[base + ra] * dk;
-                        if (rb < m) bb = F[base + rb];
-                    }
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
-                }
-                const int cc = T0 + 16 * J + (lane & 15);
-                if (cc < m) {
-                    const int base = cpk(cc, m) - cc;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int rr = T0 + 16 * I + (lane >> 4) + 4 * v;
-                        if (rr < m && rr >= cc) F[base + rr] -= acc[v];
-                    }
-                }
-            }
-            __syncthreads();
-            PROF_MARK(PH_MFMA);
-        }
-        // L panel, D, y; update matrix (packed) and its rhs onto the stack
-        const int lp = cpk(p, m);
-        for (int t = tid; t < lp; t += NT) Lg[t] = F[t];
-        for (int t = tid; t < p; t += NT) Dg[t] = F[cpk(t, m)];
-        for (int t = tid; t < p * nrhs; t += NT) {
-            const int j = t % p, col = t / p;
-            yg[t] = rl[col * m + j];
-        }
-        if (mu > 0) {
-            T* dst = reinterpret_cast<T*>(c.U + fr.U_off);
-            const int usz = tot - lp;
-            for (int t = tid; t < usz; t += NT) dst[t] = F[lp + t];
-            for (int t = tid; t < mu * nrhs; t += NT) {
-                const int i = t % mu, col = t / mu;
-                dst[usz + t] = rl[col * m + p + i];
-            }
-        }
-        __syncthreads();
-        PROF_MARK(PH_OUT);
+    // workgroup fronts: one per step on the whole workgroup, or two side by side
+    // on its halves (the second one's storage after the first one's rhs rows)
+    for (int st = 0; st < pl.nwg_steps; ++st) {
+        const int s0 = pl.wg_steps[2 * st], s1 = pl.wg_steps[2 * st + 1];
+        const bool two = s1 >= 0;
+        const int g = (two && tid >= NT / 2) ? 1 : 0;
+        const int GT = two ? NT / 2 : NT, NW = two ? NWAVE / 2 : NWAVE;
+        const int s = g ? s1 : s0;
+        const int m0 = pl.fronts[s0].m, ms = pl.fronts[s].m;
+        T* const Fg = g ? F + cpk(m0, m0) + m0 * (nrhs + 1) : F;
+        T* const rlg = two ? Fg + cpk(ms, ms) : rl;
+        wg_front<D, NRHS, T>(c, sm, s, Fg, rlg, tid - g * GT, GT, wave - g * NW, NW, sm.pub[g]);
     }
 }
 

@@ -26,6 +26,8 @@ struct DevPlan {
     const int32_t* wave_hbeg;
     int32_t nwave_h;       // number of heights in the wave phase
     int32_t wave_slice;    // doubles per wave slice
+    const int32_t* wg_steps;  // [nwg_steps][2] workgroup-front steps (second front or -1)
+    int32_t nwg_steps;
 };
 
 // offsets (in doubles) of the per-slot workspace regions

@@ -70,6 +70,7 @@ def lib():
         L.rve_solve_batch_subset.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Opts), vp]
         L.rve_plan_info.argtypes = [i32, i32, C.POINTER(dp), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]
         L.rve_plan_export.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.rve_plan_schedule.argtypes = [i32, i32, vp, vp, vp]
         L.rve_strerror.argtypes = [C.c_int]
         L.rve_strerror.restype = C.c_char_p
         L.rve_last_error.argtypes = [C.c_char_p, C.c_size_t]
@@ -156,6 +157,18 @@ def plan_info(d, n):
     f, nnz, nf, mf = C.c_double(), C.c_int64(), C.c_int32(), C.c_int32()
     check(lib().rve_plan_info(d, n, C.byref(f), C.byref(nnz), C.byref(nf), C.byref(mf)), "rve_plan_info")
     return dict(factor_flops=f.value, nnz_L=nnz.value, nfronts=nf.value, max_front=mf.value)
+
+
+def plan_schedule(d, n):
+    """Workgroup-front steps [nsteps, 2] (front, partner or -1) and the per-front
+    wave-phase flags of the (d, n) plan."""
+    ns = np.zeros(1, np.int64)
+    check(lib().rve_plan_schedule(d, n, _ptr(ns), None, None), "rve_plan_schedule")
+    nf = plan_info(d, n)["nfronts"]
+    steps = np.zeros((int(ns[0]), 2), np.int32)
+    wave = np.zeros(nf, np.int32)
+    check(lib().rve_plan_schedule(d, n, _ptr(ns), _ptr(steps), _ptr(wave)), "rve_plan_schedule")
+    return dict(steps=steps, wave=wave)
 
 
 def plan_export(d, n):

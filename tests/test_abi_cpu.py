@@ -148,6 +148,38 @@ def test_plan_drives_a_correct_multifrontal_solve(d, n):
     assert np.all(x[:d] == 0)
 
 
+@pytest.mark.parametrize("d,n", [(2, 12), (2, 16), (2, 24), (2, 32), (3, 3), (3, 4)])
+def test_workgroup_front_schedule(d, n):
+    """Every workgroup front is processed once, after its children; two fronts
+    sharing a step are independent, have equal pivot and child counts (the
+    kernel's halves then pass the same barriers), at most 128 rows each, and fit
+    the front region (largest packed front plus its rhs rows and diagonal)."""
+    sch = rve.plan_schedule(d, n)
+    e = rve.plan_export(d, n)
+    fr, ch = e["fronts"], e["children"]
+    m, p, cb, ce = fr[:, 0], fr[:, 1], fr[:, 5], fr[:, 6]
+    wave = sch["wave"].astype(bool)
+    done = wave.copy()
+    seen = np.zeros(len(fr), int)
+    mm = int(m.max())
+    region = mm * (mm + 1) // 2 + mm * (d * d + 1)
+    for a, b in sch["steps"]:
+        for s in (a, b):
+            if s < 0:
+                continue
+            assert not wave[s]
+            assert all(done[ch[q]] for q in range(cb[s], ce[s])), (a, b)
+            seen[s] += 1
+        if b >= 0:
+            assert p[a] == p[b] and ce[a] - cb[a] == ce[b] - cb[b]
+            assert max(m[a], m[b]) <= 128
+            assert m[a] * (m[a] + 1) // 2 + m[b] * (m[b] + 1) // 2 + (m[a] + m[b]) * (d * d + 1) <= region
+        done[[s for s in (a, b) if s >= 0]] = True
+    assert np.all(seen[~wave] == 1) and np.all(seen[wave] == 0)
+    if (d, n) == (2, 32):
+        assert (sch["steps"][:, 1] >= 0).sum() == 12  # the 24 small separator fronts in pairs
+
+
 def test_fehmm_symbols_exported():
     from paper_1908_08292_amd import fehmm
     names = fehmm.declared_functions()
