@@ -399,7 +399,10 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
         // workgroup fronts by height (children first).  Two of one height are
         // independent; with equal p and child counts they pass the same barriers,
         // so they can share a step when each has at most 128 rows (one thread per
-        // row in half of a 256-thread workgroup) and both fit the front region.
+        // row in half of a 256-thread workgroup) and both fit the front region:
+        // the two packed fronts with their rhs rows and diagonals, and in the
+        // backward substitution the two staged panels with their FP64 scratch
+        // (d^2 m + 3 p doubles, i.e. twice as many FP32 elements).
         const int64_t mm = P.max_m, region = mm * (mm + 1) / 2 + mm * (d * d + 1);
         int hmax = 0;
         for (const FrontHost& F : P.fronts) hmax = std::max(hmax, F.height);
@@ -417,8 +420,12 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
                     const FrontHost& Bf = P.fronts[lst[b]];
                     const int64_t need = (int64_t)A.m * (A.m + 1) / 2 + (int64_t)Bf.m * (Bf.m + 1) / 2 +
                                          (int64_t)(A.m + Bf.m) * (d * d + 1);
+                    auto panel = [](const FrontHost& X) { return (int64_t)X.p * X.m - (int64_t)X.p * (X.p - 1) / 2; };
+                    const int64_t bneed = panel(A) + panel(Bf) +
+                                          2 * ((int64_t)d * d * (A.m + Bf.m) + 3 * (int64_t)(A.p + Bf.p)) + 2;
                     if (!used[b] && Bf.m <= 128 && Bf.p == A.p &&
-                        Bf.child_end - Bf.child_begin == A.child_end - A.child_begin && need <= region) {
+                        Bf.child_end - Bf.child_begin == A.child_end - A.child_begin && need <= region &&
+                        bneed <= region) {
                         partner = lst[b];
                         used[b] = 1;
                         break;

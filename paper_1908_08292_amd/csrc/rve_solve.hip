@@ -1463,6 +1463,135 @@ __device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
 // memory and the LDS front buffer serves as FP64 scratch.  16-pivot blocks from
 // the last: the block triangle is solved in registers of wave 0 (readlane
 // chain), then all threads fold the block into the remaining pivots.
+// Backward substitution of one workgroup front s on threads gt = 0..GT-1 (wave
+// gw of the group; the whole workgroup, or one half of it beside a second
+// front): the packed L panel staged at Ls (or read from global memory when Ls is
+// null), FP64 scratch vb ([NRHS][p] pivot values, [NRHS][m-p] update-row
+// solution, [3][p] partial sums), then the update-row products, the pivot
+// triangle in 16-pivot blocks (readlane chains in wave 0 of the group) and the
+// solution scattered to x.  Fronts sharing a step have equal pivot counts, so
+// both halves pass the same barriers.
+template <int D, int NRHS, typename T>
+__device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, double* x, int gt, int GT, int gw) {
+    const DevPlan& pl = *c.plan;
+    const int lane = threadIdx.x & 63;
+    constexpr int NPART = (NRHS == 1) ? 3 : 1;
+    const DevFront fr = pl.fronts[s];
+    const int m = fr.m, p = fr.p;
+    const int32_t* rows = pl.rows + fr.rows_off;
+    const T* Lg = reinterpret_cast<const T*>(c.L + fr.L_off);
+    const double* Dg = c.L + fr.D_off;
+    const double* yg = c.L + fr.y_off;
+    const int lp = cpk(p, m);
+    const T* Lp = Lg;
+    if (Ls) {
+        copy_in(Ls, Lg, lp, gt, GT);
+        Lp = Ls;
+    }
+    double* v = vb;                 // [NRHS][p]
+    double* xs = vb + NRHS * p;     // [NRHS][m - p]
+    double* part = vb + NRHS * m;   // [NPART][p] (NRHS == 1)
+    for (int t = gt; t < p * NRHS; t += GT) {
+        const int j = t % p, q = t / p;
+        v[t] = yg[(int64_t)q * p + j] / Dg[j];
+    }
+    for (int t = gt; t < (m - p) * NRHS; t += GT) {
+        const int i = t % (m - p), q = t / (m - p);
+        xs[t] = x[(int64_t)rows[p + i] * NRHS + q];
+    }
+    __syncthreads();
+    if constexpr (NRHS == 1) {
+        for (int t = gt; t < NPART * p; t += GT) {
+            const int j = t % p, pt = t / p;
+            const T* colj = Lp + cpk(j, m) - j;
+            double acc = 0.0;
+            for (int i = p + pt; i < m; i += NPART) acc += (double)colj[i] * xs[i - p];
+            part[t] = acc;
+        }
+        __syncthreads();
+        for (int j = gt; j < p; j += GT) v[j] -= (part[j] + part[p + j]) + part[2 * p + j];
+    } else {
+        for (int j = gt; j < p; j += GT) {
+            const T* colj = Lp + cpk(j, m) - j;
+            double acc[NRHS];
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) acc[q] = 0.0;
+            for (int i = p; i < m; ++i) {
+                const double l = colj[i];
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) acc[q] += l * xs[q * (m - p) + i - p];
+            }
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) v[q * p + j] -= acc[q];
+        }
+    }
+    __syncthreads();
+    if (p <= 64) {
+        // the pivot triangle by the group's wave 0 alone, lane = pivot, from the last pivot
+        // (readlane broadcasts of the finished values, no barrier)
+        if (gw == 0) {
+            const int jl = lane < p ? lane : 0;
+            const T* colj = Lp + cpk(jl, m) - jl;  // L(i, lane) = colj[i], i >= lane
+            double vv[NRHS];
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) vv[q] = lane < p ? v[q * p + lane] : 0.0;
+            for (int i = p - 1; i > 0; --i) {
+                const double l = (lane < i) ? (double)colj[i] : 0.0;
+#pragma unroll
+                for (int q = 0; q < NRHS; ++q) vv[q] -= l * readlane_d(vv[q], i);
+            }
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q)
+                if (lane < p) v[q * p + lane] = vv[q];
+        }
+        __syncthreads();
+    }
+    const int nb = p <= 64 ? 0 : (p + 15) >> 4;
+    for (int bk = nb - 1; bk >= 0; --bk) {
+        const int K = 16 * bk, kb = min(16, p - K);
+        if (gw == 0) {
+            const bool own = lane < kb;
+            double Lr[16];
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc)
+                Lr[cc] = (own && cc < kb && cc > lane) ? (double)Lp[cpk(K + lane, m) + cc - lane] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) {
+                double vv = own ? v[q * p + K + lane] : 0.0;
+#pragma unroll
+                for (int cc = 15; cc >= 0; --cc) {
+                    if (cc < kb) {
+                        const double xc = readlane_d(vv, cc);
+                        if (lane < cc) vv -= Lr[cc] * xc;
+                    }
+                }
+                if (own) v[q * p + K + lane] = vv;
+            }
+        }
+        __syncthreads();
+        for (int j = gt; j < K; j += GT) {
+            const T* colj = Lp + cpk(j, m) - j;
+            double lk[16];
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) lk[cc] = (cc < kb) ? (double)colj[K + cc] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) {
+                double acc = v[q * p + j];
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc)
+                    if (cc < kb) acc -= lk[cc] * v[q * p + K + cc];
+                v[q * p + j] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    for (int t = gt; t < p * NRHS; t += GT) {
+        const int j = t % p, q = t / p;
+        x[(int64_t)rows[j] * NRHS + q] = v[t];
+    }
+    __syncthreads();
+}
+
 template <int D, int NRHS, typename T>
 __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* rl, double* x, int front_elems,
                                          int wave_slice) {
@@ -1472,134 +1601,34 @@ __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* r
     for (int t = tid; t < D * NRHS; t += NT) x[t] = 0.0;  // pinned node
     // large fronts (the top of the tree) with the whole workgroup, then the
     // small subtrees wave by wave
-    for (int s = pl.nfront - 1; s >= 0; --s) {
-        const DevFront fr = pl.fronts[s];
-        if (fr.wave) continue;
-        const int m = fr.m, p = fr.p;
-        const int32_t* rows = pl.rows + fr.rows_off;
-        const T* Lg = reinterpret_cast<const T*>(c.L + fr.L_off);
-        const double* Dg = c.L + fr.D_off;
-        const double* yg = c.L + fr.y_off;
-        const int lp = cpk(p, m);
-        const T* Lp;
+    for (int st = pl.nwg_steps - 1; st >= 0; --st) {
+        const int s0 = pl.wg_steps[2 * st], s1 = pl.wg_steps[2 * st + 1];
+        const bool two = s1 >= 0;
+        const int g = (two && tid >= NT / 2) ? 1 : 0;
+        const int GT = two ? NT / 2 : NT;
+        const int s = g ? s1 : s0;
+        const int m = pl.fronts[s].m, p = pl.fronts[s].p, lp = cpk(p, m);
+        // scratch and staged panel: one front uses the front region and (FP64) the
+        // rhs region as before; two fronts split the front region, each taking
+        // [panel | FP64 scratch] (FP32: [FP64 scratch | panel]) in turn
+        constexpr int dpe = sizeof(double) / sizeof(T);  // T elements per double
+        const int vneed = dpe * (m * NRHS + 3 * p);
+        T* base = F;
+        if (g) {
+            const int m0 = pl.fronts[s0].m, p0 = pl.fronts[s0].p;
+            base = F + ((cpk(p0, m0) + dpe * (m0 * NRHS + 3 * p0) + 1) & ~1);
+        }
+        T* Ls;
         double* vb;
         if constexpr (sizeof(T) == sizeof(double)) {
-            copy_in(F, Lg, lp, tid, NT);
-            Lp = F;
-            vb = reinterpret_cast<double*>(rl);
+            Ls = base;
+            vb = two ? reinterpret_cast<double*>(base + lp) : reinterpret_cast<double*>(rl);
         } else {
             // FP32 panel staged after the FP64 scratch when both fit the front region
-            const int vneed = 2 * (m * NRHS + 3 * p);
-            if (vneed + lp <= front_elems) {
-                copy_in(F + vneed, Lg, lp, tid, NT);
-                Lp = F + vneed;
-            } else {
-                Lp = Lg;
-            }
-            vb = reinterpret_cast<double*>(F);
+            vb = reinterpret_cast<double*>(base);
+            Ls = (two || vneed + lp <= front_elems) ? base + vneed : nullptr;
         }
-        double* v = vb;                 // [NRHS][p]
-        double* xs = vb + NRHS * p;     // [NRHS][m - p]
-        double* part = vb + NRHS * m;   // [NPART][p] (NRHS == 1)
-        for (int t = tid; t < p * NRHS; t += NT) {
-            const int j = t % p, q = t / p;
-            v[t] = yg[(int64_t)q * p + j] / Dg[j];
-        }
-        for (int t = tid; t < (m - p) * NRHS; t += NT) {
-            const int i = t % (m - p), q = t / (m - p);
-            xs[t] = x[(int64_t)rows[p + i] * NRHS + q];
-        }
-        __syncthreads();
-        if constexpr (NRHS == 1) {
-            for (int t = tid; t < NPART * p; t += NT) {
-                const int j = t % p, pt = t / p;
-                const T* colj = Lp + cpk(j, m) - j;
-                double acc = 0.0;
-                for (int i = p + pt; i < m; i += NPART) acc += (double)colj[i] * xs[i - p];
-                part[t] = acc;
-            }
-            __syncthreads();
-            for (int j = tid; j < p; j += NT) v[j] -= (part[j] + part[p + j]) + part[2 * p + j];
-        } else {
-            for (int j = tid; j < p; j += NT) {
-                const T* colj = Lp + cpk(j, m) - j;
-                double acc[NRHS];
-#pragma unroll
-                for (int q = 0; q < NRHS; ++q) acc[q] = 0.0;
-                for (int i = p; i < m; ++i) {
-                    const double l = colj[i];
-#pragma unroll
-                    for (int q = 0; q < NRHS; ++q) acc[q] += l * xs[q * (m - p) + i - p];
-                }
-#pragma unroll
-                for (int q = 0; q < NRHS; ++q) v[q * p + j] -= acc[q];
-            }
-        }
-        __syncthreads();
-        if (p <= 64) {
-            // the pivot triangle by wave 0 alone, lane = pivot, from the last pivot
-            // (readlane broadcasts of the finished values, no barrier)
-            if (wave == 0) {
-                const int jl = lane < p ? lane : 0;
-                const T* colj = Lp + cpk(jl, m) - jl;  // L(i, lane) = colj[i], i >= lane
-                double vv[NRHS];
-#pragma unroll
-                for (int q = 0; q < NRHS; ++q) vv[q] = lane < p ? v[q * p + lane] : 0.0;
-                for (int i = p - 1; i > 0; --i) {
-                    const double l = (lane < i) ? (double)colj[i] : 0.0;
-#pragma unroll
-                    for (int q = 0; q < NRHS; ++q) vv[q] -= l * readlane_d(vv[q], i);
-                }
-#pragma unroll
-                for (int q = 0; q < NRHS; ++q)
-                    if (lane < p) v[q * p + lane] = vv[q];
-            }
-            __syncthreads();
-        }
-        const int nb = p <= 64 ? 0 : (p + 15) >> 4;
-        for (int bk = nb - 1; bk >= 0; --bk) {
-            const int K = 16 * bk, kb = min(16, p - K);
-            if (wave == 0) {
-                const bool own = lane < kb;
-                double Lr[16];
-#pragma unroll
-                for (int cc = 0; cc < 16; ++cc)
-                    Lr[cc] = (own && cc < kb && cc > lane) ? (double)Lp[cpk(K + lane, m) + cc - lane] : 0.0;
-#pragma unroll
-                for (int q = 0; q < NRHS; ++q) {
-                    double vv = own ? v[q * p + K + lane] : 0.0;
-#pragma unroll
-                    for (int cc = 15; cc >= 0; --cc) {
-                        if (cc < kb) {
-                            const double xc = readlane_d(vv, cc);
-                            if (lane < cc) vv -= Lr[cc] * xc;
-                        }
-                    }
-                    if (own) v[q * p + K + lane] = vv;
-                }
-            }
-            __syncthreads();
-            for (int j = tid; j < K; j += NT) {
-                const T* colj = Lp + cpk(j, m) - j;
-                double lk[16];
-#pragma unroll
-                for (int cc = 0; cc < 16; ++cc) lk[cc] = (cc < kb) ? (double)colj[K + cc] : 0.0;
-#pragma unroll
-                for (int q = 0; q < NRHS; ++q) {
-                    double acc = v[q * p + j];
-#pragma unroll
-                    for (int cc = 0; cc < 16; ++cc)
-                        if (cc < kb) acc -= lk[cc] * v[q * p + K + cc];
-                    v[q * p + j] = acc;
-                }
-            }
-            __syncthreads();
-        }
-        for (int t = tid; t < p * NRHS; t += NT) {
-            const int j = t % p, q = t / p;
-            x[(int64_t)rows[j] * NRHS + q] = v[t];
-        }
-        __syncthreads();
+        wg_backsolve<D, NRHS, T>(c, s, Ls, vb, x, tid - g * GT, GT, wave - g * (two ? NWAVE / 2 : NWAVE));
     }
     // small subtrees: one front per wave, parents (greater height) first
     for (int h = pl.nwave_h - 1; h >= 0; --h) {

@@ -153,7 +153,8 @@ def test_workgroup_front_schedule(d, n):
     """Every workgroup front is processed once, after its children; two fronts
     sharing a step are independent, have equal pivot and child counts (the
     kernel's halves then pass the same barriers), at most 128 rows each, and fit
-    the front region (largest packed front plus its rhs rows and diagonal)."""
+    the front region (largest packed front plus its rhs rows and diagonal), also
+    with their staged panels and FP64 scratch in the backward substitution."""
     sch = rve.plan_schedule(d, n)
     e = rve.plan_export(d, n)
     fr, ch = e["fronts"], e["children"]
@@ -174,6 +175,8 @@ def test_workgroup_front_schedule(d, n):
             assert p[a] == p[b] and ce[a] - cb[a] == ce[b] - cb[b]
             assert max(m[a], m[b]) <= 128
             assert m[a] * (m[a] + 1) // 2 + m[b] * (m[b] + 1) // 2 + (m[a] + m[b]) * (d * d + 1) <= region
+            panel = [p[s] * m[s] - p[s] * (p[s] - 1) // 2 for s in (a, b)]
+            assert sum(panel) + 2 * (d * d * (m[a] + m[b]) + 3 * (p[a] + p[b])) + 2 <= region
         done[[s for s in (a, b) if s >= 0]] = True
     assert np.all(seen[~wave] == 1) and np.all(seen[wave] == 0)
     if (d, n) == (2, 32):
