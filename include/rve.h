@@ -204,11 +204,11 @@ int rve_plan_export(int32_t ndim, int32_t n, int64_t* sizes, int32_t* fronts, in
 
 /* Processing schedule of the (ndim, n) plan's LDS path, for tooling and tests
  * (host only).  *nsteps receives the number of workgroup-front steps (0 when
- * the fronts live in global memory); steps, if non-NULL, receives [nsteps][2]
- * = (front, second front processed beside it on the other half of the
- * workgroup, or -1) in processing order; wave, if non-NULL, receives one flag
- * per front (elimination order): 1 for the fronts eliminated one per wave
- * before the workgroup fronts. */
+ * the fronts live in global memory); steps, if non-NULL, receives [nsteps][4]
+ * in processing order: the 1, 2 or 4 fronts processed side by side on equal
+ * parts of the workgroup, -1 padded; wave, if non-NULL, receives one flag per
+ * front (elimination order): 1 for the fronts eliminated one per wave before
+ * the workgroup fronts. */
 int rve_plan_schedule(int32_t ndim, int32_t n, int64_t* nsteps, int32_t* steps, int32_t* wave);
 
 /* ---- errors ------------------------------------------------------------------ */

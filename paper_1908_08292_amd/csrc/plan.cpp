@@ -396,14 +396,18 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
         }
         P.wave_hbeg.push_back((int32_t)P.wave_list.size());
         P.wave_slice = (P.wave_slice + 31) / 32 * 32;
-        // workgroup fronts by height (children first).  Two of one height are
+        // workgroup fronts by height (children first).  Fronts of one height are
         // independent; with equal p and child counts they pass the same barriers,
-        // so they can share a step when each has at most 128 rows (one thread per
-        // row in half of a 256-thread workgroup) and both fit the front region:
-        // the two packed fronts with their rhs rows and diagonals, and in the
-        // backward substitution the two staged panels with their FP64 scratch
-        // (d^2 m + 3 p doubles, i.e. twice as many FP32 elements).
+        // so up to kStepFronts of them can share a step (each on a group of at
+        // least 128 threads, one per front row: m <= 128) when together they fit
+        // the front region: the packed fronts with their rhs rows and diagonals,
+        // and in the backward substitution the staged panels with their FP64
+        // scratch (d^2 m + 3 p doubles, i.e. twice as many FP32 elements).
         const int64_t mm = P.max_m, region = mm * (mm + 1) / 2 + mm * (d * d + 1);
+        auto fneed = [&](const FrontHost& X) { return (int64_t)X.m * (X.m + 1) / 2 + (int64_t)X.m * (d * d + 1); };
+        auto bneed = [&](const FrontHost& X) {
+            return (int64_t)X.p * X.m - (int64_t)X.p * (X.p - 1) / 2 + 2 * ((int64_t)d * d * X.m + 3 * (int64_t)X.p) + 1;
+        };
         int hmax = 0;
         for (const FrontHost& F : P.fronts) hmax = std::max(hmax, F.height);
         for (int h = 0; h <= hmax; ++h) {
@@ -415,24 +419,25 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
                 if (used[a]) continue;
                 used[a] = 1;
                 const FrontHost& A = P.fronts[lst[a]];
-                int partner = -1;
-                for (size_t b = a + 1; b < lst.size() && A.m <= 128; ++b) {
+                std::vector<int> grp = {lst[a]};
+                int64_t fsum = fneed(A), bsum = bneed(A);
+                for (size_t b = a + 1; b < lst.size() && A.m <= 128 && (int)grp.size() < kStepFronts; ++b) {
                     const FrontHost& Bf = P.fronts[lst[b]];
-                    const int64_t need = (int64_t)A.m * (A.m + 1) / 2 + (int64_t)Bf.m * (Bf.m + 1) / 2 +
-                                         (int64_t)(A.m + Bf.m) * (d * d + 1);
-                    auto panel = [](const FrontHost& X) { return (int64_t)X.p * X.m - (int64_t)X.p * (X.p - 1) / 2; };
-                    const int64_t bneed = panel(A) + panel(Bf) +
-                                          2 * ((int64_t)d * d * (A.m + Bf.m) + 3 * (int64_t)(A.p + Bf.p)) + 2;
                     if (!used[b] && Bf.m <= 128 && Bf.p == A.p &&
-                        Bf.child_end - Bf.child_begin == A.child_end - A.child_begin && need <= region &&
-                        bneed <= region) {
-                        partner = lst[b];
+                        Bf.child_end - Bf.child_begin == A.child_end - A.child_begin &&
+                        fsum + fneed(Bf) <= region && bsum + bneed(Bf) <= region) {
+                        grp.push_back(lst[b]);
+                        fsum += fneed(Bf);
+                        bsum += bneed(Bf);
                         used[b] = 1;
-                        break;
                     }
                 }
-                P.wg_steps.push_back(lst[a]);
-                P.wg_steps.push_back(partner);
+                // 1, 2 or 4 fronts per step (the kernel splits the workgroup evenly)
+                while (grp.size() == 3) {
+                    used[std::find(lst.begin(), lst.end(), grp.back()) - lst.begin()] = 0;
+                    grp.pop_back();
+                }
+                for (int k = 0; k < kStepFronts; ++k) P.wg_steps.push_back(k < (int)grp.size() ? grp[k] : -1);
             }
         }
     }

@@ -65,9 +65,10 @@ struct PlanHost {
     // fronts processed wave-per-front before the workgroup fronts, grouped by
     // height (all fronts of one height are independent)
     std::vector<int32_t> wave_list, wave_hbeg;
-    // the other (workgroup) fronts in processing order, two entries per step:
-    // {s, -1} one front on the whole workgroup, {s, s2} two independent fronts
-    // (equal height, pivot and child counts) side by side on its two halves
+    // the other (workgroup) fronts in processing order, kStepFronts entries per
+    // step (-1 padded): one front on the whole workgroup, or 2 or 4 independent
+    // fronts (equal height, pivot and child counts) side by side on equal parts
+    // of it
     std::vector<int32_t> wg_steps;
     int64_t wave_slice = 0;    // doubles of one wave's LDS slice (packed front + rhs rows)
     bool lds_path = false;     // every front fits the LDS front buffer
@@ -82,6 +83,7 @@ struct PlanHost {
 // LDS budget of the front buffer (packed front + its m x d^2 rhs rows)
 constexpr int64_t kLdsFrontBytes = 148 * 1024;
 constexpr int kWaveFrontMaxM = 64;
+constexpr int kStepFronts = 4;  // fronts per workgroup-front step at most
 
 // Builds the plan; throws std::runtime_error on unsupported (d, n).
 // structural parameters of a plan (the autotuner's plan-level knobs)

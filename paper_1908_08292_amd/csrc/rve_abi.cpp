@@ -157,7 +157,7 @@ int plan_device(PlanEntry* e) {
                      e->d_fronts, e->d_rows, e->d_relind, e->d_children, e->d_kpair, e->d_kcontrib,
                      e->d_asm_rc, e->d_asm_src, e->d_ea_dst, e->d_wave_list, e->d_wave_hbeg,
                      (int32_t)P.wave_hbeg.size() - 1, (int32_t)P.wave_slice, e->d_wg_steps,
-                     (int32_t)(P.wg_steps.size() / 2)};
+                     (int32_t)(P.wg_steps.size() / kStepFronts)};
     if (P.wave_hbeg.empty()) e->dev.nwave_h = 0;
     // whole fronts in LDS when the largest packed front plus its rhs rows fit;
     // the front region also hosts the FP64 scratch of the triangular solves
@@ -616,7 +616,7 @@ extern "C" int rve_plan_schedule(int32_t ndim, int32_t n, int64_t* nsteps, int32
     if (st) return st;
     const PlanHost& P = e->host;
     if (!nsteps) return fail(RVE_EINVAL, "rve_plan_schedule: nsteps is required");
-    *nsteps = P.lds_path ? (int64_t)(P.wg_steps.size() / 2) : 0;
+    *nsteps = P.lds_path ? (int64_t)(P.wg_steps.size() / kStepFronts) : 0;
     if (steps && P.lds_path) std::memcpy(steps, P.wg_steps.data(), P.wg_steps.size() * sizeof(int32_t));
     if (wave)
         for (size_t s = 0; s < P.fronts.size(); ++s) wave[s] = P.lds_path ? P.fronts[s].wave : 0;

@@ -69,7 +69,7 @@ __device__ unsigned long long g_phase[PH_N];
 #endif
 
 struct Smem {
-    double pub[2][2][18 + kMaxNrhs];  // pivot publication per workgroup half (double-buffered)
+    double pub[kStepFronts][2][18 + kMaxNrhs];  // pivot publication per front group (double-buffered)
     double red[NWAVE * 81];
     double dN[8 * 8 * 3];    // [gp][a][k]
     double Fbar[9];
@@ -1399,18 +1399,27 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* r
         __syncthreads();
     }
     PROF_MARK(PH_TRSM);
-    // workgroup fronts: one per step on the whole workgroup, or two side by side
-    // on its halves (the second one's storage after the first one's rhs rows)
+    // workgroup fronts: one per step on the whole workgroup, or nf = 2 or 4 side
+    // by side on G equal groups of threads (at least 128 each; with fewer groups
+    // than fronts each group takes nf / G of them in turn), front k's storage
+    // after the rhs rows of fronts 0..k-1
     for (int st = 0; st < pl.nwg_steps; ++st) {
-        const int s0 = pl.wg_steps[2 * st], s1 = pl.wg_steps[2 * st + 1];
-        const bool two = s1 >= 0;
-        const int g = (two && tid >= NT / 2) ? 1 : 0;
-        const int GT = two ? NT / 2 : NT, NW = two ? NWAVE / 2 : NWAVE;
-        const int s = g ? s1 : s0;
-        const int m0 = pl.fronts[s0].m, ms = pl.fronts[s].m;
-        T* const Fg = g ? F + cpk(m0, m0) + m0 * (nrhs + 1) : F;
-        T* const rlg = two ? Fg + cpk(ms, ms) : rl;
-        wg_front<D, NRHS, T>(c, sm, s, Fg, rlg, tid - g * GT, GT, wave - g * NW, NW, sm.pub[g]);
+        const int32_t* e = pl.wg_steps + kStepFronts * st;
+        const int nf = e[3] >= 0 ? 4 : (e[1] >= 0 ? 2 : 1);
+        const int G = min(nf, NT / 128);
+        const int GT = NT / G, NW = NWAVE / G, g = tid / GT;
+        for (int r = 0; r < nf / G; ++r) {
+            const int k = r * G + g;
+            int off = 0;
+            for (int j = 0; j < k; ++j) {
+                const int mj = pl.fronts[e[j]].m;
+                off += cpk(mj, mj) + mj * (nrhs + 1);
+            }
+            const int ms = pl.fronts[e[k]].m;
+            T* const Fk = F + off;
+            T* const rlk = nf > 1 ? Fk + cpk(ms, ms) : rl;
+            wg_front<D, NRHS, T>(c, sm, e[k], Fk, rlk, tid - g * GT, GT, wave - g * NW, NW, sm.pub[g]);
+        }
     }
 }
 
@@ -1602,33 +1611,37 @@ __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* r
     // large fronts (the top of the tree) with the whole workgroup, then the
     // small subtrees wave by wave
     for (int st = pl.nwg_steps - 1; st >= 0; --st) {
-        const int s0 = pl.wg_steps[2 * st], s1 = pl.wg_steps[2 * st + 1];
-        const bool two = s1 >= 0;
-        const int g = (two && tid >= NT / 2) ? 1 : 0;
-        const int GT = two ? NT / 2 : NT;
-        const int s = g ? s1 : s0;
-        const int m = pl.fronts[s].m, p = pl.fronts[s].p, lp = cpk(p, m);
+        const int32_t* e = pl.wg_steps + kStepFronts * st;
+        const int nf = e[3] >= 0 ? 4 : (e[1] >= 0 ? 2 : 1);
+        const int G = min(nf, NT / 128);
+        const int GT = NT / G, NW = NWAVE / G, g = tid / GT;
         // scratch and staged panel: one front uses the front region and (FP64) the
-        // rhs region as before; two fronts split the front region, each taking
-        // [panel | FP64 scratch] (FP32: [FP64 scratch | panel]) in turn
+        // rhs region as before; several fronts split the front region, front k
+        // taking [panel | FP64 scratch] (FP32: [FP64 scratch | panel]) after
+        // those of fronts 0..k-1
         constexpr int dpe = sizeof(double) / sizeof(T);  // T elements per double
-        const int vneed = dpe * (m * NRHS + 3 * p);
-        T* base = F;
-        if (g) {
-            const int m0 = pl.fronts[s0].m, p0 = pl.fronts[s0].p;
-            base = F + ((cpk(p0, m0) + dpe * (m0 * NRHS + 3 * p0) + 1) & ~1);
+        for (int r = 0; r < nf / G; ++r) {
+            const int k = r * G + g;
+            int off = 0;
+            for (int j = 0; j < k; ++j) {
+                const int mj = pl.fronts[e[j]].m, pj = pl.fronts[e[j]].p;
+                off += (cpk(pj, mj) + dpe * (mj * NRHS + 3 * pj) + 1) & ~1;
+            }
+            const int m = pl.fronts[e[k]].m, p = pl.fronts[e[k]].p, lp = cpk(p, m);
+            const int vneed = dpe * (m * NRHS + 3 * p);
+            T* const base = F + off;
+            T* Ls;
+            double* vb;
+            if constexpr (sizeof(T) == sizeof(double)) {
+                Ls = base;
+                vb = nf > 1 ? reinterpret_cast<double*>(base + lp) : reinterpret_cast<double*>(rl);
+            } else {
+                // FP32 panel staged after the FP64 scratch when both fit the front region
+                vb = reinterpret_cast<double*>(base);
+                Ls = (nf > 1 || vneed + lp <= front_elems) ? base + vneed : nullptr;
+            }
+            wg_backsolve<D, NRHS, T>(c, e[k], Ls, vb, x, tid - g * GT, GT, wave - g * NW);
         }
-        T* Ls;
-        double* vb;
-        if constexpr (sizeof(T) == sizeof(double)) {
-            Ls = base;
-            vb = two ? reinterpret_cast<double*>(base + lp) : reinterpret_cast<double*>(rl);
-        } else {
-            // FP32 panel staged after the FP64 scratch when both fit the front region
-            vb = reinterpret_cast<double*>(base);
-            Ls = (two || vneed + lp <= front_elems) ? base + vneed : nullptr;
-        }
-        wg_backsolve<D, NRHS, T>(c, s, Ls, vb, x, tid - g * GT, GT, wave - g * (two ? NWAVE / 2 : NWAVE));
     }
     // small subtrees: one front per wave, parents (greater height) first
     for (int h = pl.nwave_h - 1; h >= 0; --h) {

@@ -26,7 +26,7 @@ struct DevPlan {
     const int32_t* wave_hbeg;
     int32_t nwave_h;       // number of heights in the wave phase
     int32_t wave_slice;    // doubles per wave slice
-    const int32_t* wg_steps;  // [nwg_steps][2] workgroup-front steps (second front or -1)
+    const int32_t* wg_steps;  // [nwg_steps][kStepFronts] workgroup-front steps (-1 padded)
     int32_t nwg_steps;
 };
 

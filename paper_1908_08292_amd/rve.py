@@ -160,12 +160,12 @@ def plan_info(d, n):
 
 
 def plan_schedule(d, n):
-    """Workgroup-front steps [nsteps, 2] (front, partner or -1) and the per-front
-    wave-phase flags of the (d, n) plan."""
+    """Workgroup-front steps [nsteps, 4] (1, 2 or 4 fronts side by side, -1
+    padded) and the per-front wave-phase flags of the (d, n) plan."""
     ns = np.zeros(1, np.int64)
     check(lib().rve_plan_schedule(d, n, _ptr(ns), None, None), "rve_plan_schedule")
     nf = plan_info(d, n)["nfronts"]
-    steps = np.zeros((int(ns[0]), 2), np.int32)
+    steps = np.zeros((int(ns[0]), 4), np.int32)
     wave = np.zeros(nf, np.int32)
     check(lib().rve_plan_schedule(d, n, _ptr(ns), _ptr(steps), _ptr(wave)), "rve_plan_schedule")
     return dict(steps=steps, wave=wave)

@@ -150,11 +150,12 @@ def test_plan_drives_a_correct_multifrontal_solve(d, n):
 
 @pytest.mark.parametrize("d,n", [(2, 12), (2, 16), (2, 24), (2, 32), (3, 3), (3, 4)])
 def test_workgroup_front_schedule(d, n):
-    """Every workgroup front is processed once, after its children; two fronts
-    sharing a step are independent, have equal pivot and child counts (the
-    kernel's halves then pass the same barriers), at most 128 rows each, and fit
-    the front region (largest packed front plus its rhs rows and diagonal), also
-    with their staged panels and FP64 scratch in the backward substitution."""
+    """Every workgroup front is processed once, after its children; the 1, 2 or 4
+    fronts sharing a step are independent, have equal pivot and child counts
+    (the kernel's thread groups then pass the same barriers), at most 128 rows
+    each, and fit the front region (largest packed front plus its rhs rows and
+    diagonal) together, also with their staged panels and FP64 scratch in the
+    backward substitution."""
     sch = rve.plan_schedule(d, n)
     e = rve.plan_export(d, n)
     fr, ch = e["fronts"], e["children"]
@@ -164,23 +165,26 @@ def test_workgroup_front_schedule(d, n):
     seen = np.zeros(len(fr), int)
     mm = int(m.max())
     region = mm * (mm + 1) // 2 + mm * (d * d + 1)
-    for a, b in sch["steps"]:
-        for s in (a, b):
-            if s < 0:
-                continue
+    sizes = []
+    for step in sch["steps"]:
+        fs = [int(s) for s in step if s >= 0]
+        assert len(fs) in (1, 2, 4) and list(step[:len(fs)]) == fs
+        sizes.append(len(fs))
+        for s in fs:
             assert not wave[s]
-            assert all(done[ch[q]] for q in range(cb[s], ce[s])), (a, b)
+            assert all(done[ch[q]] for q in range(cb[s], ce[s])), step
             seen[s] += 1
-        if b >= 0:
-            assert p[a] == p[b] and ce[a] - cb[a] == ce[b] - cb[b]
-            assert max(m[a], m[b]) <= 128
-            assert m[a] * (m[a] + 1) // 2 + m[b] * (m[b] + 1) // 2 + (m[a] + m[b]) * (d * d + 1) <= region
-            panel = [p[s] * m[s] - p[s] * (p[s] - 1) // 2 for s in (a, b)]
-            assert sum(panel) + 2 * (d * d * (m[a] + m[b]) + 3 * (p[a] + p[b])) + 2 <= region
-        done[[s for s in (a, b) if s >= 0]] = True
+        if len(fs) > 1:
+            assert len({(p[s], ce[s] - cb[s]) for s in fs}) == 1
+            assert max(m[s] for s in fs) <= 128
+            assert sum(m[s] * (m[s] + 1) // 2 + m[s] * (d * d + 1) for s in fs) <= region
+            panel = [p[s] * m[s] - p[s] * (p[s] - 1) // 2 for s in fs]
+            assert sum(panel) + sum(2 * (d * d * m[s] + 3 * p[s]) + 1 for s in fs) <= region
+        done[fs] = True
     assert np.all(seen[~wave] == 1) and np.all(seen[wave] == 0)
     if (d, n) == (2, 32):
-        assert (sch["steps"][:, 1] >= 0).sum() == 12  # the 24 small separator fronts in pairs
+        # the 24 small separator fronts: 16 of at most 78 rows four at a time, 8 in pairs
+        assert sorted(sizes, reverse=True)[:8] == [4, 4, 4, 4, 2, 2, 2, 2] and len(sizes) == 15
 
 
 def test_fehmm_symbols_exported():
