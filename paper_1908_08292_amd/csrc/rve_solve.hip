@@ -1306,9 +1306,15 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
                 __syncthreads();
                 if (own && i > K + j) {
                     const double l = r[j] * P[1];
+                    // every P entry is read (all within the buffer; entries past the
+                    // block are stale) and the multiplier selected, so the reads
+                    // need no branch of their own: r[cc] off the row's lower part or
+                    // past the block is neither stored nor used
 #pragma unroll
-                    for (int cc = j + 1; cc < 16; ++cc)
-                        if (cc < kb && K + cc <= i) r[cc] -= l * P[2 + cc];
+                    for (int cc = j + 1; cc < 16; ++cc) {
+                        const double lc = (cc < kb && K + cc <= i) ? l : 0.0;
+                        r[cc] -= lc * P[2 + cc];
+                    }
                     r[j] = l;
 #pragma unroll
                     for (int q = 0; q < NRHS; ++q) b[q] -= l * P[18 + q];
@@ -1492,8 +1498,9 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
     const double* Dg = c.L + fr.D_off;
     const double* yg = c.L + fr.y_off;
     const int lp = cpk(p, m);
+    // (FP64 panels are always staged: one address space for the reads)
     const T* Lp = Lg;
-    if (Ls) {
+    if (sizeof(T) == sizeof(double) || Ls) {
         copy_in(Ls, Lg, lp, gt, GT);
         Lp = Ls;
     }
