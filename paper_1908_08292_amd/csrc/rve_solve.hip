@@ -1063,9 +1063,15 @@ __device__ inline void extend_add_packed(const int32_t* ea, const T* Uc, int nu,
             e[u] = ea[t];
             v[u] = Uc[t];
         }
+        // the targets of a pass are distinct (a child adds to each parent entry
+        // once; clamped duplicates are read, never written): every target is read
+        // before any is written, one LDS round trip per pass
+        T o[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) o[u] = F[e[u]];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (t0 + u * stride < nu) F[e[u]] += v[u];
+            if (t0 + u * stride < nu) F[e[u]] = o[u] + v[u];
     }
 }
 
