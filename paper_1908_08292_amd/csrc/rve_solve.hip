@@ -1345,28 +1345,36 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
             while (rem > I) { rem -= I + 1; ++I; }
             const int J = rem;
             const int ra = T0 + 16 * I + (lane & 15), rb = T0 + 16 * J + (lane & 15);
-            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+            // operands from clamped addresses inside the front (column K and row
+            // m - 1 stand in past the block or the front) times 0/1 masks, so all
+            // twelve reads issue together without branches
+            double a[4], bb[4];
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
                 const int kk = 4 * ks + (lane >> 4);
-                const int kc = K + kk;
-                double a = 0.0, bb = 0.0;
-                if (kk < kb) {
-                    const int base = cpk(kc, m) - kc;
-                    const double dk = F[base + kc];
-                    if (ra < m) a = F[base + ra] * dk;
-                    if (rb < m) bb = F[base + rb];
-                }
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+                const int kc = kk < kb ? K + kk : K;
+                const int base = cpk(kc, m) - kc;
+                const double dk = F[base + kc];
+                const double ma = (kk < kb && ra < m) ? 1.0 : 0.0, mb = (kk < kb && rb < m) ? 1.0 : 0.0;
+                a[ks] = (double)F[base + min(ra, m - 1)] * dk * ma;
+                bb[ks] = (double)F[base + min(rb, m - 1)] * mb;
             }
-            const int cc = T0 + 16 * J + (lane & 15);
-            if (cc < m) {
-                const int base = cpk(cc, m) - cc;
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int rr = T0 + 16 * I + (lane >> 4) + 4 * v;
-                    if (rr < m && rr >= cc) F[base + rr] -= acc[v];
-                }
+            for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], bb[ks], acc, 0, 0, 0);
+            // the tile's targets are distinct: all four read (clamped), then written
+            const int cc = T0 + 16 * J + (lane & 15), ccl = min(cc, m - 1);
+            const int base = cpk(ccl, m) - ccl;
+            double o[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = T0 + 16 * I + (lane >> 4) + 4 * v;
+                o[v] = F[base + min(max(rr, ccl), m - 1)];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = T0 + 16 * I + (lane >> 4) + 4 * v;
+                if (cc < m && rr < m && rr >= cc) F[base + rr] = o[v] - acc[v];
             }
         }
         __syncthreads();
