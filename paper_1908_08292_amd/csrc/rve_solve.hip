@@ -1181,32 +1181,50 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
                 Jj[u] = rem;
                 acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
             }
+            // operands from clamped addresses inside the front (column K and row
+            // m - 1 stand in past the block, the front or the last tile) times 0/1
+            // masks: every read of both tiles issues without branches
+            double av[4][2], bv[4][2];
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
                 const int kk = 4 * ks + (lane >> 4);
-                const int kc = K + kk;
+                const int kc = kk < kb ? K + kk : K;
                 const int base = cpk(kc, m) - kc;
-                const double dk = (kk < kb) ? F[base + kc] : 0.0;
+                const double dk = F[base + kc];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     const int ra = R0 + 16 * Ii[u] + (lane & 15), rb = R0 + 16 * Jj[u] + (lane & 15);
                     const bool live = (t0 + u < ntile) && kk < kb;
-                    const double av = (live && ra < m) ? F[base + ra] * dk : 0.0;
-                    const double bv = (live && rb < m) ? F[base + rb] : 0.0;
-                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+                    const double ma = (live && ra < m) ? 1.0 : 0.0, mb = (live && rb < m) ? 1.0 : 0.0;
+                    av[ks][u] = (double)F[base + min(ra, m - 1)] * dk * ma;
+                    bv[ks][u] = (double)F[base + min(rb, m - 1)] * mb;
+                }
+            }
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][u], bv[ks][u], acc[u], 0, 0, 0);
+            // the tiles' targets are distinct: all eight read (clamped), then written
+            double o[2][4];
+            int bs[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int cc = R0 + 16 * Jj[u] + (lane & 15), ccl = min(cc, m - 1);
+                bs[u] = cpk(ccl, m) - ccl;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = R0 + 16 * Ii[u] + (lane >> 4) + 4 * v;
+                    o[u][v] = F[bs[u] + min(max(rr, ccl), m - 1)];
                 }
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                if (t0 + u >= ntile) continue;
                 const int cc = R0 + 16 * Jj[u] + (lane & 15);
-                if (cc < m) {
-                    const int base = cpk(cc, m) - cc;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int rr = R0 + 16 * Ii[u] + (lane >> 4) + 4 * v;
-                        if (rr < m && rr >= cc) F[base + rr] -= acc[u][v];
-                    }
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = R0 + 16 * Ii[u] + (lane >> 4) + 4 * v;
+                    if (t0 + u < ntile && cc < m && rr < m && rr >= cc) F[bs[u] + rr] = o[u][v] - acc[u][v];
                 }
             }
         }
