@@ -992,10 +992,12 @@ __device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& s
 }
 
 // Multifrontal LDL^T, fronts in LDS (F: packed front, rl: m x nrhs rhs rows).
-// Per pivot block of 16 columns: a row-owner sweep (one barrier per pivot) gives
-// the 16 L columns of every row and the forward-substituted rhs; the trailing
-// lower triangle is then updated with v_mfma_f64_16x16x4 (lane layouts:
-// A[l%16][l/16], B[l/16][l%16], D row = l/16 + 4 v, col = l%16).
+// Small subtrees first, one front per wave (wave_front); then the workgroup
+// fronts in the plan's steps of 1, 2 or 4 independent fronts side by side
+// (wg_front).  Per pivot block of 16 columns: a row-owner sweep (one barrier per
+// pivot) gives the 16 L columns of every row and the forward-substituted rhs;
+// the trailing lower triangle is then updated with v_mfma_f64_16x16x4 (lane
+// layouts: A[l%16][l/16], B[l/16][l%16], D row = l/16 + 4 v, col = l%16).
 
 
 // Original entries of an LDS front from the element matrices (one gather level)
