@@ -1490,13 +1490,16 @@ __device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
     // (in bounds: p + i < m <= cpk(p, m)) and discard the value
     const int jl = lane < p ? lane : 0;
     const int cj = cpk(jl, m) - jl;
+    // (unrolled: the panel reads do not depend on the chain and issue ahead)
+#pragma unroll 8
     for (int i = 0; i < mu; ++i) {
-        const double l = (lane < p) ? (double)S[cj + p + i] : 0.0;
+        const double l = (double)S[cj + p + i] * (lane < p ? 1.0 : 0.0);
 #pragma unroll
         for (int q = 0; q < NRHS; ++q) v[q] -= l * readlane_d(xs[q], i);
     }
+#pragma unroll 4
     for (int jj = p - 1; jj > 0; --jj) {
-        const double l = (lane < jj) ? (double)S[cj + jj] : 0.0;
+        const double l = (double)S[cj + jj] * (lane < jj ? 1.0 : 0.0);
 #pragma unroll
         for (int q = 0; q < NRHS; ++q) v[q] -= l * readlane_d(v[q], jj);
     }
@@ -1506,12 +1509,6 @@ __device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
     __builtin_amdgcn_wave_barrier();
 }
 
-// backward substitution L^T x = D^-1 y with NRHS columns; y is each front's
-// stored forward-substituted rhs, x (node-major [dof][NRHS], FP64) receives the
-// solution.  FP64 panels are staged in LDS; FP32 panels are read from global
-// memory and the LDS front buffer serves as FP64 scratch.  16-pivot blocks from
-// the last: the block triangle is solved in registers of wave 0 (readlane
-// chain), then all threads fold the block into the remaining pivots.
 // Backward substitution of one workgroup front s on threads gt = 0..GT-1 (wave
 // gw of the group; the whole workgroup, or one half of it beside a second
 // front): the packed L panel staged at Ls (or read from global memory when Ls is
@@ -1642,6 +1639,11 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
     __syncthreads();
 }
 
+// backward substitution L^T x = D^-1 y with NRHS columns; y is each front's
+// stored forward-substituted rhs, x (node-major [dof][NRHS], FP64) receives the
+// solution.  The workgroup fronts in the plan's steps, in reverse (wg_backsolve;
+// panels staged in LDS, for FP32 when they fit beside the FP64 scratch), then
+// the small subtrees one front per wave, parents first.
 template <int D, int NRHS, typename T>
 __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* rl, double* x, int front_elems,
                                          int wave_slice) {
