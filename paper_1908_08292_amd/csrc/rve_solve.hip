@@ -1552,6 +1552,7 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
             const int j = t % p, pt = t / p;
             const T* colj = Lp + cpk(j, m) - j;
             double acc = 0.0;
+#pragma unroll 4
             for (int i = p + pt; i < m; i += NPART) acc += (double)colj[i] * xs[i - p];
             part[t] = acc;
         }
@@ -1563,6 +1564,7 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
             double acc[NRHS];
 #pragma unroll
             for (int q = 0; q < NRHS; ++q) acc[q] = 0.0;
+#pragma unroll 4
             for (int i = p; i < m; ++i) {
                 const double l = colj[i];
 #pragma unroll
@@ -1582,8 +1584,11 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
             double vv[NRHS];
 #pragma unroll
             for (int q = 0; q < NRHS; ++q) vv[q] = lane < p ? v[q * p + lane] : 0.0;
+            // (masked reads at row max(i, jl) of column jl, inside the panel for
+            // every lane; unrolled so they issue ahead of the chain)
+#pragma unroll 4
             for (int i = p - 1; i > 0; --i) {
-                const double l = (lane < i) ? (double)colj[i] : 0.0;
+                const double l = (double)colj[max(i, jl)] * (lane < i ? 1.0 : 0.0);
 #pragma unroll
                 for (int q = 0; q < NRHS; ++q) vv[q] -= l * readlane_d(vv[q], i);
             }
