@@ -1739,8 +1739,13 @@ __device__ __noinline__ void forward_lds(const RveCtx& c, Smem& sm, T* F, double
                 double vv[NRHS];
 #pragma unroll
                 for (int q = 0; q < NRHS; ++q) vv[q] = lane < p ? vb[q * m + lane] : 0.0;
+                // (masked reads at row max(min(lane, m - 1), j + 1) of column j,
+                // inside the panel for every lane; unrolled so they issue ahead of
+                // the chain)
+#pragma unroll 4
                 for (int j = 0; j < p - 1; ++j) {
-                    const double l = (lane > j && lane < p) ? (double)Lp[cpk(j, m) + lane - j] : 0.0;
+                    const int row = max(min(lane, m - 1), j + 1);
+                    const double l = (double)Lp[cpk(j, m) + row - j] * ((lane > j && lane < p) ? 1.0 : 0.0);
 #pragma unroll
                     for (int q = 0; q < NRHS; ++q) vv[q] -= l * readlane_d(vv[q], j);
                 }
@@ -1753,6 +1758,7 @@ __device__ __noinline__ void forward_lds(const RveCtx& c, Smem& sm, T* F, double
                 double acc[NRHS];
 #pragma unroll
                 for (int q = 0; q < NRHS; ++q) acc[q] = vb[q * m + i];
+#pragma unroll 4
                 for (int j = 0; j < p; ++j) {
                     const double l = (double)Lp[cpk(j, m) + i - j];
 #pragma unroll
