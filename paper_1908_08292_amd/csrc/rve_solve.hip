@@ -1144,17 +1144,20 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
                     const bool below = act && r > K + j;
                     const double l = below ? row[j] * rp : 0.0;
                     const double lpv = l * piv;
+                    // unconditional updates: l = 0 off the rows below the pivot, and
+                    // the only other entries touched, row[cc] with K + cc > r, lie
+                    // above the diagonal and are neither stored nor read
 #pragma unroll
                     for (int cc = j + 1; cc < 16; ++cc) {
                         if (cc < kb) {
                             const double lc = readlane_d(l, K + cc);
-                            if (act && K + cc <= r) row[cc] -= lpv * lc;
+                            row[cc] -= lpv * lc;
                         }
                     }
 #pragma unroll
                     for (int q = 0; q < NRHS; ++q) {
                         const double yj = readlane_d(yv[q], K + j);
-                        if (below) yv[q] -= l * yj;
+                        yv[q] -= l * yj;
                     }
                     if (below) row[j] = l;
                 }
