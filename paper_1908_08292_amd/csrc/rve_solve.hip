@@ -1129,9 +1129,13 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
             const bool act = r >= K && r < m;
             double row[16];
             double yv[NRHS];
+            // (clamped reads inside the front, masked: no branch per entry)
 #pragma unroll
-            for (int cc = 0; cc < 16; ++cc)
-                row[cc] = (act && cc < kb && K + cc <= r) ? (double)F[cpk(K + cc, m) + r - K - cc] : 0.0;
+            for (int cc = 0; cc < 16; ++cc) {
+                const int col = min(K + cc, m - 1);
+                const int idx = min(max(cpk(col, m) + r - col, 0), cpk(m, m) - 1);
+                row[cc] = (double)F[idx] * ((act && cc < kb && K + cc <= r) ? 1.0 : 0.0);
+            }
 #pragma unroll
             for (int q = 0; q < NRHS; ++q) yv[q] = act ? rl[q * m + r] : 0.0;
             const double d0 = (act && r < K + kb) ? (double)D0[r] : 1.0;
@@ -1337,11 +1341,12 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
                     const double l = r[j] * P[1];
                     // every P entry is read (all within the buffer; entries past the
                     // block are stale) and the multiplier selected, so the reads
-                    // need no branch of their own: r[cc] off the row's lower part or
-                    // past the block is neither stored nor used
+                    // need no branch of their own: r[cc] above the row's diagonal
+                    // (K + cc > i) is neither stored nor read, so only the block
+                    // bound masks the update
 #pragma unroll
                     for (int cc = j + 1; cc < 16; ++cc) {
-                        const double lc = (cc < kb && K + cc <= i) ? l : 0.0;
+                        const double lc = cc < kb ? l : 0.0;
                         r[cc] -= lc * P[2 + cc];
                     }
                     r[j] = l;
