@@ -1136,9 +1136,11 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
                 const int idx = min(max(cpk(col, m) + r - col, 0), cpk(m, m) - 1);
                 row[cc] = (double)F[idx] * ((act && cc < kb && K + cc <= r) ? 1.0 : 0.0);
             }
+            // (clamped reads; lanes off the front never store or broadcast these,
+            // and only the pivot's own lane tests its d0)
 #pragma unroll
-            for (int q = 0; q < NRHS; ++q) yv[q] = act ? rl[q * m + r] : 0.0;
-            const double d0 = (act && r < K + kb) ? (double)D0[r] : 1.0;
+            for (int q = 0; q < NRHS; ++q) yv[q] = rl[q * m + min(r, m - 1)];
+            const double d0 = (double)D0[min(r, m - 1)];
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 if (j < kb) {
@@ -1316,12 +1318,18 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
         const bool own = i < m;
         double r[16];
         double b[NRHS];
+        // (clamped reads inside the front, masked or unused: rows off the front
+        // never publish, update or store these, and only a pivot's owner tests
+        // its d0)
 #pragma unroll
-        for (int cc = 0; cc < 16; ++cc)
-            r[cc] = (own && cc < kb && K + cc <= i) ? F[cpk(K + cc, m) + i - K - cc] : 0.0;
+        for (int cc = 0; cc < 16; ++cc) {
+            const int col = min(K + cc, m - 1);
+            const int idx = min(max(cpk(col, m) + min(i, m - 1) - col, 0), cpk(m, m) - 1);
+            r[cc] = (double)F[idx] * ((own && cc < kb && K + cc <= i) ? 1.0 : 0.0);
+        }
 #pragma unroll
-        for (int q = 0; q < NRHS; ++q) b[q] = own ? rl[q * m + i] : 0.0;
-        const double d0 = (own && i < K + kb) ? (double)D0[i] : 1.0;
+        for (int q = 0; q < NRHS; ++q) b[q] = rl[q * m + min(i, m - 1)];
+        const double d0 = (double)D0[min(i, m - 1)];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             if (j < kb) {
