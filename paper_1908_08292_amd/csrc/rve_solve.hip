@@ -315,6 +315,18 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 __device__ inline int cpk(int j, int m) { return j * m - ((j * (j - 1)) >> 1); }
 
+// 1/x for a pivot on the elimination's dependent chain: the hardware reciprocal
+// estimate refined by two Newton-Raphson steps r <- r + r (1 - x r), each of
+// which squares the relative error (full double precision for the normal pivots
+// that pass the vanishing-pivot test; a pivot that fails it is flagged whatever
+// this returns)
+__device__ inline double recip_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
 __device__ inline double readlane_d(double v, int l) {
     union { double d; int i[2]; } u;
     u.d = v;
@@ -1145,7 +1157,7 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
             for (int j = 0; j < 16; ++j) {
                 if (j < kb) {
                     const double piv = readlane_d(row[j], K + j);
-                    const double rp = 1.0 / piv;
+                    const double rp = recip_nr(piv);
                     if (r == K + j && (!(fabs(piv) > 1e-14 * fabs(d0)) || !isfinite(piv))) sm.flag = 2;
                     const bool below = act && r > K + j;
                     const double l = below ? row[j] * rp : 0.0;
@@ -1338,7 +1350,7 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
                     const double piv = r[j];
                     if (!(fabs(piv) > 1e-14 * fabs(d0)) || !isfinite(piv)) sm.flag = 2;
                     P[0] = piv;
-                    P[1] = 1.0 / piv;
+                    P[1] = recip_nr(piv);
 #pragma unroll
                     for (int q = 0; q < NRHS; ++q) P[18 + q] = b[q];
                 } else if (i > K + j && i < K + kb) {
