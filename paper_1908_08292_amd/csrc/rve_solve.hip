@@ -1453,8 +1453,7 @@ template <int D, int NRHS, typename T>
 __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* rl, int wave_slice) {
     constexpr int nrhs = NRHS;
     const DevPlan& pl = *c.plan;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NEN = 1 << D;
+    const int tid = threadIdx.x, wave = tid >> 6;
     PROF_T0();
     // small subtrees: one front per wave, all fronts of one height at a time
     for (int h = 0; h < pl.nwave_h; ++h) {
@@ -1518,14 +1517,12 @@ __device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
     // (in bounds: p + i < m <= cpk(p, m)) and discard the value
     const int jl = lane < p ? lane : 0;
     const int cj = cpk(jl, m) - jl;
-    // (unrolled: the panel reads do not depend on the chain and issue ahead)
-#pragma unroll 8
+    // (masked reads: no branch per entry)
     for (int i = 0; i < mu; ++i) {
         const double l = (double)S[cj + p + i] * (lane < p ? 1.0 : 0.0);
 #pragma unroll
         for (int q = 0; q < NRHS; ++q) v[q] -= l * readlane_d(xs[q], i);
     }
-#pragma unroll 4
     for (int jj = p - 1; jj > 0; --jj) {
         const double l = (double)S[cj + jj] * (lane < jj ? 1.0 : 0.0);
 #pragma unroll
@@ -1613,8 +1610,7 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
 #pragma unroll
             for (int q = 0; q < NRHS; ++q) vv[q] = lane < p ? v[q * p + lane] : 0.0;
             // (masked reads at row max(i, jl) of column jl, inside the panel for
-            // every lane; unrolled so they issue ahead of the chain)
-#pragma unroll 4
+            // every lane: no branch per entry)
             for (int i = p - 1; i > 0; --i) {
                 const double l = (double)colj[max(i, jl)] * (lane < i ? 1.0 : 0.0);
 #pragma unroll
@@ -1681,11 +1677,10 @@ template <int D, int NRHS, typename T>
 __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* rl, double* x, int front_elems,
                                          int wave_slice) {
     const DevPlan& pl = *c.plan;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NPART = (NRHS == 1) ? 3 : 1;
+    const int tid = threadIdx.x, wave = tid >> 6;
     for (int t = tid; t < D * NRHS; t += NT) x[t] = 0.0;  // pinned node
-    // large fronts (the top of the tree) with the whole workgroup, then the
-    // small subtrees wave by wave
+    // large fronts (the top of the tree) in the plan's steps, then the small
+    // subtrees wave by wave
     for (int st = pl.nwg_steps - 1; st >= 0; --st) {
         const int32_t* e = pl.wg_steps + kStepFronts * st;
         const int nf = e[3] >= 0 ? 4 : (e[1] >= 0 ? 2 : 1);
@@ -1768,9 +1763,7 @@ __device__ __noinline__ void forward_lds(const RveCtx& c, Smem& sm, T* F, double
 #pragma unroll
                 for (int q = 0; q < NRHS; ++q) vv[q] = lane < p ? vb[q * m + lane] : 0.0;
                 // (masked reads at row max(min(lane, m - 1), j + 1) of column j,
-                // inside the panel for every lane; unrolled so they issue ahead of
-                // the chain)
-#pragma unroll 4
+                // inside the panel for every lane: no branch per entry)
                 for (int j = 0; j < p - 1; ++j) {
                     const int row = max(min(lane, m - 1), j + 1);
                     const double l = (double)Lp[cpk(j, m) + row - j] * ((lane > j && lane < p) ? 1.0 : 0.0);
