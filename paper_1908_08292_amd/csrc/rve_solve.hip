@@ -1517,16 +1517,29 @@ __device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
     // (in bounds: p + i < m <= cpk(p, m)) and discard the value
     const int jl = lane < p ? lane : 0;
     const int cj = cpk(jl, m) - jl;
-    // (masked reads: no branch per entry)
-    for (int i = 0; i < mu; ++i) {
-        const double l = (double)S[cj + p + i] * (lane < p ? 1.0 : 0.0);
+    // four entries per pass, read ahead of the updates (clamped indices, masked
+    // values; the broadcast lanes are uniform)
+    const double pm = lane < p ? 1.0 : 0.0;
+    for (int i0 = 0; i0 < mu; i0 += 4) {
+        double l[4];
 #pragma unroll
-        for (int q = 0; q < NRHS; ++q) v[q] -= l * readlane_d(xs[q], i);
+        for (int u = 0; u < 4; ++u) l[u] = (double)S[cj + p + min(i0 + u, mu - 1)] * (i0 + u < mu ? pm : 0.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) v[q] -= l[u] * readlane_d(xs[q], min(i0 + u, mu - 1));
     }
-    for (int jj = p - 1; jj > 0; --jj) {
-        const double l = (double)S[cj + jj] * (lane < jj ? 1.0 : 0.0);
+    for (int j0 = p - 1; j0 > 0; j0 -= 4) {
+        double l[4];
 #pragma unroll
-        for (int q = 0; q < NRHS; ++q) v[q] -= l * readlane_d(v[q], jj);
+        for (int u = 0; u < 4; ++u) {
+            const int jj = max(j0 - u, 1);
+            l[u] = (double)S[cj + jj] * ((j0 - u >= 1 && lane < jj) ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) v[q] -= l[u] * readlane_d(v[q], max(j0 - u, 1));
     }
     if (lane < p)
 #pragma unroll
