@@ -1622,12 +1622,19 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
             double vv[NRHS];
 #pragma unroll
             for (int q = 0; q < NRHS; ++q) vv[q] = lane < p ? v[q * p + lane] : 0.0;
-            // (masked reads at row max(i, jl) of column jl, inside the panel for
-            // every lane: no branch per entry)
-            for (int i = p - 1; i > 0; --i) {
-                const double l = (double)colj[max(i, jl)] * (lane < i ? 1.0 : 0.0);
+            // four pivots per pass, read ahead of the updates (row max(i, jl) of
+            // column jl, inside the panel for every lane; masked values)
+            for (int i0 = p - 1; i0 > 0; i0 -= 4) {
+                double l[4];
 #pragma unroll
-                for (int q = 0; q < NRHS; ++q) vv[q] -= l * readlane_d(vv[q], i);
+                for (int u = 0; u < 4; ++u) {
+                    const int i = max(i0 - u, 1);
+                    l[u] = (double)colj[max(i, jl)] * ((i0 - u >= 1 && lane < i) ? 1.0 : 0.0);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int q = 0; q < NRHS; ++q) vv[q] -= l[u] * readlane_d(vv[q], max(i0 - u, 1));
             }
 #pragma unroll
             for (int q = 0; q < NRHS; ++q)
@@ -1775,13 +1782,22 @@ __device__ __noinline__ void forward_lds(const RveCtx& c, Smem& sm, T* F, double
                 double vv[NRHS];
 #pragma unroll
                 for (int q = 0; q < NRHS; ++q) vv[q] = lane < p ? vb[q * m + lane] : 0.0;
-                // (masked reads at row max(min(lane, m - 1), j + 1) of column j,
-                // inside the panel for every lane: no branch per entry)
-                for (int j = 0; j < p - 1; ++j) {
-                    const int row = max(min(lane, m - 1), j + 1);
-                    const double l = (double)Lp[cpk(j, m) + row - j] * ((lane > j && lane < p) ? 1.0 : 0.0);
+                // four pivots per pass, read ahead of the updates (row
+                // max(min(lane, m - 1), j + 1) of column j, inside the panel for
+                // every lane; masked values)
+                for (int j0 = 0; j0 < p - 1; j0 += 4) {
+                    double l[4];
 #pragma unroll
-                    for (int q = 0; q < NRHS; ++q) vv[q] -= l * readlane_d(vv[q], j);
+                    for (int u = 0; u < 4; ++u) {
+                        const int j = min(j0 + u, p - 2);
+                        const int row = max(min(lane, m - 1), j + 1);
+                        l[u] = (double)Lp[cpk(j, m) + row - j] *
+                               ((j0 + u < p - 1 && lane > j && lane < p) ? 1.0 : 0.0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int q = 0; q < NRHS; ++q) vv[q] -= l[u] * readlane_d(vv[q], min(j0 + u, p - 2));
                 }
 #pragma unroll
                 for (int q = 0; q < NRHS; ++q)
