@@ -103,3 +103,30 @@ def test_nested_newton_is_quadratic_and_alternating_agrees():
         assert h[-1] <= 1e-10
         assert h[-2] < 1e-3 and h[-1] <= 10 * h[-2] ** 2
     assert np.abs(mn.u() - ma.u()).max() < 1e-7 * np.abs(mn.u()).max()
+
+
+def test_holed_plate_mesh_counts():
+    """The 64 x 64 plate with a centred hole of radius 0.2 (elements removed by
+    centroid, strict '<'): 3572 kept elements, 14288 quadrature points, 3752
+    nodes (7504 dofs), counted here by brute force over the grid, and equal to
+    the counts derived for this workload beforehand."""
+    nx = ny = 64
+    h = 1.0 / nx
+    keep = np.zeros((ny, nx), bool)
+    for j in range(ny):
+        for i in range(nx):
+            keep[j, i] = np.hypot((i + 0.5) * h - 0.5, (j + 0.5) * h - 0.5) >= 0.2
+    used = np.zeros((ny + 1, nx + 1), bool)
+    for j, i in zip(*np.nonzero(keep)):
+        used[j:j + 2, i:i + 2] = True
+    assert keep.sum() == 3572 and used.sum() == 3752
+    ph = oracle.phase_by_centroid(2, 2, 0.25)
+    m = oracle.Macro(nx, ny, 2, ph, LAME, hole_r=0.2, bc=1, stretch=1.15, nsteps=20)
+    assert m.nqp == 4 * 3572 == 14288
+    assert m.ndof == 2 * 3752 == 7504
+    xy = m.nodes()
+    # exactly the grid nodes of kept elements, none inside the hole's removed core
+    got = {(int(round(x / h)), int(round(y / h))) for x, y in xy}
+    want = {(i, j) for j, i in zip(*np.nonzero(used))}
+    assert got == want
+    m.close()
