@@ -1,12 +1,17 @@
-"""Builds the HIP library librve.so (gfx950) in-tree with hipcc."""
+"""Builds the HIP library librve.so (gfx950) in-tree with hipcc.
+
+Every source is compiled to an object of its own (in parallel), then the
+objects are linked into the shared library."""
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librve.so")
-SOURCES = ["plan.cpp", "rve_abi.cpp", "rve_solve.hip", "rve_solve512.hip", "fehmm.hip", "surrogate.hip"]
+SOURCES = ["plan.cpp", "rve_abi.cpp", "rve_solve.hip", "rve_solve512.hip", "fehmm.hip",
+           "surrogate.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed FP32 add/mul/FMA in any kernel: the device pass honours
          # this target feature switch (the host pass warns that it does not
@@ -18,7 +23,21 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", LIB + ".tmp"]
+    os.makedirs(OBJ, exist_ok=True)
+    cflags = [f for f in FLAGS if f != "-shared"]
+    procs = []
+    objs = []
+    for s in SOURCES:
+        o = os.path.join(OBJ, os.path.splitext(s)[0] + ".o")
+        cmd = [hipcc] + cflags + ["-c", os.path.join(CSRC, s), "-o", o]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((s, subprocess.Popen(cmd)))
+        objs.append(o)
+    failed = [s for s, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, "hipcc -c " + " ".join(failed))
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
