@@ -156,6 +156,30 @@ int rve_solve_batch_subset(rve_batch b, const int32_t* idx, const int32_t* count
 int rve_solve_batch_sync(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
                          int32_t* iters, const rve_opts* opts, void* hip_stream);
 
+/* ---- solve without allocation --------------------------------------------------
+ * rve_solve_batch_static: for callers that cannot allocate device memory while
+ * they solve (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and asynchrony as rve_solve_batch,
+ * bitwise identical outputs; the solver's workspace (the persistent queue counter
+ * and one slot per persistent workgroup) lives in a static device array of
+ * RVE_STATIC_SCRATCH_BYTES instead of the batch's own slots, so the call makes
+ * no hipMalloc, hipFree or other allocating call.  The number of persistent
+ * workgroups is min(the batch's slots, what fits the array): 1424 for 2D 8 x 8,
+ * 236 for 16 x 16, 44 for 32 x 32 (rve_solve_batch: up to 1024), so batches of
+ * large RVEs take longer; 3D: 19 (8^3), 4 (12^3), 1 (16^3).
+ * Each device holds its own copy of the array from the first call on it until
+ * the process ends (the first call on a device also looks its address up).
+ * Errors: RVE_EINVAL when one slot of the batch exceeds the array (3D meshes
+ * beyond 16^3) or when the batch was created on another device than the current
+ * one; otherwise as rve_solve_batch.
+ * All calls on one device share its array: calls that overlap on one device
+ * (other streams, other threads) race and give wrong results; serialize them
+ * (one stream, or events).  The array keeps the last call's contents; the queue
+ * counter is cleared by the call itself, and nothing else needs to start at zero. */
+#define RVE_STATIC_SCRATCH_BYTES (256ull << 20)
+int rve_solve_batch_static(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
+                           int32_t* iters, const rve_opts* opts, void* hip_stream);
+
 /* ---- autotuning -------------------------------------------------------------
  * Choices that shape the solve of one mesh size: the leaf size of the nested
  * dissection (largest leaf box, in nodes: front sizes and tree depth), the

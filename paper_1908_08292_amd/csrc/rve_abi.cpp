@@ -36,6 +36,10 @@ using namespace fehmm;
 
 namespace {
 
+// caller-provided workspaces: the queue counter takes the first 256 bytes (the
+// slots that follow stay 256-byte aligned)
+constexpr size_t kExtCounterBytes = 256;
+
 thread_local std::string g_err;
 
 int fail(int code, const std::string& msg) {
@@ -220,6 +224,7 @@ struct rve_batch_s {
     int32_t* d_order = nullptr;
     double* d_ws = nullptr;
     unsigned int* d_counter = nullptr;
+    int device = -1;  // the device the batch's memory lives on
     bool alive = true;
 };
 
@@ -381,6 +386,7 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
     auto b = std::make_unique<rve_batch_s>();
     b->d = d;
     b->B = B;
+    HIP_OR(hipGetDevice(&b->device));
     // distinct plans and meshes
     std::vector<PlanEntry*> plans;
     std::map<PlanEntry*, int> plan_id;
@@ -512,11 +518,30 @@ int rve_batch_state_offsets(rve_batch b, int64_t* host_off) {
     return RVE_OK;
 }
 
+// ext_ws: optional caller-provided device memory (queue counter in its first
+// 256 bytes, then workspace slots) of ext_bytes bytes used instead of the
+// batch's own workspace; the number of persistent workgroups is then limited to
+// the slots that fit
 static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* subset_count, const double* F,
                             double* P, double* A, double* w_state, int32_t* status, int32_t* iters,
-                            const rve_opts* opts, void* hip_stream, const int* skip) {
+                            const rve_opts* opts, void* hip_stream, const int* skip, void* ext_ws = nullptr,
+                            size_t ext_bytes = 0) {
     if (!b || !b->alive) return fail(RVE_EINVAL, "rve_solve_batch: invalid batch handle");
     if (!F || !P) return fail(RVE_EINVAL, "rve_solve_batch: F and P are required");
+    int nslots = b->nslots;
+    double* ws = b->d_ws;
+    unsigned int* counter = b->d_counter;
+    if (ext_ws) {
+        const size_t slot_bytes = (size_t)b->lay.stride * sizeof(double);
+        const size_t fit = ext_bytes > kExtCounterBytes ? (ext_bytes - kExtCounterBytes) / slot_bytes : 0;
+        if (fit < 1)
+            return fail(RVE_EINVAL, "rve_solve_batch_static: one workspace slot of this batch (" +
+                                        std::to_string(slot_bytes) + " bytes) does not fit the static scratch (" +
+                                        std::to_string(ext_bytes) + " bytes)");
+        nslots = (int)std::min<size_t>((size_t)nslots, fit);
+        counter = reinterpret_cast<unsigned int*>(ext_ws);
+        ws = reinterpret_cast<double*>(reinterpret_cast<char*>(ext_ws) + kExtCounterBytes);
+    }
     rve_opts o;
     rve_opts_default(&o);
     if (opts) o = *opts;
@@ -540,9 +565,9 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
     a.count_dev = subset ? subset_count : nullptr;
     a.skip = skip;
     a.B = b->B;
-    a.ws = b->d_ws;
+    a.ws = ws;
     a.lay = b->lay;
-    a.counter = b->d_counter;
+    a.counter = counter;
     a.F = F;
     a.P = P;
     a.A = A;
@@ -579,8 +604,8 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
     a.ir_max_tan = 0;
     a.ir_eta = 1e-2;
     a.ir_eta_tan = 0.0;
-    hipError_t e = wide ? nt512::launch_rve_solve(a, b->nslots, dyn, fp32, (hipStream_t)hip_stream)
-                        : nt256::launch_rve_solve(a, b->nslots, dyn, fp32, (hipStream_t)hip_stream);
+    hipError_t e = wide ? nt512::launch_rve_solve(a, nslots, dyn, fp32, (hipStream_t)hip_stream)
+                        : nt256::launch_rve_solve(a, nslots, dyn, fp32, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(RVE_EHIP, std::string("rve_solve_batch launch: ") + hipGetErrorString(e));
     return RVE_OK;
 }
@@ -665,6 +690,17 @@ int rve_internal_solve(rve_batch b, const int32_t* subset, const int32_t* count,
                        double* A, double* w_state, int32_t* status, int32_t* iters, const rve_opts* opts,
                        void* hip_stream, const int* skip) {
     return solve_batch_impl(b, subset, count, F, P, A, w_state, status, iters, opts, hip_stream, skip);
+}
+
+int rve_internal_solve_ext(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,
+                           int32_t* iters, const rve_opts* opts, void* hip_stream, void* ext_ws, size_t ext_bytes,
+                           int device) {
+    if (!ext_ws) return fail(RVE_EINVAL, "rve_solve_batch_static: no scratch");
+    if (!b || !b->alive) return fail(RVE_EINVAL, "rve_solve_batch_static: invalid batch handle");
+    if (b->device != device)
+        return fail(RVE_EINVAL, "rve_solve_batch_static: the batch lives on another device than the current one");
+    return solve_batch_impl(b, nullptr, nullptr, F, P, A, w_state, status, iters, opts, hip_stream, nullptr, ext_ws,
+                            ext_bytes);
 }
 
 extern "C" {

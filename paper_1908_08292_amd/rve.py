@@ -68,6 +68,7 @@ def lib():
         L.rve_solve_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(Opts), vp]
         L.rve_solve_batch_sync.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(Opts), vp]
         L.rve_solve_batch_subset.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Opts), vp]
+        L.rve_solve_batch_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(Opts), vp]
         L.rve_plan_info.argtypes = [i32, i32, C.POINTER(dp), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]
         L.rve_plan_export.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.rve_plan_schedule.argtypes = [i32, i32, vp, vp, vp]
@@ -250,9 +251,11 @@ class Batch:
             raise ValueError(f"{name}: expected contiguous {dtype} with {numel} elements, got "
                              f"{t.dtype} {tuple(t.shape)} contiguous={t.is_contiguous()}")
 
-    def solve(self, F, P, A=None, w_state=None, status=None, iters=None, opts=None, stream=None, sync=False):
+    def solve(self, F, P, A=None, w_state=None, status=None, iters=None, opts=None, stream=None, sync=False,
+              static=False):
         """All tensors on the GPU (float64 / int32), contiguous; sizes are checked
-        here because the C ABI receives bare device pointers."""
+        here because the C ABI receives bare device pointers.  static=True calls
+        rve_solve_batch_static (workspace in the library's static device array)."""
         import torch
         d2 = self.d * self.d
         self._check(F, self.B * d2, torch.float64, "F")
@@ -265,9 +268,11 @@ class Batch:
             raise ValueError("F and P are required")
         o = opts if opts is not None else default_opts()
         s = C.c_void_p(stream) if stream is not None else None
-        fn = lib().rve_solve_batch_sync if sync else lib().rve_solve_batch
+        if static and sync:
+            raise ValueError("static and sync are exclusive")
+        fn = lib().rve_solve_batch_static if static else (lib().rve_solve_batch_sync if sync else lib().rve_solve_batch)
         return check(fn(self.h, _ptr(F), _ptr(P), _ptr(A), _ptr(w_state), _ptr(status), _ptr(iters),
-                        C.byref(o), s), "rve_solve_batch")
+                        C.byref(o), s), "rve_solve_batch_static" if static else "rve_solve_batch")
 
     def solve_subset(self, idx, count, F, P, A=None, w_state=None, status=None, iters=None, opts=None, stream=None):
         """Solves only the RVEs idx[0 .. count[0]) (device int32 tensors)."""
