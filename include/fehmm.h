@@ -12,9 +12,12 @@
  * stiffness transfer sum_qp B_mac^T Abar B_mac w|J|, equal to the FE-HMM
  * transfer sum omega/|K_delta| T^T K T of eq. (k-mac-element-6) for the unit
  * displacement states of the macro nodes.  Load steps apply the prescribed
- * right-edge displacement in nsteps equal increments; each step runs the macro
- * Newton to ||R_H|| <= rtol_macro ||R_H^(0)|| (R_H^(0): first residual of the
- * step, after the increment).
+ * right-edge displacement in nsteps equal increments; the increment of a step
+ * enters its first macro Newton iteration through the linear solve (an
+ * inhomogeneous Dirichlet condition: K_ff du_f = -(R_f + K_fd du_d), then the
+ * fixed dofs take du_d), and the step runs the macro Newton to
+ * ||R_H|| <= rtol_macro ||R_H^(0)|| with R_H^(0) = R_f + K_fd du_d, the
+ * load-equivalent first residual.
  *
  * Schemes (Sec. 5): FEHMM_NESTED runs every micro Newton to convergence per
  * macro iteration, warm-started from the stored fluctuations (Algorithm 1);

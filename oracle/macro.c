@@ -217,8 +217,9 @@ static int macro_micro(oracle_macro* m, int one_step, int64_t* micro_iters) {
     return nbad;
 }
 
-/* R_H (free dofs) and K_H; returns ||R_H|| */
-static double macro_assemble(oracle_macro* m, double* R) {
+/* R_H (free dofs) and K_H; with dud (first iteration of a load step) also the
+ * prescribed increment's pull on the free dofs, R_f += K_fd dud */
+static double macro_assemble(oracle_macro* m, double* R, const double* dud) {
     memset(R, 0, sizeof(double) * (m->nfree ? m->nfree : 1));
     memset(m->K.val, 0, sizeof(double) * m->K.ptr[m->K.N]);
     for (int e = 0; e < m->nelem; ++e)
@@ -235,6 +236,14 @@ static double macro_assemble(oracle_macro* m, double* R) {
                     for (int b = 0; b < 4; ++b)
                         for (int k = 0; k < 2; ++k) {
                             int g2 = m->dofmap[2 * m->conn[4 * e + b] + k];
+                            if (g2 < 0 && dud) {
+                                double t = 0;
+                                for (int J = 0; J < 2; ++J)
+                                    for (int L = 0; L < 2; ++L)
+                                        t += m->dN[p][a][J] * A[(i * 2 + J) * 4 + k * 2 + L] * m->dN[p][b][L];
+                                R[g] += t * m->wdet * dud[2 * m->conn[4 * e + b] + k];
+                                continue;
+                            }
                             if (g2 < 0 || g2 > g) continue;
                             double t = 0;
                             for (int J = 0; J < 2; ++J)
@@ -251,10 +260,15 @@ static double macro_assemble(oracle_macro* m, double* R) {
 
 int oracle_macro_step(oracle_macro* m, int step, int* macro_iters, double* res_hist, int64_t* micro_iters) {
     const oracle_macro_desc* d = &m->desc;
+    /* the prescribed displacements of the step enter the first macro Newton
+     * iteration as an inhomogeneous Dirichlet condition of the linearized
+     * system: K_ff du_f = -(R_f + K_fd dud), u_d += dud; the first residual of
+     * the step is that load-equivalent residual */
     double ux = (d->stretch - 1.0) * d->Lx * (double)step / d->nsteps;
+    double* dud = (double*)calloc(m->ndof, sizeof(double));
     for (int v = 0; v < m->nnode; ++v) {
-        if (m->fixed[2 * v]) m->u[2 * v] = (m->xy[2 * v] > 0.5 * d->Lx) ? ux : 0.0;
-        if (m->fixed[2 * v + 1]) m->u[2 * v + 1] = 0.0;
+        if (m->fixed[2 * v]) dud[2 * v] = ((m->xy[2 * v] > 0.5 * d->Lx) ? ux : 0.0) - m->u[2 * v];
+        if (m->fixed[2 * v + 1]) dud[2 * v + 1] = 0.0 - m->u[2 * v + 1];
     }
     double* R = (double*)malloc(sizeof(double) * (m->nfree ? m->nfree : 1));
     int64_t mic = 0;
@@ -263,7 +277,7 @@ int oracle_macro_step(oracle_macro* m, int step, int* macro_iters, double* res_h
     for (;;) {
         macro_gather_F(m);
         if (macro_micro(m, d->scheme == 1, &mic)) { status = 2; break; }
-        double rn = macro_assemble(m, R);
+        double rn = macro_assemble(m, R, it == 0 ? dud : NULL);
         if (it == 0) r0 = rn;
         if (res_hist) res_hist[it] = r0 > 0 ? rn / r0 : 0.0;
         if (rn <= d->rtol_macro * r0 || rn == 0.0) break;
@@ -271,11 +285,14 @@ int oracle_macro_step(oracle_macro* m, int step, int* macro_iters, double* res_h
         if (sky_ldlt(&m->K)) { status = 2; break; }
         for (int g = 0; g < m->nfree; ++g) R[g] = -R[g];
         sky_solve(&m->K, R);
-        for (int k = 0; k < m->ndof; ++k)
+        for (int k = 0; k < m->ndof; ++k) {
             if (m->dofmap[k] >= 0) m->u[k] += R[m->dofmap[k]];
+            else if (it == 0) m->u[k] += dud[k];
+        }
         ++it;
     }
     free(R);
+    free(dud);
     if (macro_iters) *macro_iters = it;
     if (micro_iters) *micro_iters = mic;
     return status;

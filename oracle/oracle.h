@@ -107,8 +107,11 @@ oracle_macro* oracle_macro_create(const oracle_macro_desc* d, const oracle_opts*
 void oracle_macro_destroy(oracle_macro* m);
 int oracle_macro_ndof(const oracle_macro* m);
 int oracle_macro_nqp(const oracle_macro* m);
-/* One load step (1-based; load factor step/nsteps).  Fills the macro iteration
- * count, the residual history normalized to the first residual of the step
+/* One load step (1-based; load factor step/nsteps).  The increment of the
+ * prescribed displacements enters the first macro Newton iteration through the
+ * linear solve (K_ff du_f = -(R_f + K_fd du_d), then u_d += du_d), so the first
+ * residual of the step is the load-equivalent R_f + K_fd du_d.  Fills the macro
+ * iteration count, the residual history normalized to that first residual
  * (max_macro_iter+1 entries) and the total micro iterations.  Returns 0, 1 if
  * the macro Newton did not converge, or 2 if some RVE failed. */
 int oracle_macro_step(oracle_macro* m, int step, int* macro_iters, double* res_hist, int64_t* micro_iters);

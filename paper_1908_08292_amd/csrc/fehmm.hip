@@ -118,7 +118,26 @@ __global__ void macro_scatter(const int* __restrict__ elist, int nel, const int*
     }
 }
 
-// Dirichlet dofs: identity row/column, zero residual (the increment there is 0)
+// first macro iteration of a load step: the prescribed increment moves the free
+// dofs through the coupling block, R_f += K_fd dud (K symmetric, lower band:
+// K(i, j) for j <= i sits in row i, for j > i as K(j, i) in row j)
+__global__ void macro_dirichlet_rhs(const double* __restrict__ K, const double* __restrict__ dud,
+                                    const int* __restrict__ fixed, int ndof, int bw, double* __restrict__ R,
+                                    const int* __restrict__ done) {
+    if (*done) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ndof || fixed[i]) return;
+    double acc = 0.0;
+    for (int k = 1; k <= bw; ++k) {
+        const int jl = i - k, ju = i + k;
+        if (jl >= 0) acc += K[(int64_t)i * (bw + 1) + k] * dud[jl];
+        if (ju < ndof) acc += K[(int64_t)ju * (bw + 1) + k] * dud[ju];
+    }
+    R[i] += acc;
+}
+
+// Dirichlet dofs: identity row/column, zero residual (their increment is
+// applied by macro_update)
 __global__ void macro_bc(const int* __restrict__ fixed, int ndof, int bw, double* __restrict__ K,
                          double* __restrict__ R, const int* __restrict__ done) {
     if (*done) return;
@@ -152,13 +171,17 @@ struct StepState {
     double hist[FEHMM_MAX_HIST];
 };
 
-// start of a load step: prescribed displacements (right-edge x dofs: the step's
-// fraction of the stretch, other fixed dofs 0) and a reset state
-__global__ void macro_step_init(StepState* __restrict__ st, double* __restrict__ u, const int* __restrict__ fixed,
+// start of a load step: the increment of the prescribed displacements
+// (right-edge x dofs: the step's fraction of the stretch, other fixed dofs 0),
+// dud = target - u on fixed dofs and 0 elsewhere; it enters the first macro
+// Newton iteration through the linear solve (macro_dirichlet_rhs), and u takes
+// it with that iteration's update.  Also resets the step state.
+__global__ void macro_step_init(StepState* __restrict__ st, const double* __restrict__ u,
+                                double* __restrict__ dud, const int* __restrict__ fixed,
                                 const int* __restrict__ rightx, double ux_per_step, int ndof) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int step = st->step;
-    if (i < ndof && fixed[i]) u[i] = rightx[i] ? ux_per_step * step : 0.0;
+    if (i < ndof) dud[i] = fixed[i] ? (rightx[i] ? ux_per_step * step : 0.0) - u[i] : 0.0;
     if (i == 0) {
         st->done = 0;
         st->it = 0;
@@ -506,11 +529,15 @@ __global__ __launch_bounds__(kBandNT) void macro_band_solve_blocked(double* __re
     }
 }
 
+// u += du on free dofs; in the first iteration of a step (dud non-null) the
+// fixed dofs take the prescribed increment
 __global__ void macro_update(double* __restrict__ u, const double* __restrict__ du, const int* __restrict__ fixed,
-                             int ndof, const int* __restrict__ done) {
+                             const double* __restrict__ dud, int ndof, const int* __restrict__ done) {
     if (*done) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ndof && !fixed[i]) u[i] += du[i];
+    if (i >= ndof) return;
+    if (!fixed[i]) u[i] += du[i];
+    else if (dud) u[i] += dud[i];
 }
 
 inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
@@ -532,6 +559,7 @@ struct fehmm_s {
     int *d_status = nullptr, *d_iters = nullptr, *d_rightx = nullptr;
     StepState* d_state = nullptr;
     double *d_u = nullptr, *d_du = nullptr, *d_F = nullptr, *d_P = nullptr, *d_A = nullptr;
+    double* d_dud = nullptr;  // prescribed increment of the load step (0 on free dofs)
     double *d_w = nullptr, *d_ke = nullptr, *d_fe = nullptr, *d_K = nullptr, *d_R = nullptr, *d_norm = nullptr;
     double* d_Kt = nullptr;  // transposed copy of the band factor (blocked band solve)
     // surrogate replacement of micro solves
@@ -563,7 +591,7 @@ static void fehmm_free(fehmm_s* h) {
     if (h->graph) (void)hipGraphDestroy(h->graph);
     h->gexec = nullptr;
     h->graph = nullptr;
-    double* dp[] = {h->d_Kt, h->d_u, h->d_du, h->d_F, h->d_P, h->d_A, h->d_w, h->d_ke, h->d_fe, h->d_K,
+    double* dp[] = {h->d_Kt, h->d_u, h->d_du, h->d_dud, h->d_F, h->d_P, h->d_A, h->d_w, h->d_ke, h->d_fe, h->d_K,
                     h->d_R, h->d_norm};
     for (double* p : dp) (void)hipFree(p);
     (void)hipFree(h->d_ind);
@@ -692,7 +720,7 @@ int fehmm_create(const fehmm_desc* d, fehmm* out) {
     fehmm_s* H = h.get();
     if ((st = up(&H->d_conn, H->conn)) || (st = up(&H->d_fixed, H->fixed)) || (st = up(&H->d_col[0], H->colour[0])) ||
         (st = up(&H->d_col[1], H->colour[1])) || (st = up(&H->d_col[2], H->colour[2])) ||
-        (st = up(&H->d_col[3], H->colour[3])) || (st = zal(&H->d_u, H->ndof)) || (st = zal(&H->d_du, H->ndof)) ||
+        (st = up(&H->d_col[3], H->colour[3])) || (st = zal(&H->d_u, H->ndof)) || (st = zal(&H->d_du, H->ndof)) || (st = zal(&H->d_dud, H->ndof)) ||
         (st = up(&H->d_rightx, rightx)) || (st = zal(&H->d_F, 4 * (int64_t)H->nqp)) ||
         (st = zal(&H->d_P, 4 * (int64_t)H->nqp)) || (st = zal(&H->d_A, 16 * (int64_t)H->nqp)) ||
         (st = zal(&H->d_w, H->state_doubles)) || (st = zal(&H->d_ke, 64 * (int64_t)H->nelem)) ||
@@ -746,8 +774,8 @@ static int enqueue_step(fehmm_s* h, int it_begin, int it_end, bool with_init) {
     StepState* st = h->d_state;
     const int* done = &st->done;
     if (with_init) {
-        hipLaunchKernelGGL(macro_step_init, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, st, h->d_u, h->d_fixed,
-                           h->d_rightx, (d.stretch - 1.0) * d.Lx / d.nsteps, h->ndof);
+        hipLaunchKernelGGL(macro_step_init, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, st, h->d_u, h->d_dud,
+                           h->d_fixed, h->d_rightx, (d.stretch - 1.0) * d.Lx / d.nsteps, h->ndof);
         if (h->surr)  // a new load step starts with an empty fallback set
             hipLaunchKernelGGL(macro_zero_ints, dim3(nblk(h->nqp, 256)), dim3(256), 0, s, h->d_smask,
                                (int64_t)h->nqp, (const int*)nullptr);
@@ -798,6 +826,9 @@ static int enqueue_step(fehmm_s* h, int it_begin, int it_end, bool with_init) {
             hipLaunchKernelGGL(macro_scatter, dim3(nblk(8 * (int64_t)nel, 256)), dim3(256), 0, s, h->d_col[c], nel,
                                h->d_conn, h->d_ke, h->d_fe, h->bw, h->d_K, h->d_R, done);
         }
+        if (it == 0)
+            hipLaunchKernelGGL(macro_dirichlet_rhs, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_K, h->d_dud,
+                               h->d_fixed, h->ndof, h->bw, h->d_R, done);
         hipLaunchKernelGGL(macro_bc, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_fixed, h->ndof, h->bw, h->d_K,
                            h->d_R, done);
         hipLaunchKernelGGL(macro_norm_step, dim3(1), dim3(256), 0, s, h->d_R, h->ndof, h->d_status, h->d_iters,
@@ -818,7 +849,7 @@ static int enqueue_step(fehmm_s* h, int it_begin, int it_end, bool with_init) {
             hipLaunchKernelGGL(macro_band_solve, dim3(1), dim3(NTB), 0, s, h->d_K, h->d_R, h->ndof, h->bw, h->d_du,
                                &st->band_flag, done);
         hipLaunchKernelGGL(macro_update, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->d_u, h->d_du, h->d_fixed,
-                           h->ndof, done);
+                           it == 0 ? (const double*)h->d_dud : (const double*)nullptr, h->ndof, done);
     }
     FH_HIP(hipGetLastError());
     return RVE_OK;

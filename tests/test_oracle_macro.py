@@ -8,8 +8,12 @@ from tests import fe_ref
 LAME = oracle.two_phase_lame(10.0)
 
 
-def single_scale_fe(nx, ny, lam, mu, stretch, nsteps, bc):
-    """Independent dense single-scale Q1 neo-Hookean FE with the same BCs."""
+def single_scale_fe(nx, ny, lam, mu, stretch, nsteps, bc, through_solve=False, hist=None):
+    """Independent dense single-scale Q1 neo-Hookean FE with the same BCs.
+    through_solve: the step's prescribed increment enters the first Newton
+    iteration as an inhomogeneous Dirichlet condition of the linear system
+    (otherwise it is written into u before the first iteration); hist, a list,
+    receives each step's residual history normalized to its first residual."""
     hx, hy = 1.0 / nx, 1.0 / ny
     nn = (nx + 1) * (ny + 1)
     xy = np.array([[i * hx, j * hy] for j in range(ny + 1) for i in range(nx + 1)])
@@ -31,9 +35,16 @@ def single_scale_fe(nx, ny, lam, mu, stretch, nsteps, bc):
         if abs(x - 1) < 1e-12:
             fixed[2 * v] = True
     u = np.zeros(2 * nn)
+    right = np.zeros(2 * nn, bool)
+    right[0::2] = np.abs(xy[:, 0] - 1) < 1e-12
     for k in range(1, nsteps + 1):
-        u[0::2][np.abs(xy[:, 0] - 1) < 1e-12] = (stretch - 1) * k / nsteps
+        target = np.where(right, (stretch - 1) * k / nsteps, 0.0)
+        dud = np.where(fixed, target - u, 0.0)
+        if not through_solve:
+            u[fixed] = target[fixed]
+            dud[:] = 0.0
         r0 = None
+        h = []
         for it in range(30):
             R = np.zeros(2 * nn); K = np.zeros((2 * nn, 2 * nn))
             for e in conn:
@@ -44,12 +55,19 @@ def single_scale_fe(nx, ny, lam, mu, stretch, nsteps, bc):
                     A = fe_ref.A_closed(F, lam, mu).reshape(2, 2, 2, 2)
                     R[dofs] += np.einsum("iJ,aJ->ai", P, dN[p]).ravel() * wdet
                     K[np.ix_(dofs, dofs)] += np.einsum("aJ,iJkL,bL->aibk", dN[p], A, dN[p]).reshape(8, 8) * wdet
-            rn = np.linalg.norm(R[~fixed])
+            free = ~fixed
+            if it == 0:
+                R[free] += K[np.ix_(free, fixed)] @ dud[fixed]
+            rn = np.linalg.norm(R[free])
             r0 = rn if r0 is None else r0
+            h.append(rn / r0)
             if rn <= 1e-12 * r0:
                 break
-            free = ~fixed
             u[free] -= np.linalg.solve(K[np.ix_(free, free)], R[free])
+            if it == 0:
+                u[fixed] += dud[fixed]
+        if hist is not None:
+            hist.append(np.array(h))
     return xy, u
 
 
@@ -70,6 +88,37 @@ def test_homogeneous_rve_fe_hmm_equals_single_scale_fe(bc):
     order = [int(np.argmin(np.abs(xy_ref - p).sum(axis=1))) for p in xy]
     u_ref = u_ref.reshape(-1, 2)[order].reshape(-1)
     assert np.abs(u - u_ref).max() < 1e-10 * np.abs(u_ref).max()
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_load_increment_enters_through_the_solve(bc):
+    """With a one-phase RVE the FE-HMM macro Newton is the single-scale FE
+    Newton iteration by iteration.  The independent single-scale code applies
+    each step's prescribed increment as an inhomogeneous Dirichlet condition of
+    the first linear solve (K_ff du_f = -(R_f + K_fd du_d)); the oracle's
+    residual histories, normalized to that load-equivalent first residual,
+    and its solution must follow it."""
+    nx = ny = 3
+    ph = np.zeros(4, np.uint8)
+    m = oracle.Macro(nx, ny, 2, ph, LAME, bc=bc, stretch=1.1, nsteps=2, rtol_macro=1e-12)
+    hist = []
+    xy_ref, u_ref = single_scale_fe(nx, ny, *LAME[0], 1.1, 2, bc, through_solve=True, hist=hist)
+    for k in (1, 2):
+        st = m.step(k)
+        assert st["status"] == 0
+        h_ref = hist[k - 1]
+        assert st["macro_iters"] == len(h_ref) - 1
+        # early iterates agree tightly; the last ones sit at round-off
+        big = h_ref > 1e-8
+        assert np.allclose(st["res_hist"][big], h_ref[big], rtol=1e-6)
+    xy = m.nodes()
+    order = [int(np.argmin(np.abs(xy_ref - p).sum(axis=1))) for p in xy]
+    u_ref = u_ref.reshape(-1, 2)[order].reshape(-1)
+    assert np.abs(m.u() - u_ref).max() < 1e-10 * np.abs(u_ref).max()
+    # the other way of applying the increment takes a different path
+    hist_w = []
+    single_scale_fe(nx, ny, *LAME[0], 1.1, 2, bc, through_solve=False, hist=hist_w)
+    assert len(hist_w[0]) != len(hist[0]) or not np.allclose(hist_w[0], hist[0], rtol=1e-3)
 
 
 def test_uniaxial_stretch_gives_uniform_macro_state():
