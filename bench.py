@@ -16,11 +16,18 @@ Prints one JSON line.  Options:
   --no-cpu-baseline        skip the oracle timing
   --calib-copy MiB         after the timed steps, run one plain device copy of
                            this size (for HBM counter calibration under rocprofv3)
-  --macro                  also time the two-scale driver (macro steps/s): 4 x 4
+  --no-macro               skip the two-scale driver block (macro steps/s): 4 x 4
                            macro grid / RVE 8 x 8 over 10 load steps, and the
                            64 x 64 plate with a hole (14288 RVEs of 16 x 16) over
-                           its first --macro-steps of 20 load steps, nested and
-                           alternating two-level Newton
+                           all 20 load steps, nested and alternating two-level
+                           Newton, with the oracle's macro driver beside it (all
+                           steps of the 4 x 4 plate, step 1 of the 64 x 64 plate)
+  --no-assembly            skip the assembly phase timed alone (HBM roofline)
+  --no-peaks               skip the measured FP64 / FP32 MFMA and HBM copy rates
+  --no-cpu-3d              skip the oracle subsample of the uneven 3D batch
+                           (16 RVEs of 8^3 and of 12^3)
+  --cpu-3d-full            also time 16 RVEs of 16^3 on the host (minutes) and
+                           extrapolate the oracle to the whole 3D batch
   --precision fp64|fp32ir|both   the timed RVE path(s); `value` is the FP64 path
                            when it is timed, the FP32-factor path otherwise
   --no-surrogate           skip the surrogate block: MLP energy W(C) trained by the
@@ -28,8 +35,9 @@ Prints one JSON line.  Options:
                            H in [-0.2, 0.2]), its evals/s on 14288 points, a 2 %
                            random audit of the plate problem's accepted points
                            against RVE solves, and macro steps/s of the 64 x 64
-                           plate with a hole, nested, plain FP64 vs surrogate with
-                           fallback at indicator 1e-3
+                           plate with a hole over its first --macro-steps load
+                           steps, nested, plain FP64 (macro rtol 1e-10 and 1e-4)
+                           vs surrogate with fallback at indicator 1e-3
   --no-3d                  skip the uneven 3D block (with a 2D workload): 1024 RVEs
                            of 8^3 / 12^3 / 16^3, one timed launch per precision
 """
@@ -104,46 +112,91 @@ def measured_traffic(workload, precision="fp64"):
 
 
 def cpu_baseline(wl, meta, budget_rves, gpu_results=None):
-    """Oracle throughput on the first RVEs of the workload; when GPU results of
-    the same RVEs are given, also the largest relative errors against them."""
+    """Oracle throughput on the first RVEs of the (single-material) 2D workload:
+    one untimed warm-up on 32 RVEs, then three timed runs of the sample, median
+    reported (OpenMP over RVEs on every host thread).  When GPU results of the
+    same RVEs are given, also the largest relative errors against them."""
     import oracle
     d = meta["d"]
     B = min(budget_rves, len(wl.F))
     nthreads = len(os.sched_getaffinity(0))
-    t_total = 0.0
-    ndone = 0
+    n = int(wl.n[0])
+    assert np.all(wl.n[:B] == n) and len(set(wl.ratio[:B])) == 1
+    phases = np.stack([oracle.phase_by_centroid(d, n, wl.radius[b]) for b in range(B)])
+    lame = oracle.two_phase_lame(float(wl.ratio[0]))
+    oracle.rve_solve_batch(d, n, phases[:32], lame, wl.F[:32], nthreads=nthreads)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        out = oracle.rve_solve_batch(d, n, phases, lame, wl.F[:B], nthreads=nthreads)
+        times.append(time.perf_counter() - t0)
+    assert np.all(out["status"] == 0)
+    t_med = float(np.median(times))
     worst = {}
-    for n in sorted(set(int(x) for x in wl.n[:B])):
-        idx = np.nonzero(wl.n[:B] == n)[0]
-        phases = np.stack([oracle.phase_by_centroid(d, n, wl.radius[b]) for b in idx])
-        lame = oracle.two_phase_lame(10.0)
-        if len(set(wl.ratio[idx])) != 1:
-            # per-RVE material: solve one by one (still OpenMP-free per RVE)
-            t0 = time.perf_counter()
-            for k, b in enumerate(idx):
-                oracle.rve_solve(d, n, phases[k], oracle.two_phase_lame(wl.ratio[b]), wl.F[b])
-            t_total += time.perf_counter() - t0
-        else:
-            lame = oracle.two_phase_lame(float(wl.ratio[idx[0]]))
-            t0 = time.perf_counter()
-            out = oracle.rve_solve_batch(d, n, phases, lame, wl.F[idx], nthreads=nthreads)
-            t_total += time.perf_counter() - t0
-            assert np.all(out["status"] == 0)
-            mu_max = lame[:, 1].max()
-            for name, res in (gpu_results or {}).items():
-                Pg = res["P"].reshape(len(wl.F), -1)[idx]
-                Ag = res["A"].reshape(len(wl.F), -1)[idx]
-                Po, Ao = out["P"].reshape(len(idx), -1), out["A"].reshape(len(idx), -1)
-                eP = np.linalg.norm(Pg - Po, axis=1) / np.maximum(np.linalg.norm(Po, axis=1), 1e-12 * mu_max)
-                eA = np.linalg.norm(Ag - Ao, axis=1) / np.maximum(np.linalg.norm(Ao, axis=1), 1e-12 * mu_max)
-                w = worst.setdefault(name, [0.0, 0.0])
-                w[0], w[1] = max(w[0], float(eP.max())), max(w[1], float(eA.max()))
-        ndone += len(idx)
-    out = dict(value=ndone / t_total, unit="RVE solves/s", cores=nthreads, kind="oracle",
-               sample=f"first {ndone} of {len(wl.F)} RVEs of the same workload ({t_total:.1f} s, "
-                      f"OpenMP over RVEs, {nthreads} threads)")
+    mu_max = lame[:, 1].max()
+    Po, Ao = out["P"].reshape(B, -1), out["A"].reshape(B, -1)
+    for name, res in (gpu_results or {}).items():
+        Pg = res["P"].reshape(len(wl.F), -1)[:B]
+        Ag = res["A"].reshape(len(wl.F), -1)[:B]
+        eP = np.linalg.norm(Pg - Po, axis=1) / np.maximum(np.linalg.norm(Po, axis=1), 1e-12 * mu_max)
+        eA = np.linalg.norm(Ag - Ao, axis=1) / np.maximum(np.linalg.norm(Ao, axis=1), 1e-12 * mu_max)
+        worst[name] = {"max_rel_err_P": float(eP.max()), "max_rel_err_A": float(eA.max())}
+    res = dict(value=B / t_med, unit="RVE solves/s", cores=nthreads, kind="oracle",
+               sample=f"first {B} of {len(wl.F)} RVEs of the same workload: median of 3 runs "
+                      f"({', '.join(f'{t:.2f}' for t in times)} s) after a 32-RVE warm-up, OpenMP over RVEs, "
+                      f"{nthreads} threads", cpu_model=cpu_model())
     if worst:
-        out["gpu_vs_oracle_on_sample"] = {k: {"max_rel_err_P": v[0], "max_rel_err_A": v[1]} for k, v in worst.items()}
+        res["gpu_vs_oracle_on_sample"] = worst
+    return res
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline_3d(per_size, full16=False):
+    """Oracle on a subsample of the uneven 3D workload: per mesh size the first
+    per_size RVEs of that size, solved concurrently on the host threads (one
+    RVE per thread; ctypes releases the GIL).  16^3 (about 4 minutes per RVE and
+    core) is timed only with full16; the batch estimate then extrapolates the
+    per-size rates to the 1024-RVE mix."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    from paper_1908_08292_amd import workloads
+    wl = workloads.rve3d(1024)
+    nthreads = len(os.sched_getaffinity(0))
+    out = {"workload": "rve3d_8-12-16_B1024", "cores": nthreads, "kind": "oracle", "per_size": {}}
+    sizes = (8, 12, 16) if full16 else (8, 12)
+
+    def one(b):
+        n = int(wl.n[b])
+        r = oracle.rve_solve(3, n, oracle.phase_by_centroid(3, n, float(wl.radius[b])),
+                             oracle.two_phase_lame(float(wl.ratio[b])), wl.F[b])
+        return r["status"]
+
+    for n in sizes:
+        idx = [int(i) for i in np.nonzero(wl.n == n)[0][:per_size]]
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=nthreads) as ex:
+            st = list(ex.map(one, idx))
+        dt = time.perf_counter() - t0
+        out["per_size"][f"{n}^3"] = dict(rves=len(idx), seconds=dt, solves_per_s=len(idx) / dt,
+                                         threads=min(nthreads, len(idx)), failed=int(sum(x != 0 for x in st)))
+        print(f"[bench] oracle 3d {n}^3: {len(idx)} RVEs in {dt:.1f} s", file=sys.stderr, flush=True)
+    if full16:
+        counts = {n: int((wl.n == n).sum()) for n in (8, 12, 16)}
+        est = sum(counts[n] / out["per_size"][f"{n}^3"]["solves_per_s"] for n in (8, 12, 16))
+        out["batch_estimate"] = dict(seconds=est, solves_per_s=1024 / est, extrapolated=True,
+                                     note="per-size rates of the subsample applied to the 1024-RVE mix")
+    else:
+        out["note"] = "16^3 not timed in the default run (about 230 s per RVE and core); bench.py --cpu-3d-full"
     return out
 
 
@@ -176,10 +229,12 @@ def surrogate_bench(macro_steps):
     # macro steps/s, plain FP64 vs surrogate with fallback (nested)
     lame = rve.two_phase_lame(10.0)
     runs = {}
-    for use in (False, True):
+    # plain FP64 at the default macro tolerance (1e-10) and at the surrogate's (1e-4)
+    for use in (False, "plain_rtol", True):
         mesh = rve.Mesh(2, 16, lame, radius=0.25)
-        drv = fehmm.Driver(mesh, nx=64, ny=64, hole_r=0.2, bc=fehmm.BC_UNIAXIAL, stretch=1.15, nsteps=20)
-        if use:
+        drv = fehmm.Driver(mesh, nx=64, ny=64, hole_r=0.2, bc=fehmm.BC_UNIAXIAL, stretch=1.15, nsteps=20,
+                           rtol_macro=1e-4 if use == "plain_rtol" else 1e-10)
+        if use is True:
             drv.set_surrogate(sg, threshold=1e-3, precision=surrogate.BF16X3, macro_rtol=1e-4)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -188,22 +243,28 @@ def surrogate_bench(macro_steps):
             st = drv.step(k)
             its.append(st["macro_iters"])
             ev += (st["macro_iters"] + 1) * drv.nqp
-            fb += st["fallback_points"] if use else (st["macro_iters"] + 1) * drv.nqp
+            fb += st["fallback_points"] if use is True else (st["macro_iters"] + 1) * drv.nqp
             ok = ok and st["status"] == 0
         dt = time.perf_counter() - t0
         runs[use] = dict(macro_steps_per_s=macro_steps / dt, seconds=dt, macro_iters=its, rve_solves=int(fb),
-                         qp_evaluations=int(ev), converged=bool(ok), u=drv.u())
-        if use:
+                         qp_evaluations=int(ev), converged=bool(ok), u=drv.u(),
+                         macro_rtol=1e-10 if use is False else 1e-4)
+        if use is True:
             F_last = torch.tensor(drv.qp()[0], device="cuda").reshape(-1, 4).contiguous()
         drv.destroy()
-        print(f"[bench] plate 64x64 {'surrogate' if use else 'plain'}: {runs[use]['seconds']:.2f} s",
-              file=sys.stderr, flush=True)
-    du = float(np.linalg.norm(runs[True]["u"] - runs[False]["u"]) / np.linalg.norm(runs[False]["u"]))
+        print(f"[bench] plate 64x64 {use}: {runs[use]['seconds']:.2f} s", file=sys.stderr, flush=True)
+    ref = runs[False]["u"]
+    du = float(np.linalg.norm(runs[True]["u"] - ref) / np.linalg.norm(ref))
+    du_plain = float(np.linalg.norm(runs["plain_rtol"]["u"] - ref) / np.linalg.norm(ref))
     for r in runs.values():
         r.pop("u")
-    out["macro_plate64_hole_rve16"] = dict(plain_fp64=runs[False], surrogate=runs[True],
-                                           speedup=runs[True]["macro_steps_per_s"] / runs[False]["macro_steps_per_s"],
-                                           rel_displacement_diff=du, steps=macro_steps, rves=int(F_last.shape[0]))
+    runs["plain_rtol"]["rel_displacement_diff"] = du_plain
+    out["macro_plate64_hole_rve16"] = dict(
+        plain_fp64=runs[False], plain_fp64_at_surrogate_rtol=runs["plain_rtol"], surrogate=runs[True],
+        speedup=runs[True]["macro_steps_per_s"] / runs[False]["macro_steps_per_s"],
+        speedup_at_equal_rtol=runs[True]["macro_steps_per_s"] / runs["plain_rtol"]["macro_steps_per_s"],
+        rel_displacement_diff=du, steps=macro_steps, rves=int(F_last.shape[0]),
+        note="rel_displacement_diff against the plain run at macro rtol 1e-10")
     # evals/s on the last state's 14288 points, and the audit of a 2% random sample
     nq = F_last.shape[0]
     P = torch.empty(nq, 4, dtype=torch.float64, device="cuda")
@@ -249,19 +310,26 @@ def surrogate_bench(macro_steps):
     return out
 
 
-def macro_bench(nsteps3):
-    """Macro steps/s of the GPU two-scale driver (host wall clock per load step)."""
+MACRO_CASES = [
+    # name, driver keywords, RVE elements per edge, load steps run
+    ("plate4x4_rve8x8", dict(nx=4, ny=4, hole_r=0.0, bc=0, stretch=1.1, nsteps=10), 8, 10),
+    ("plate64x64_hole_rve16x16", dict(nx=64, ny=64, hole_r=0.2, bc=1, stretch=1.15, nsteps=20), 16, 20),
+]
+
+
+def macro_bench(oracle_baseline=True):
+    """Macro steps/s of the GPU two-scale driver (host wall clock per load step),
+    nested and alternating two-level Newton, on the 4 x 4 plate (RVE 8 x 8, 10
+    steps) and the 64 x 64 plate with a hole (14288 RVEs of 16 x 16, all 20
+    steps); beside it the oracle's macro driver on the host: all 10 steps of the
+    4 x 4 plate (both schemes) and load step 1 of the 64 x 64 plate (nested)."""
     from paper_1908_08292_amd import fehmm, rve
     res = {}
     lame = rve.two_phase_lame(10.0)
-    cases = [("plate4x4_rve8x8", dict(nx=4, ny=4, hole_r=0.0, bc=fehmm.BC_CLAMPED_PULL, stretch=1.1, nsteps=10),
-              8, 10),
-             ("plate64x64_hole_rve16x16", dict(nx=64, ny=64, hole_r=0.2, bc=fehmm.BC_UNIAXIAL, stretch=1.15,
-                                                nsteps=20), 16, nsteps3)]
-    for name, kw, n, nrun in cases:
+    for name, kw, n, nrun in MACRO_CASES:
         for scheme, sname in ((fehmm.NESTED, "nested"), (fehmm.ALTERNATING, "alternating")):
             mesh = rve.Mesh(2, n, lame, radius=0.25)
-            drv = fehmm.Driver(mesh, scheme=scheme, **kw)
+            drv = fehmm.Driver(mesh, scheme=scheme, max_macro_iter=40, **kw)
             t0 = time.perf_counter()
             its, mic, ok = [], 0, True
             for k in range(1, nrun + 1):
@@ -269,14 +337,78 @@ def macro_bench(nsteps3):
                 its.append(st["macro_iters"])
                 mic += st["micro_iters"]
                 ok = ok and st["status"] == 0
-                print(f"[bench] {name} {sname} step {k}: {st['macro_iters']} macro iters", file=sys.stderr,
-                      flush=True)
             dt = time.perf_counter() - t0
+            print(f"[bench] {name} {sname}: {nrun} steps in {dt:.2f} s, macro iters {its}", file=sys.stderr,
+                  flush=True)
             res[f"{name}_{sname}"] = dict(macro_steps_per_s=nrun / dt, steps=nrun, rves=drv.nqp,
-                                          macro_iters=its, micro_iters=int(mic), converged=bool(ok),
-                                          seconds=dt)
+                                          macro_iters=its, total_macro_iters=int(sum(its)),
+                                          micro_updates=int(mic), converged=bool(ok), seconds=dt,
+                                          u_max=float(st["u_max"]))
             drv.destroy()
+    for name in ("plate4x4_rve8x8", "plate64x64_hole_rve16x16"):
+        a, b = res[f"{name}_nested"], res[f"{name}_alternating"]
+        res[f"{name}_alternating_vs_nested"] = dict(
+            time_ratio=b["seconds"] / a["seconds"], macro_iter_ratio=b["total_macro_iters"] / a["total_macro_iters"],
+            micro_update_ratio=b["micro_updates"] / max(a["micro_updates"], 1))
+    if oracle_baseline:
+        res["cpu_baseline"] = macro_oracle_baseline()
     return res
+
+
+def macro_oracle_baseline():
+    import oracle
+    nthreads = len(os.sched_getaffinity(0))
+    out = {"kind": "oracle", "cores": nthreads}
+    lame = oracle.two_phase_lame(10.0)
+    for name, kw, n, nrun in MACRO_CASES:
+        ph = oracle.phase_by_centroid(2, n, 0.25)
+        schemes = (0, 1) if nrun == 10 else (0,)
+        for scheme in schemes:
+            m = oracle.Macro(kw["nx"], kw["ny"], n, ph, lame, hole_r=kw["hole_r"], bc=kw["bc"],
+                             stretch=kw["stretch"], nsteps=kw["nsteps"], scheme=scheme, max_macro_iter=40)
+            steps = nrun if nrun == 10 else 1
+            t0 = time.perf_counter()
+            its = [m.step(k)["macro_iters"] for k in range(1, steps + 1)]
+            dt = time.perf_counter() - t0
+            m.close()
+            sname = "nested" if scheme == 0 else "alternating"
+            out[f"{name}_{sname}"] = dict(macro_steps_per_s=steps / dt, steps_timed=steps, seconds=dt,
+                                         macro_iters=its)
+            print(f"[bench] oracle {name} {sname}: {steps} steps in {dt:.1f} s", file=sys.stderr, flush=True)
+    return out
+
+
+def assembly_block(s, wl, meta, reps=20):
+    """The assembly phase alone (element pass + residual gather of every RVE,
+    rve_assemble_batch) on the timed batch at w = 0, against HBM: algorithmic
+    bytes per assembly = w + phase + R + the symmetric node-block tangent
+    (nodes x d^2 x (3^d + 1) / 2 doubles), and the bytes this kernel moves
+    (w, phase, element residuals written and read back, element tangents, R)."""
+    import torch
+    d, n, B = meta["d"], int(wl.n[0]), meta["B"]
+    nn = ne = n ** d
+    nen = 2 ** d
+    nd = nen * d
+    alg = 8 * nn * d * 2 + ne + 8 * nn * d * d * (3 ** d + 1) / 2
+    moved = 8 * nn * d * 2 + ne + 8 * ne * nd * 2 + 8 * ne * nd * nd + 8 * nn * d
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        s.batch.assemble(s.F, None, s.status, stream=stream.cuda_stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        s.batch.assemble(s.F, None, s.status, stream=stream.cuda_stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    ach = alg * B / (ms * 1e-3) / 1e9
+    ach_moved = moved * B / (ms * 1e-3) / 1e9
+    return {"kernel": f"rve_assembly_kernel<{d}>", "ms_per_launch": ms, "rves": B,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": ach / PEAK_HBM_GBS, "bytes_per_assembly": alg,
+                         "bytes_counted": "w + phase + R + symmetric node-block K (algorithmic)"},
+            "moved_bytes_per_assembly": moved, "achieved_gbs_on_moved_bytes": ach_moved}
 
 
 def rve3d_block(precs, steps=1, warmup=1):
@@ -321,13 +453,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rve2d_32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--cpu-sample", type=int, default=768)
     ap.add_argument("--calib-copy", type=int, default=0)
-    ap.add_argument("--macro", action="store_true")
+    ap.add_argument("--no-macro", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32ir", "both"], default="both")
     ap.add_argument("--macro-steps", type=int, default=4)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-cpu-3d", action="store_true")
+    ap.add_argument("--cpu-3d-full", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true")
+    ap.add_argument("--no-assembly", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: runs on one GPU only (the RVE batch would be sharded by macro elements "
@@ -396,16 +532,26 @@ def main():
                                       mean_newton_iters=float(t["res"]["iters"].mean()),
                                       dtype="f32 factors (LDL^T, solves) + f64 residuals, refinement, "
                                             "norms, averages and condensation")
+    if not args.no_assembly and d == 2:
+        out["assembly"] = assembly_block(s, wl, meta)
+        print(f"[bench] assembly: {out['assembly']['ms_per_launch']:.3f} ms", file=sys.stderr, flush=True)
+    if not args.no_peaks:
+        out["measured_peaks"] = dict(rve.probe_peaks(stream.cuda_stream),
+                                     probe="rve_probe_peaks: v_mfma_*_16x16x4 with 8 independent accumulators "
+                                           "per wave; 1 GiB device copy (read + write bytes)")
+        print(f"[bench] peaks: {out['measured_peaks']}", file=sys.stderr, flush=True)
     if not args.no_3d and d == 2:
         out["rve3d_uneven"] = rve3d_block(precs)
-    if args.macro:
-        out["macro"] = macro_bench(args.macro_steps)
+    if not args.no_macro and d == 2:
+        out["macro"] = macro_bench(oracle_baseline=not args.no_cpu_baseline)
     if not args.no_surrogate and d == 2:
         out["surrogate"] = surrogate_bench(args.macro_steps)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, meta, args.cpu_sample,
                                            gpu_results={p: t["res"] for p, t in timed.items()})
+        if not args.no_cpu_3d and not args.no_3d and d == 2:
+            out["rve3d_uneven"]["cpu_baseline"] = cpu_baseline_3d(16, full16=args.cpu_3d_full)
     print(json.dumps(out), flush=True)
 
 

@@ -235,6 +235,24 @@ int rve_plan_export(int32_t ndim, int32_t n, int64_t* sizes, int32_t* fronts, in
  * the workgroup fronts. */
 int rve_plan_schedule(int32_t ndim, int32_t n, int64_t* nsteps, int32_t* steps, int32_t* wave);
 
+/* ---- the assembly phase alone ------------------------------------------------
+ * rve_assemble_batch: runs one assembly of every RVE of the batch -- the element
+ * pass (F at the Gauss points, the neo-Hookean P and A, element residual and
+ * tangent) and the node gather of the residual, Sec. 3.3 -- at its stored
+ * fluctuation (w_state, may be NULL: zero) and the macro gradient F, into the
+ * batch's workspace, without the linear solve.  It exists to time the assembly
+ * phase of the Newton iteration on its own.  status [B] (may be NULL) receives
+ * RVE_S_DETF where some J <= 0, else RVE_S_CONVERGED.  Asynchronous. */
+int rve_assemble_batch(rve_batch b, const double* F, const double* w_state, int32_t* status, void* hip_stream);
+
+/* ---- measured ceilings -------------------------------------------------------
+ * rve_probe_peaks: rates this device reaches on plain probes, for reading the
+ * solver's roofline fractions beside the published peaks: dense FP64 and FP32
+ * MFMA (v_mfma_*_16x16x4, eight independent accumulators per wave, eight
+ * four-wave workgroups per CU) in TFLOP/s, and a 1 GiB device-to-device copy in
+ * GB/s (bytes read + written).  Host-blocking; allocates and frees 2 GiB. */
+int rve_probe_peaks(double* fp64_mfma_tflops, double* fp32_mfma_tflops, double* hbm_copy_gbs, void* hip_stream);
+
 /* ---- errors ------------------------------------------------------------------ */
 const char* rve_strerror(int code);
 /* Copies the calling thread's last error message (NUL-terminated) into buf. */

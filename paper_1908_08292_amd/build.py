@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librve.so")
 SOURCES = ["plan.cpp", "rve_abi.cpp", "rve_solve.hip", "rve_solve512.hip", "rve_static.hip", "fehmm.hip",
-           "surrogate.hip"]
+           "surrogate.hip", "probe.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed FP32 add/mul/FMA in any kernel: the device pass honours
          # this target feature switch (the host pass warns that it does not

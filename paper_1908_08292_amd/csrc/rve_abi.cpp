@@ -21,11 +21,13 @@ namespace fehmm {
 // the solver compiled with 256-thread (four-wave) and 512-thread (eight-wave) workgroups
 namespace nt256 {
 hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, bool fp32, hipStream_t stream);
+hipError_t launch_rve_assembly(const SolveArgs& a, int nslots, hipStream_t stream);
 hipError_t prepare_rve_solve();
 int lds_static_bytes();
 }
 namespace nt512 {
 hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, bool fp32, hipStream_t stream);
+hipError_t launch_rve_assembly(const SolveArgs& a, int nslots, hipStream_t stream);
 hipError_t prepare_rve_solve();
 int lds_static_bytes();
 }
@@ -620,6 +622,34 @@ int rve_solve_batch_subset(rve_batch b, const int32_t* idx, const int32_t* count
                            void* hip_stream) {
     if (!idx || !count) return fail(RVE_EINVAL, "rve_solve_batch_subset: idx and count are required");
     return solve_batch_impl(b, idx, count, F, P, A, w_state, status, iters, opts, hip_stream, nullptr);
+}
+
+int rve_assemble_batch(rve_batch b, const double* F, const double* w_state, int32_t* status, void* hip_stream) {
+    if (!b || !b->alive || !F) return fail(RVE_EINVAL, "rve_assemble_batch: invalid argument");
+    int pst = ensure_prepared();
+    if (pst) return pst;
+    SolveArgs a{};
+    a.plans = b->d_plans;
+    a.rve_plan = b->d_rve_plan;
+    a.rve_phase = b->d_rve_phase;
+    a.phase_pool = b->d_phase_pool;
+    a.rve_lame = b->d_rve_lame;
+    a.lame_pool = b->d_lame_pool;
+    a.state_off = b->d_state_off;
+    a.rve_atol = b->d_atol;
+    a.order = b->d_order;
+    a.B = b->B;
+    a.ws = b->d_ws;
+    a.lay = b->lay;
+    a.counter = b->d_counter;
+    a.F = F;
+    a.wstate = const_cast<double*>(w_state);
+    a.status = status;
+    a.dim = b->d;
+    a.atol = -1.0;
+    hipError_t e = nt256::launch_rve_assembly(a, b->nslots, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(RVE_EHIP, std::string("rve_assemble_batch launch: ") + hipGetErrorString(e));
+    return RVE_OK;
 }
 
 int rve_solve_batch_sync(rve_batch b, const double* F, double* P, double* A, double* w_state, int32_t* status,

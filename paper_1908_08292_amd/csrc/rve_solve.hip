@@ -1910,6 +1910,58 @@ __device__ double free_norm2(const RveCtx& c, Smem& sm, const double* R) {
     return sm.outv[0];
 }
 
+// per-RVE context (plan, phases, Lame table, slot regions) and the uniform-grid
+// constants in LDS: grad N at the Gauss points, w|J|, Fbar, the tolerance
+template <int D>
+__device__ inline void rve_setup(const SolveArgs& a, int rve, double* base, RveCtx& c, Smem& sm) {
+    constexpr int NEN = 1 << D, ND = NEN * D, D2 = D * D;
+    c.plan = &a.plans[a.rve_plan[rve]];
+    c.d = D;
+    c.n = c.plan->n;
+    c.ne = c.plan->nelem;
+    c.nn = c.plan->nnode;
+    c.nen = NEN;
+    c.nd = ND;
+    c.phase = a.phase_pool + a.rve_phase[rve];
+    c.lame = a.lame_pool + a.rve_lame[rve];
+    c.w = base + a.lay.w;
+    c.wt = base + a.lay.wt;
+    c.R = base + a.lay.R;
+    c.rhs = base + a.lay.rhs;
+    c.x = base + a.lay.x;
+    c.fe = base + a.lay.fe;
+    c.ke = base + a.lay.ke;
+    c.re = base + a.lay.re;
+    c.L = base + a.lay.L;
+    c.U = base + a.lay.U;
+    c.S = base + a.lay.S;
+    // constants of the uniform grid: grad N at the Gauss points, w|J|
+    if (threadIdx.x < NEN * NEN) {
+        const int gp = threadIdx.x / NEN, an = threadIdx.x % NEN;
+        const double gq = 0.57735026918962576451, h = 1.0 / c.n;
+        int og[3] = {0, 0, 0}, oa[3] = {0, 0, 0};
+        local_offset(D, gp, og);
+        local_offset(D, an, oa);
+        for (int k = 0; k < D; ++k) {
+            double v = 1.0;
+            for (int q = 0; q < D; ++q) {
+                const double sa = oa[q] ? 1.0 : -1.0, xi = og[q] ? gq : -gq;
+                v *= (q == k) ? 0.5 * sa : 0.5 * (1.0 + sa * xi);
+            }
+            sm.dN[(gp * 8 + an) * 3 + k] = v * 2.0 / h;
+        }
+    }
+    if (threadIdx.x < D2) sm.Fbar[threadIdx.x] = a.F[(int64_t)rve * D2 + threadIdx.x];
+    if (threadIdx.x == 0) {
+        double h = 1.0 / c.n, wj = 1.0;
+        for (int k = 0; k < D; ++k) wj *= 0.5 * h;
+        sm.wJ = wj;
+        sm.flag = 0;
+        sm.atol = a.atol >= 0 ? a.atol : a.rve_atol[rve];
+    }
+    __syncthreads();
+}
+
 template <int D, typename T>
 __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
     __shared__ Smem sm;
@@ -1942,54 +1994,10 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
         const int rve = sm.rve;
         if (rve < 0) return;
         RveCtx c;
-        c.plan = &a.plans[a.rve_plan[rve]];
-        c.d = D;
-        c.n = c.plan->n;
-        c.ne = c.plan->nelem;
-        c.nn = c.plan->nnode;
-        c.nen = NEN;
-        c.nd = ND;
-        c.phase = a.phase_pool + a.rve_phase[rve];
-        c.lame = a.lame_pool + a.rve_lame[rve];
-        c.w = base + a.lay.w;
-        c.wt = base + a.lay.wt;
-        c.R = base + a.lay.R;
-        c.rhs = base + a.lay.rhs;
-        c.x = base + a.lay.x;
-        c.fe = base + a.lay.fe;
-        c.ke = base + a.lay.ke;
-        c.re = base + a.lay.re;
-        c.L = base + a.lay.L;
-        c.U = base + a.lay.U;
-        c.S = base + a.lay.S;
+        rve_setup<D>(a, rve, base, c, sm);
         double* ir1 = base + a.lay.ir1;
         double* ir2 = base + a.lay.ir2;
         const int ndof = c.nn * D;
-        // constants of the uniform grid: grad N at the Gauss points, w|J|
-        if (threadIdx.x < NEN * NEN) {
-            const int gp = threadIdx.x / NEN, an = threadIdx.x % NEN;
-            const double gq = 0.57735026918962576451, h = 1.0 / c.n;
-            int og[3] = {0, 0, 0}, oa[3] = {0, 0, 0};
-            local_offset(D, gp, og);
-            local_offset(D, an, oa);
-            for (int k = 0; k < D; ++k) {
-                double v = 1.0;
-                for (int q = 0; q < D; ++q) {
-                    const double sa = oa[q] ? 1.0 : -1.0, xi = og[q] ? gq : -gq;
-                    v *= (q == k) ? 0.5 * sa : 0.5 * (1.0 + sa * xi);
-                }
-                sm.dN[(gp * 8 + an) * 3 + k] = v * 2.0 / h;
-            }
-        }
-        if (threadIdx.x < D2) sm.Fbar[threadIdx.x] = a.F[(int64_t)rve * D2 + threadIdx.x];
-        if (threadIdx.x == 0) {
-            double h = 1.0 / c.n, wj = 1.0;
-            for (int k = 0; k < D; ++k) wj *= 0.5 * h;
-            sm.wJ = wj;
-            sm.flag = 0;
-            sm.atol = a.atol >= 0 ? a.atol : a.rve_atol[rve];
-        }
-        __syncthreads();
         // input checks and initial guess
         bool finite_in = true;
 #pragma unroll
@@ -2187,6 +2195,36 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
     }
 }
 
+// The Newton residual and the element tangents of every RVE at its stored (or
+// zero) fluctuation, alone: one element pass and the node gather of R per RVE
+// (the assembly phase of a Newton iteration, timed on its own by
+// rve_assemble_batch).  status[r] = 2 where some J <= 0, else 0.
+template <int D>
+__global__ __launch_bounds__(NT, 512 / NT) void rve_assembly_kernel(SolveArgs a) {
+    __shared__ Smem sm;
+    double* base = a.ws + (int64_t)blockIdx.x * a.lay.stride;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const unsigned int idx = atomicAdd(a.counter, 1u);
+            sm.rve = idx < (unsigned int)a.B ? a.order[idx] : -1;
+        }
+        __syncthreads();
+        const int rve = sm.rve;
+        if (rve < 0) return;
+        RveCtx c;
+        rve_setup<D>(a, rve, base, c, sm);
+        const int ndof = c.nn * D;
+        const double* wst = a.wstate ? a.wstate + a.state_off[rve] : nullptr;
+        for (int t = threadIdx.x; t < ndof; t += NT) c.w[t] = (wst && t >= D) ? wst[t] : 0.0;
+        __syncthreads();
+        element_pass<D>(c, sm, c.w, 0, nullptr, nullptr);
+        __syncthreads();
+        node_gather<D>(c, c.fe, 1, c.R, 1.0);
+        if (threadIdx.x == 0 && a.status) a.status[rve] = sm.flag ? 2 : 0;
+        __syncthreads();
+    }
+}
+
 __global__ void reset_counter_kernel(unsigned int* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
@@ -2203,6 +2241,15 @@ hipError_t prepare_rve_solve() {
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_rve_assembly(const SolveArgs& a, int nslots, hipStream_t stream) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, a.counter);
+    if (a.dim == 2)
+        hipLaunchKernelGGL((rve_assembly_kernel<2>), dim3(nslots), dim3(NT), 0, stream, a);
+    else
+        hipLaunchKernelGGL((rve_assembly_kernel<3>), dim3(nslots), dim3(NT), 0, stream, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_rve_solve(const SolveArgs& a, int nslots, size_t dyn_bytes, bool fp32, hipStream_t stream) {

@@ -69,6 +69,8 @@ def lib():
         L.rve_solve_batch_sync.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(Opts), vp]
         L.rve_solve_batch_subset.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Opts), vp]
         L.rve_solve_batch_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(Opts), vp]
+        L.rve_probe_peaks.argtypes = [C.POINTER(dp), C.POINTER(dp), C.POINTER(dp), vp]
+        L.rve_assemble_batch.argtypes = [vp, vp, vp, vp, vp]
         L.rve_plan_info.argtypes = [i32, i32, C.POINTER(dp), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]
         L.rve_plan_export.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.rve_plan_schedule.argtypes = [i32, i32, vp, vp, vp]
@@ -152,6 +154,14 @@ def autotune(mesh, F, opts=None, stream=None):
     check(lib().rve_autotune(mesh.h, _ptr(F), nF, C.byref(o), C.byref(t), C.c_void_p(stream) if stream else None),
           "rve_autotune")
     return _tuning_dict(t)
+
+
+def probe_peaks(stream=None):
+    """Measured FP64 / FP32 MFMA TFLOP/s and HBM copy GB/s of the current device."""
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    check(lib().rve_probe_peaks(C.byref(a), C.byref(b), C.byref(c), C.c_void_p(stream) if stream else None),
+          "rve_probe_peaks")
+    return dict(fp64_mfma_tflops=a.value, fp32_mfma_tflops=b.value, hbm_copy_gbs=c.value)
 
 
 def plan_info(d, n):
@@ -273,6 +283,17 @@ class Batch:
         fn = lib().rve_solve_batch_static if static else (lib().rve_solve_batch_sync if sync else lib().rve_solve_batch)
         return check(fn(self.h, _ptr(F), _ptr(P), _ptr(A), _ptr(w_state), _ptr(status), _ptr(iters),
                         C.byref(o), s), "rve_solve_batch_static" if static else "rve_solve_batch")
+
+    def assemble(self, F, w_state=None, status=None, stream=None):
+        """One assembly (element pass + residual gather) of every RVE, alone
+        (rve_assemble_batch)."""
+        import torch
+        d2 = self.d * self.d
+        self._check(F, self.B * d2, torch.float64, "F")
+        self._check(w_state, int(self.state_offsets[-1]), torch.float64, "w_state")
+        self._check(status, self.B, torch.int32, "status")
+        s = C.c_void_p(stream) if stream is not None else None
+        return check(lib().rve_assemble_batch(self.h, _ptr(F), _ptr(w_state), _ptr(status), s), "rve_assemble_batch")
 
     def solve_subset(self, idx, count, F, P, A=None, w_state=None, status=None, iters=None, opts=None, stream=None):
         """Solves only the RVEs idx[0 .. count[0]) (device int32 tensors)."""
