@@ -62,6 +62,12 @@ _dp = C.POINTER(C.c_double)
 def _setup(L):
     L.oracle_nh_sc.restype = C.c_int
     L.oracle_nh_sc.argtypes = [C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.oracle_set_law.restype = None
+    L.oracle_set_law.argtypes = [C.c_int]
+    L.oracle_get_law.restype = C.c_int
+    L.oracle_law_sc.restype = C.c_int
+    L.oracle_law_sc.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p]
     L.oracle_phase_by_centroid.restype = None
     L.oracle_phase_by_centroid.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_void_p]
     L.oracle_element.restype = C.c_int
@@ -145,6 +151,41 @@ def nh_sc(d, lam, mu, F):
     F = _f64(F).reshape(d, d)
     S = np.zeros((d, d)); Cm = np.zeros((d,) * 4); psi = np.zeros(1)
     st = lib().oracle_nh_sc(d, lam, mu, _p(F), _p(S), _p(Cm), _p(psi))
+    return st, S, Cm, float(psi[0])
+
+
+LAW_NEOHOOKE, LAW_SVK, LAW_LINEAR = 0, 1, 2
+
+
+def set_law(law):
+    """Micro constitutive law of every later oracle call (process-wide)."""
+    lib().oracle_set_law(int(law))
+
+
+def get_law():
+    return lib().oracle_get_law()
+
+
+class law:
+    """Context manager: `with oracle.law(oracle.LAW_SVK): ...`."""
+
+    def __init__(self, which):
+        self.which = which
+
+    def __enter__(self):
+        self.prev = get_law()
+        set_law(self.which)
+        return self
+
+    def __exit__(self, *exc):
+        set_law(self.prev)
+
+
+def law_sc(which, d, lam, mu, F):
+    """S (sigma for the linear law), material tangent (d^4) and psi."""
+    F = _f64(F).reshape(d, d)
+    S = np.zeros((d, d)); Cm = np.zeros((d,) * 4); psi = np.zeros(1)
+    st = lib().oracle_law_sc(int(which), d, lam, mu, _p(F), _p(S), _p(Cm), _p(psi))
     return st, S, Cm, float(psi[0])
 
 

@@ -39,6 +39,18 @@ enum { ORC_OK = 0, ORC_NOCONV = 1, ORC_DETF = 2, ORC_SINGULAR = 3, ORC_NONFINITE
  * or ORC_DETF when det F <= 0. */
 int oracle_nh_sc(int d, double lam, double mu, const double* F, double* S, double* Cmat, double* psi);
 
+/* Micro constitutive law used by every later call (process-wide; default the
+ * neo-Hookean law).  ORC_LAW_SVK: geometrically nonlinear linear elasticity
+ * (St. Venant-Kirchhoff, S = lambda tr(E) 1 + 2 mu E); ORC_LAW_LINEAR: the
+ * fully linear case (small strain, sigma = lambda tr(eps) 1 + 2 mu eps, which
+ * stands for both S and P; no geometric stiffness) -- the laws of the paper's
+ * micro-convergence comparisons (Sec. 6). */
+enum { ORC_LAW_NEOHOOKE = 0, ORC_LAW_SVK = 1, ORC_LAW_LINEAR = 2 };
+void oracle_set_law(int law);
+int oracle_get_law(void);
+/* S (or sigma), the material tangent (d^4) and psi of law at F; as oracle_nh_sc. */
+int oracle_law_sc(int law, int d, double lam, double mu, const double* F, double* S, double* Cmat, double* psi);
+
 /* Phase of every element by centroid: phase = incl_phase iff |centroid - c| < r. */
 void oracle_phase_by_centroid(int d, int n, const double* center, double r, int incl_phase,
                               int base_phase, uint8_t* phase);

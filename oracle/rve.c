@@ -86,6 +86,65 @@ int oracle_nh_sc(int d, double lam, double mu, const double* F, double* S, doubl
     return ORC_OK;
 }
 
+/* The constitutive variants of the paper's examples (Sec. 6 material table and
+ * micro-convergence studies): geometrically nonlinear linear elasticity, i.e.
+ * the St. Venant-Kirchhoff law S = lambda tr(E) 1 + 2 mu E with the
+ * Green-Lagrange strain E = (C - 1)/2 (psi = lambda/2 tr(E)^2 + mu E:E), and the
+ * fully linear case, small strain eps = sym(F - 1), sigma = lambda tr(eps) 1 +
+ * 2 mu eps, which takes the place of both S and P (no geometric stiffness).
+ * Cmat is the constant C_IJKL = lambda d_IJ d_KL + mu (d_IK d_JL + d_IL d_JK) for
+ * both.  2D is plane strain (E_33 = eps_33 = 0).  The J > 0 guard is kept for
+ * every law. */
+static int g_law = ORC_LAW_NEOHOOKE;
+
+void oracle_set_law(int law) { g_law = law; }
+int oracle_get_law(void) { return g_law; }
+
+int oracle_law_sc(int law, int d, double lam, double mu, const double* F, double* S, double* Cmat, double* psi) {
+    if (law == ORC_LAW_NEOHOOKE) return oracle_nh_sc(d, lam, mu, F, S, Cmat, psi);
+    if (!(det_d(d, F) > 0)) return ORC_DETF;
+    double E[9];
+    for (int I = 0; I < d; ++I)
+        for (int J = 0; J < d; ++J) {
+            double v;
+            if (law == ORC_LAW_SVK) {
+                v = 0;
+                for (int k = 0; k < d; ++k) v += F[k * d + I] * F[k * d + J];
+                v = 0.5 * (v - (I == J ? 1.0 : 0.0));
+            } else {
+                v = 0.5 * (F[I * d + J] + F[J * d + I]) - (I == J ? 1.0 : 0.0);
+            }
+            E[I * d + J] = v;
+        }
+    double trE = 0, EE = 0;
+    for (int I = 0; I < d; ++I) trE += E[I * d + I];
+    for (int q = 0; q < d * d; ++q) EE += E[q] * E[q];
+    for (int I = 0; I < d; ++I)
+        for (int J = 0; J < d; ++J) S[I * d + J] = (I == J ? lam * trE : 0.0) + 2.0 * mu * E[I * d + J];
+    if (Cmat)
+        for (int I = 0; I < d; ++I)
+            for (int J = 0; J < d; ++J)
+                for (int K = 0; K < d; ++K)
+                    for (int L = 0; L < d; ++L)
+                        Cmat[((I * d + J) * d + K) * d + L] = (I == J && K == L ? lam : 0.0) +
+                                                              mu * ((I == K && J == L ? 1.0 : 0.0) +
+                                                                    (I == L && J == K ? 1.0 : 0.0));
+    if (psi) *psi = 0.5 * lam * trE * trE + mu * EE;
+    return ORC_OK;
+}
+
+/* first Piola-Kirchhoff stress: P = F S, or sigma itself in the fully linear case */
+static void first_piola(int d, const double* F, const double* S, double* P) {
+    for (int i = 0; i < d; ++i)
+        for (int J = 0; J < d; ++J) {
+            double v = 0;
+            if (g_law == ORC_LAW_LINEAR) v = S[i * d + J];
+            else
+                for (int K = 0; K < d; ++K) v += F[i * d + K] * S[K * d + J];
+            P[i * d + J] = v;
+        }
+}
+
 /* ------------------------------------------------------------------ mesh */
 static int ipow(int n, int d) { int r = 1; for (int i = 0; i < d; ++i) r *= n; return r; }
 
@@ -186,17 +245,20 @@ int oracle_element(int d, int n, const uint8_t* phase, const double* lame, int e
                 F[i * d + J] = s;
             }
         double S[9], Cm[81], psi;
-        int st = oracle_nh_sc(d, lam, mu, F, S, Cm, &psi);
+        int st = oracle_law_sc(g_law, d, lam, mu, F, S, Cm, &psi);
         if (st) return st;
         en += psi * wJ;
-        /* B[r][a*d+k] : dE_r = sum B dd */
+        /* B[r][a*d+k] : dE_r = sum B dd (the linear B at F = 1 in the fully linear case) */
+        const int lin = g_law == ORC_LAW_LINEAR;
         double B[MAXV][MAXNE * MAXD];
         for (int r = 0; r < nv; ++r) {
             int I = pr[r][0], J = pr[r][1];
             for (int a = 0; a < nen; ++a)
                 for (int k = 0; k < d; ++k) {
-                    double v = F[k * d + I] * dN[p][a][J];
-                    if (I != J) v += F[k * d + J] * dN[p][a][I];
+                    double fkI = lin ? (k == I ? 1.0 : 0.0) : F[k * d + I];
+                    double fkJ = lin ? (k == J ? 1.0 : 0.0) : F[k * d + J];
+                    double v = fkI * dN[p][a][J];
+                    if (I != J) v += fkJ * dN[p][a][I];
                     B[r][a * d + k] = v;
                 }
         }
@@ -226,8 +288,8 @@ int oracle_element(int d, int n, const uint8_t* phase, const double* lame, int e
                     for (int r = 0; r < nv; ++r) s += B[r][q1] * CB[r][q2];
                     ke[q1 * nd + q2] += s * wJ;
                 }
-            /* initial-stress matrix S_hat_IK 1 */
-            for (int a = 0; a < nen; ++a)
+            /* initial-stress matrix S_hat_IK 1 (geometric stiffness; none in the fully linear case) */
+            for (int a = 0; a < nen && !lin; ++a)
                 for (int b = 0; b < nen; ++b) {
                     double sh = 0;
                     for (int I = 0; I < d; ++I)
@@ -367,7 +429,8 @@ static int all_J_positive(const rve_sys* r, const uint8_t* phase, const double* 
     return 1;
 }
 
-/* P = <P^eps> = sum_gp F S w|J| / |B_0| with |B_0| = 1 (eq. Average-of-P-and-F). */
+/* P = <P^eps> = sum_gp P(F) w|J| / |B_0| with |B_0| = 1 (eq. Average-of-P-and-F); P = F S, or sigma in
+ * the fully linear case. */
 static void average_P(const rve_sys* r, const uint8_t* phase, const double* lame, const double* Fbar,
                       const double* w, double* P) {
     double dN[MAXNE][MAXNE][MAXD], wJ;
@@ -386,13 +449,10 @@ static void average_P(const rve_sys* r, const uint8_t* phase, const double* lame
                     for (int a = 0; a < nen; ++a) s += w[nodes[a] * d + i] * dN[p][a][J];
                     F[i * d + J] = s;
                 }
-            oracle_nh_sc(d, lam, mu, F, S, NULL, NULL);
-            for (int i = 0; i < d; ++i)
-                for (int J = 0; J < d; ++J) {
-                    double s = 0;
-                    for (int K = 0; K < d; ++K) s += F[i * d + K] * S[K * d + J];
-                    P[i * d + J] += s * wJ;
-                }
+            double Pq[9];
+            oracle_law_sc(g_law, d, lam, mu, F, S, NULL, NULL);
+            first_piola(d, F, S, Pq);
+            for (int q = 0; q < d * d; ++q) P[q] += Pq[q] * wJ;
         }
     }
 }
