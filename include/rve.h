@@ -73,6 +73,14 @@ int rve_lame(double E, double nu, double* lambda_out, double* mu_out);
  *   phase      host array [n^d] of phase ids (x-fastest), or NULL: then an
  *              element is in incl_phase iff |centroid - incl_center| < incl_radius
  *              (strict), else in phase 0.  The data are copied.
+ *   law        micro constitutive law (RVE_LAW_*): the compressible neo-Hookean
+ *              law of Sec. 6 (default, 0), or the two laws the paper sets beside
+ *              it in its micro-convergence studies: geometrically nonlinear
+ *              linear elasticity (St. Venant-Kirchhoff, S = lambda tr(E) 1 +
+ *              2 mu E, E the Green-Lagrange strain) and the fully linear case
+ *              (small strain, sigma = lambda tr(eps) 1 + 2 mu eps takes the place
+ *              of P; A is the constant elasticity tensor).  The J > 0 guard of the
+ *              Newton update applies to every law.
  * The symbolic factorization plan for (ndim, n) is built on first use and shared
  * by every mesh of that size. */
 typedef struct {
@@ -84,7 +92,12 @@ typedef struct {
     double incl_center[3];
     double incl_radius;
     int32_t incl_phase;
+    int32_t law;
 } rve_mesh_desc;
+
+#define RVE_LAW_NEOHOOKE 0
+#define RVE_LAW_SVK 1
+#define RVE_LAW_LINEAR 2
 
 int rve_mesh_create(const rve_mesh_desc* desc, rve_mesh* out);
 int rve_mesh_destroy(rve_mesh m);

@@ -5,7 +5,7 @@ import numpy as np
 from . import rve
 
 
-def build_batch(d, n_list, radius_list, ratio_list, nu=0.3, E=1.0, center=None):
+def build_batch(d, n_list, radius_list, ratio_list, nu=0.3, E=1.0, center=None, law=rve.LAW_NEOHOOKE):
     """One mesh per distinct (n, radius, ratio); returns (Batch, meshes)."""
     cache = {}
     meshes = []
@@ -13,7 +13,7 @@ def build_batch(d, n_list, radius_list, ratio_list, nu=0.3, E=1.0, center=None):
         key = (int(n), float(r), float(q))
         if key not in cache:
             cache[key] = rve.Mesh(d, int(n), rve.two_phase_lame(float(q), E=E, nu=nu), radius=float(r),
-                                  center=center)
+                                  center=center, law=law)
         meshes.append(cache[key])
     return rve.Batch(meshes), meshes
 
@@ -98,3 +98,42 @@ def fit_surrogate(n=16, radius=0.25, ratio=10.0, n_train=200000, n_calib=20000, 
                        final_loss=float(np.mean(loss[-min(50, len(loss)):])) if len(loss) else None,
                        calibrate_s=t4 - t3)
     return sg
+
+
+def square_inclusion_phase(n, half=0.25):
+    """Phase ids of an n x n cell with the centred square inclusion
+    |x - 1/2| < half, |y - 1/2| < half (by element centroid); resolved exactly
+    when half * n is an integer."""
+    c = (np.arange(n) + 0.5) / n - 0.5
+    inside = (np.abs(c)[None, :] < half) & (np.abs(c)[:, None] < half)
+    return inside.reshape(-1).astype(np.uint8)
+
+
+def micro_convergence(law, ns=(4, 8, 16, 32, 64), F=None, ratio=10.0, half=0.25):
+    """Pbar and Abar of one 2D RVE with a square inclusion resolved exactly at
+    every n of ns (the micro-convergence setting of Sec. 6 with a synthetic
+    microstructure), solved on the GPU; returns dict n -> (P, A) and the orders
+    p_n = log2(|X_n - X_2n| / |X_2n - X_4n|) of successive differences."""
+    import torch
+    F = np.array([[1.08, 0.05], [-0.03, 0.94]]) if F is None else np.asarray(F, np.float64)
+    lame = rve.two_phase_lame(ratio)
+    out = {}
+    for n in ns:
+        mesh = rve.Mesh(2, int(n), lame, phase=square_inclusion_phase(int(n), half), law=law)
+        batch = rve.Batch([mesh])
+        s = Solver(batch, keep_state=False)
+        s.set_F(F.reshape(1, 4))
+        s.solve()
+        torch.cuda.synchronize()
+        r = s.results()
+        if r["status"][0] != 0:
+            raise RuntimeError(f"micro convergence: RVE n={n} failed with status {r['status'][0]}")
+        out[int(n)] = (r["P"][0].copy(), r["A"][0].copy())
+        batch.destroy()
+        mesh.destroy()
+    orders = {}
+    for key, idx in (("P", 0), ("A", 1)):
+        diffs = [np.linalg.norm(out[a][idx] - out[b][idx]) for a, b in zip(ns[:-1], ns[1:])]
+        orders[key] = [float(np.log2(diffs[k] / diffs[k + 1])) for k in range(len(diffs) - 1)]
+        orders[key + "_diffs"] = [float(x) for x in diffs]
+    return out, orders

@@ -19,7 +19,12 @@
 //     k_(a,i),(b,k) = sum_gp (mu d_ik grad N_a . grad N_b + c1 g_a,k g_b,i + c2 g_a,i g_b,k) w|J|
 //     Y_(a,i),(kL)  = sum_gp (mu d_ik dN_a,L + c1 g_a,k Fi_Li + c2 g_a,i Fi_Lk) w|J|
 // which equal int B^T S and int B^T C B + S_hat 1 of the paper's eqs. (DG^h,
-// G_IK, S_IK) written with P and A = dP/dF.
+// G_IK, S_IK) written with P and A = dP/dF.  The two other laws of the paper's
+// micro-convergence comparisons (Sec. 6) take a generic path with P and A
+// evaluated at the Gauss point (law_PA): St. Venant-Kirchhoff, P = F S with
+// S = lambda tr(E) 1 + 2 mu E, A_iJkL = d_ik S_JL + lambda F_iJ F_kL +
+// mu (F_iL F_kJ + (F F^T)_ik d_JL); and the fully linear case, P = sigma(eps),
+// eps = sym(F - 1), A the constant elasticity tensor.
 //
 // The linear solve is a multifrontal LDL^T (no pivoting: the tangent can be
 // indefinite at the initial guess past a micro-instability of a stiff inclusion)
@@ -128,6 +133,7 @@ __device__ inline void inv_det(const double* F, double* Fi, double& J) {
 struct RveCtx {
     const DevPlan* plan;
     int d, n, ne, nn, nen, nd;
+    int law;  // RVE_LAW_*: 0 neo-Hookean, 1 St. Venant-Kirchhoff, 2 fully linear
     const uint8_t* phase;
     const double* lame;
     double* w;
@@ -142,6 +148,72 @@ struct RveCtx {
     double* U;
     double* S;
 };
+
+// P and A = dP/dF (row-major [(i*D+J)*D*D + k*D+L]) of the St. Venant-Kirchhoff
+// law (law 1) or of the fully linear law (law 2) at F; plane strain in 2D
+template <int D>
+__device__ inline void law_PA(int law, double lam, double mu, const double* F, double* P, double* A) {
+    constexpr int D2 = D * D;
+    if (law == 1) {
+        double S[D2], B[D2];
+        double trE = 0.0;
+#pragma unroll
+        for (int I = 0; I < D; ++I)
+#pragma unroll
+            for (int J = 0; J < D; ++J) {
+                double c = 0.0, b = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    c += F[k * D + I] * F[k * D + J];
+                    b += F[I * D + k] * F[J * D + k];
+                }
+                S[I * D + J] = 0.5 * (c - (I == J ? 1.0 : 0.0));  // E for now
+                B[I * D + J] = b;
+            }
+#pragma unroll
+        for (int I = 0; I < D; ++I) trE += S[I * D + I];
+#pragma unroll
+        for (int q = 0; q < D2; ++q) S[q] = 2.0 * mu * S[q] + ((q % (D + 1)) == 0 ? lam * trE : 0.0);
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int J = 0; J < D; ++J) {
+                double v = 0.0;
+#pragma unroll
+                for (int K = 0; K < D; ++K) v += F[i * D + K] * S[K * D + J];
+                P[i * D + J] = v;
+            }
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int J = 0; J < D; ++J)
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+#pragma unroll
+                    for (int L = 0; L < D; ++L)
+                        A[(i * D + J) * D2 + k * D + L] = (i == k ? S[J * D + L] : 0.0) + lam * F[i * D + J] * F[k * D + L] +
+                                                          mu * (F[i * D + L] * F[k * D + J] + (J == L ? B[i * D + k] : 0.0));
+    } else {
+        double tr = 0.0;
+#pragma unroll
+        for (int I = 0; I < D; ++I) tr += F[I * D + I] - 1.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int J = 0; J < D; ++J)
+                P[i * D + J] = mu * (F[i * D + J] + F[J * D + i] - (i == J ? 2.0 : 0.0)) + (i == J ? lam * tr : 0.0);
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int J = 0; J < D; ++J)
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+#pragma unroll
+                    for (int L = 0; L < D; ++L)
+                        A[(i * D + J) * D2 + k * D + L] = (i == J && k == L ? lam : 0.0) +
+                                                          mu * ((i == k && J == L ? 1.0 : 0.0) + (i == L && J == k ? 1.0 : 0.0));
+    }
+}
 
 // F at Gauss point gp of element e for nodal fluctuation w
 template <int D>
@@ -168,11 +240,114 @@ __device__ inline void load_wl(const RveCtx& c, const double* w, int e, double* 
         for (int i = 0; i < D; ++i) wl[b * D + i] = w[nodes[b] * D + i];
 }
 
-// Element pass.  mode 0: residual + tangent rows (Newton); mode 1: J > 0 check
-// only (on w); mode 2: final outputs (Pbar, <A>, Y rows).  Work item = (e, a)
-// in 2D (rows i = 0,1), (e, a, i) in 3D.
+// Element pass of the St. Venant-Kirchhoff and fully linear laws: as
+// element_pass_nh, with P and A evaluated at each Gauss point (law_PA) and the rows
+// contracted with the material gradients,
+//     f_(a,i) = sum P_iJ dN_a,J w|J|,  k_(a,i),(b,k) = sum dN_a,J A_iJkL dN_b,L w|J|,
+//     Y_(a,i),(kL) = sum dN_a,J A_iJkL w|J|.
 template <int D>
-__device__ __noinline__ void element_pass(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP, double* accA) {
+__device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP,
+                                              double* accA) {
+    constexpr int NEN = 1 << D, ND = NEN * D, D2 = D * D, RPI = (D == 2) ? 2 : 1;
+    const int nitems = c.ne * NEN * (D / RPI);
+    const double wJ = sm.wJ;
+    for (int it = threadIdx.x; it < nitems; it += NT) {
+        int e, a, i0;
+        if (D == 2) { e = it / NEN; a = it % NEN; i0 = 0; }
+        else { e = it / (NEN * D); a = (it / D) % NEN; i0 = it % D; }
+        if (mode == 1 && (a != 0 || i0 != 0)) continue;
+        double wl[ND];
+        int nodes[NEN];
+        load_wl<D>(c, w, e, wl, nodes);
+        const int ph = c.phase[e];
+        const double lam = c.lame[2 * ph], mu = c.lame[2 * ph + 1];
+        double kr[RPI][ND];
+        double fr[RPI];
+        double yr[RPI][D2];
+#pragma unroll
+        for (int r = 0; r < RPI; ++r) {
+            fr[r] = 0;
+#pragma unroll
+            for (int q = 0; q < ND; ++q) kr[r][q] = 0;
+#pragma unroll
+            for (int q = 0; q < D2; ++q) yr[r][q] = 0;
+        }
+        for (int gp = 0; gp < NEN; ++gp) {
+            double F[D2], Fi[D2], J;
+            gp_F<D>(c, sm, wl, gp, F);
+            inv_det<D>(F, Fi, J);
+            if (!(J > 0.0)) { sm.flag = 1; continue; }
+            if (mode == 1) continue;
+            double Pg[D2], Ag[D2 * D2];
+            law_PA<D>(c.law, lam, mu, F, Pg, Ag);
+            if (mode == 2 && a == 0 && i0 == 0) {
+#pragma unroll
+                for (int q = 0; q < D2; ++q) accP[q] += Pg[q] * wJ;
+#pragma unroll
+                for (int q = 0; q < D2 * D2; ++q) accA[q] += Ag[q] * wJ;
+            }
+            const double* dNa = &sm.dN[(gp * 8 + a) * 3];
+#pragma unroll
+            for (int r = 0; r < RPI; ++r) {
+                const int i = i0 + r;
+                if (mode == 0) {
+                    double f = 0.0;
+#pragma unroll
+                    for (int Jj = 0; Jj < D; ++Jj) f += Pg[i * D + Jj] * dNa[Jj];
+                    fr[r] += f * wJ;
+#pragma unroll
+                    for (int b = 0; b < NEN; ++b) {
+                        const double* dNb = &sm.dN[(gp * 8 + b) * 3];
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            double v = 0.0;
+#pragma unroll
+                            for (int Jj = 0; Jj < D; ++Jj)
+#pragma unroll
+                                for (int L = 0; L < D; ++L) v += dNa[Jj] * Ag[(i * D + Jj) * D2 + k * D + L] * dNb[L];
+                            kr[r][b * D + k] += v * wJ;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+#pragma unroll
+                        for (int L = 0; L < D; ++L) {
+                            double v = 0.0;
+#pragma unroll
+                            for (int Jj = 0; Jj < D; ++Jj) v += dNa[Jj] * Ag[(i * D + Jj) * D2 + k * D + L];
+                            yr[r][k * D + L] += v * wJ;
+                        }
+                }
+            }
+        }
+        if (mode == 0) {
+#pragma unroll
+            for (int r = 0; r < RPI; ++r) {
+                const int row = a * D + i0 + r;
+                c.fe[(int64_t)e * ND + row] = fr[r];
+                double* kd = c.ke + ((int64_t)e * ND + row) * ND;
+#pragma unroll
+                for (int q = 0; q < ND; ++q) kd[q] = kr[r][q];
+            }
+        } else if (mode == 2) {
+#pragma unroll
+            for (int r = 0; r < RPI; ++r) {
+                const int row = a * D + i0 + r;
+                double* yd = c.re + ((int64_t)e * ND + row) * D2;
+#pragma unroll
+                for (int q = 0; q < D2; ++q) yd[q] = yr[r][q];
+            }
+        }
+    }
+}
+
+// Element pass of the neo-Hookean law.  mode 0: residual + tangent rows
+// (Newton); mode 1: J > 0 check only (on w); mode 2: final outputs (Pbar, <A>,
+// Y rows).  Work item = (e, a) in 2D (rows i = 0,1), (e, a, i) in 3D.
+template <int D>
+__device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP,
+                                             double* accA) {
     constexpr int NEN = 1 << D, ND = NEN * D, RPI = (D == 2) ? 2 : 1;
     const int nitems = c.ne * NEN * (D / RPI);
     const double wJ = sm.wJ;
@@ -286,6 +461,15 @@ __device__ __noinline__ void element_pass(const RveCtx& c, Smem& sm, const doubl
             }
         }
     }
+}
+
+// the element pass of the RVE's law (neo-Hookean closed forms, or the generic path)
+template <int D>
+__device__ inline void element_pass(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP, double* accA) {
+    if (c.law != 0)
+        element_pass_law<D>(c, sm, w, mode, accP, accA);
+    else
+        element_pass_nh<D>(c, sm, w, mode, accP, accA);
 }
 
 // node gather of element vectors: out[(v*D+i)*nc + col] = sum_a src[e_a(v)][(a*D+i)*nc + col]
@@ -1924,6 +2108,7 @@ __device__ inline void rve_setup(const SolveArgs& a, int rve, double* base, RveC
     c.nd = ND;
     c.phase = a.phase_pool + a.rve_phase[rve];
     c.lame = a.lame_pool + a.rve_lame[rve];
+    c.law = a.rve_law ? a.rve_law[rve] : 0;
     c.w = base + a.lay.w;
     c.wt = base + a.lay.wt;
     c.R = base + a.lay.R;
