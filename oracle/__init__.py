@@ -68,6 +68,9 @@ def _setup(L):
     L.oracle_law_sc.restype = C.c_int
     L.oracle_law_sc.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p]
+    L.oracle_set_bc.restype = None
+    L.oracle_set_bc.argtypes = [C.c_int]
+    L.oracle_get_bc.restype = C.c_int
     L.oracle_phase_by_centroid.restype = None
     L.oracle_phase_by_centroid.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_void_p]
     L.oracle_element.restype = C.c_int
@@ -139,7 +142,7 @@ def two_phase_lame(ratio, E=1.0, nu=0.3):
 
 
 def debug_system(d, n, phase, lame_, Fbar, w):
-    nf = d * (n ** d - 1)
+    nf = d * n_free_nodes(d, n)
     Rf = np.zeros(nf); K = np.zeros((nf, nf)); dw = np.zeros(nf)
     st = lib().oracle_debug_system(d, n, _p(np.ascontiguousarray(phase, np.uint8)), _p(_f64(lame_)),
                                    _p(_f64(Fbar)), _p(_f64(w)), _p(Rf), _p(K), _p(dw))
@@ -179,6 +182,38 @@ class law:
 
     def __exit__(self, *exc):
         set_law(self.prev)
+
+
+BC_PERIODIC, BC_LINEAR = 0, 1
+
+
+def set_bc(bc):
+    """Micro boundary conditions of every later oracle call (process-wide)."""
+    lib().oracle_set_bc(int(bc))
+
+
+def get_bc():
+    return lib().oracle_get_bc()
+
+
+class bc:
+    """Context manager: `with oracle.bc(oracle.BC_LINEAR): ...`."""
+
+    def __init__(self, which):
+        self.which = which
+
+    def __enter__(self):
+        self.prev = get_bc()
+        set_bc(self.which)
+        return self
+
+    def __exit__(self, *exc):
+        set_bc(self.prev)
+
+
+def n_free_nodes(d, n):
+    """Free nodes of the n^d grid under the current micro boundary conditions."""
+    return n ** d - 1 if get_bc() == BC_PERIODIC else (n - 1) ** d
 
 
 def law_sc(which, d, lam, mu, F):

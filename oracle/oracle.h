@@ -51,6 +51,15 @@ int oracle_get_law(void);
 /* S (or sigma), the material tangent (d^4) and psi of law at F; as oracle_nh_sc. */
 int oracle_law_sc(int law, int d, double lam, double mu, const double* F, double* S, double* Cmat, double* psi);
 
+/* Micro boundary conditions of every later call (process-wide; default
+ * periodic).  ORC_BC_PERIODIC: periodic fluctuation, node 0 pinned.
+ * ORC_BC_LINEAR: linear displacements u = Fbar X on the RVE boundary (KUBC, the
+ * coupling of the paper's 3D example): the fluctuation vanishes on every
+ * boundary node -- on the n^d numbering, every node with some grid index 0. */
+enum { ORC_BC_PERIODIC = 0, ORC_BC_LINEAR = 1 };
+void oracle_set_bc(int bc);
+int oracle_get_bc(void);
+
 /* Phase of every element by centroid: phase = incl_phase iff |centroid - c| < r. */
 void oracle_phase_by_centroid(int d, int n, const double* center, double r, int incl_phase,
                               int base_phase, uint8_t* phase);
@@ -93,7 +102,7 @@ int oracle_rve_solve_batch(int d, int n, int64_t B, const uint8_t* phases, const
 int oracle_linear_homogenized(int d, int n, const uint8_t* phase, const double* lame, double* Chom);
 
 /* Test hook: free residual, dense free-free tangent (natural node-major order,
- * node 0 excluded) and the skyline-LDL^T Newton step dw = -K_ff^-1 R_f. */
+ * pinned nodes excluded) and the skyline-LDL^T Newton step dw = -K_ff^-1 R_f. */
 int oracle_debug_system(int d, int n, const uint8_t* phase, const double* lame, const double* Fbar, const double* w,
                         double* Rf, double* Kff, double* dw);
 

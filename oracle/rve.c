@@ -133,6 +133,29 @@ int oracle_law_sc(int law, int d, double lam, double mu, const double* F, double
     return ORC_OK;
 }
 
+/* Micro boundary conditions (Sec. 3.2, eq. ConstraintCondition and the list of
+ * energetically consistent couplings).  Periodic: the fluctuation is periodic,
+ * partner nodes are identified and node 0 is pinned against rigid translation.
+ * Linear displacement (KUBC): u = Fbar X on the boundary, i.e. the fluctuation
+ * vanishes on every boundary node and only interior nodes are free.  On the
+ * n^d node numbering the boundary faces x_k = 0 and x_k = 1 are the nodes with
+ * grid index 0 (the periodic wrap maps x_k = 1 onto them), and both carry w = 0,
+ * so the element loop is the same for both couplings: only the set of pinned
+ * nodes changes -- every node with some grid index 0. */
+static int g_bc = ORC_BC_PERIODIC;
+
+void oracle_set_bc(int bc) { g_bc = bc; }
+int oracle_get_bc(void) { return g_bc; }
+
+static int is_pinned(int d, int n, int node) {
+    if (g_bc == ORC_BC_PERIODIC) return node == 0;
+    for (int k = 0; k < d; ++k) {
+        if (node % n == 0) return 1;
+        node /= n;
+    }
+    return 0;
+}
+
 /* first Piola-Kirchhoff stress: P = F S, or sigma itself in the fully linear case */
 static void first_piola(int d, const double* F, const double* S, double* P) {
     for (int i = 0; i < d; ++i)
@@ -320,10 +343,10 @@ int oracle_residual(int d, int n, const uint8_t* phase, const double* lame, cons
     return ORC_OK;
 }
 
-/* ------------------------------------------------------------------ periodic RVE system */
+/* ------------------------------------------------------------------ RVE system (periodic or KUBC) */
 typedef struct {
-    int d, n, nn, ne, nf;  /* nf: free dofs = d*(nn-1) */
-    int* dof;              /* dof[node*d+k] -> free index or -1 (pinned node 0) */
+    int d, n, nn, ne, nf;  /* nf: free dofs */
+    int* dof;              /* dof[node*d+k] -> free index or -1 (pinned node) */
     skyline K;
 } rve_sys;
 
@@ -332,23 +355,28 @@ static void rve_sys_free(rve_sys* r) { free(r->dof); sky_free(&r->K); }
 static int rve_sys_init(rve_sys* r, int d, int n) {
     memset(r, 0, sizeof(*r));
     r->d = d; r->n = n; r->nn = ipow(n, d); r->ne = r->nn;
-    r->nf = d * (r->nn - 1);
-    int nv = r->nn - 1; /* graph over nodes 1..nn-1 */
+    /* free nodes (not pinned) in ascending order and the graph among them */
+    int* fid = (int*)malloc(sizeof(int) * r->nn); /* node -> compact free index or -1 */
+    int nv = 0;
+    for (int node = 0; node < r->nn; ++node) fid[node] = is_pinned(d, n, node) ? -1 : nv++;
+    r->nf = d * nv;
+    int* fnode = (int*)malloc(sizeof(int) * (nv ? nv : 1));
+    for (int node = 0; node < r->nn; ++node) if (fid[node] >= 0) fnode[fid[node]] = node;
     int nb = ipow(3, d);
     int* xadj = (int*)malloc(sizeof(int) * (nv + 1));
     int* adj = (int*)calloc((size_t)nv * nb + 1, sizeof(int));
     int cnt = 0;
     for (int v = 0; v < nv; ++v) {
-        int node = v + 1, c[MAXD], t = node;
+        int node = fnode[v], c[MAXD], t = node;
         for (int k = 0; k < d; ++k) { c[k] = t % n; t /= n; }
         xadj[v] = cnt;
         for (int o = 0; o < nb; ++o) {
             int oo = o, id = 0, s = 1;
             for (int k = 0; k < d; ++k) { int dk = oo % 3 - 1; oo /= 3; id += ((c[k] + dk + n) % n) * s; s *= n; }
-            if (id == node || id == 0) continue;
+            if (id == node || fid[id] < 0) continue;
             int dup = 0;
-            for (int q = xadj[v]; q < cnt; ++q) if (adj[q] == id - 1) dup = 1;
-            if (!dup) adj[cnt++] = id - 1;
+            for (int q = xadj[v]; q < cnt; ++q) if (adj[q] == fid[id]) dup = 1;
+            if (!dup) adj[cnt++] = fid[id];
         }
     }
     xadj[nv] = cnt;
@@ -357,9 +385,8 @@ static int rve_sys_init(rve_sys* r, int d, int n) {
     int* pos = (int*)malloc(sizeof(int) * (nv ? nv : 1));
     for (int k = 0; k < nv; ++k) pos[perm[k]] = k;
     r->dof = (int*)malloc(sizeof(int) * d * r->nn);
-    for (int k = 0; k < d; ++k) r->dof[k] = -1;
-    for (int v = 0; v < nv; ++v)
-        for (int k = 0; k < d; ++k) r->dof[(v + 1) * d + k] = pos[v] * d + k;
+    for (int node = 0; node < r->nn; ++node)
+        for (int k = 0; k < d; ++k) r->dof[node * d + k] = fid[node] < 0 ? -1 : pos[fid[node]] * d + k;
     /* profile: first column of each row = smallest dof of any neighbour node */
     int* fc = (int*)malloc(sizeof(int) * (r->nf ? r->nf : 1));
     for (int v = 0; v < nv; ++v) {
@@ -367,6 +394,7 @@ static int rve_sys_init(rve_sys* r, int d, int n) {
         for (int q = xadj[v]; q < xadj[v + 1]; ++q) if (pos[adj[q]] < mn) mn = pos[adj[q]];
         for (int k = 0; k < d; ++k) fc[pos[v] * d + k] = mn * d;
     }
+    free(fid); free(fnode);
     int st = sky_alloc(&r->K, r->nf, fc);
     free(fc); free(pos); free(perm); free(adj); free(xadj);
     return st;
@@ -402,7 +430,8 @@ static int rve_assemble(rve_sys* r, const uint8_t* phase, const double* lame, co
 
 static double norm_free(const rve_sys* r, const double* R) {
     double s = 0;
-    for (int i = r->d; i < r->d * r->nn; ++i) s += R[i] * R[i];
+    for (int i = 0; i < r->d * r->nn; ++i)
+        if (r->dof[i] >= 0) s += R[i] * R[i];
     return sqrt(s);
 }
 
@@ -553,7 +582,8 @@ int oracle_rve_solve(int d, int n, const uint8_t* phase, const double* lame, con
     double* dw = (double*)malloc(sizeof(double) * (r.nf ? r.nf : 1));
     double* wt = (double*)malloc(sizeof(double) * ndof);
     if (w_io) memcpy(w, w_io, sizeof(double) * ndof);
-    for (int k = 0; k < d; ++k) w[k] = 0.0; /* pinned node */
+    for (int i = 0; i < ndof; ++i)
+        if (r.dof[i] < 0) w[i] = 0.0; /* pinned nodes */
     int status = ORC_OK, it = 0, restarted = 0;
     double r0 = 0;
     for (;;) {
@@ -574,15 +604,15 @@ int oracle_rve_solve(int d, int n, const uint8_t* phase, const double* lame, con
         if (it == o->max_iter) { status = ORC_NOCONV; break; }
         st = sky_ldlt(&r.K);
         if (st) { status = st; break; }
-        for (int node = 1; node < r.nn; ++node)
-            for (int k = 0; k < d; ++k) dw[r.dof[node * d + k]] = -R[node * d + k];
+        for (int i = 0; i < ndof; ++i)
+            if (r.dof[i] >= 0) dw[r.dof[i]] = -R[i];
         sky_solve(&r.K, dw);
         double alpha = 1.0;
         int ok = 0;
         for (int bt = 0; bt <= o->max_backtrack; ++bt) {
             memcpy(wt, w, sizeof(double) * ndof);
-            for (int node = 1; node < r.nn; ++node)
-                for (int k = 0; k < d; ++k) wt[node * d + k] += alpha * dw[r.dof[node * d + k]];
+            for (int i = 0; i < ndof; ++i)
+                if (r.dof[i] >= 0) wt[i] += alpha * dw[r.dof[i]];
             if (all_J_positive(&r, phase, lame, Fbar, wt)) { ok = 1; break; }
             alpha *= 0.5;
         }
@@ -758,15 +788,15 @@ int oracle__rve_one_step(int d, int n, const uint8_t* phase, const double* lame,
     if (!status && rn > o->atol) {
         status = sky_ldlt(&r.K);
         if (!status) {
-            for (int node = 1; node < r.nn; ++node)
-                for (int k = 0; k < d; ++k) dw[r.dof[node * d + k]] = -R[node * d + k];
+            for (int i = 0; i < ndof; ++i)
+                if (r.dof[i] >= 0) dw[r.dof[i]] = -R[i];
             sky_solve(&r.K, dw);
             double alpha = 1.0;
             int ok = 0;
             for (int bt = 0; bt <= o->max_backtrack; ++bt) {
                 memcpy(wt, w_io, sizeof(double) * ndof);
-                for (int node = 1; node < r.nn; ++node)
-                    for (int k = 0; k < d; ++k) wt[node * d + k] += alpha * dw[r.dof[node * d + k]];
+                for (int i = 0; i < ndof; ++i)
+                    if (r.dof[i] >= 0) wt[i] += alpha * dw[r.dof[i]];
                 if (all_J_positive(&r, phase, lame, Fbar, wt)) { ok = 1; break; }
                 alpha *= 0.5;
             }
@@ -787,7 +817,7 @@ int oracle__rve_one_step(int d, int n, const uint8_t* phase, const double* lame,
 }
 
 /* Test hook: free residual R_f, dense free-free tangent K_ff (both in natural
- * dof order: node-major, node 0 excluded) and the Newton step dw = -K_ff^-1 R_f
+ * dof order: node-major, pinned nodes excluded) and the Newton step dw = -K_ff^-1 R_f
  * computed by the skyline LDL^T.  Small meshes only (K_ff is dense). */
 int oracle_debug_system(int d, int n, const uint8_t* phase, const double* lame, const double* Fbar, const double* w,
                         double* Rf, double* Kff, double* dw) {
@@ -795,27 +825,32 @@ int oracle_debug_system(int d, int n, const uint8_t* phase, const double* lame, 
     if (rve_sys_init(&r, d, n)) return ORC_SINGULAR;
     int ndof = d * r.nn, nf = r.nf;
     double* R = (double*)malloc(sizeof(double) * ndof);
+    int* nat = (int*)malloc(sizeof(int) * ndof); /* natural index among the free dofs */
+    for (int a = 0, q = 0; a < ndof; ++a) nat[a] = r.dof[a] >= 0 ? q++ : -1;
     int st = rve_assemble(&r, phase, lame, Fbar, w, R, 1);
     if (!st) {
-        for (int a = d; a < ndof; ++a) {
-            Rf[a - d] = R[a];
-            for (int b = d; b < ndof; ++b) {
+        for (int a = 0; a < ndof; ++a) {
+            if (nat[a] < 0) continue;
+            Rf[nat[a]] = R[a];
+            for (int b = 0; b < ndof; ++b) {
+                if (nat[b] < 0) continue;
                 int ga = r.dof[a], gb = r.dof[b];
                 int i = ga > gb ? ga : gb, j = ga > gb ? gb : ga;
                 double v = 0;
                 if (j >= r.K.fc[i]) v = r.K.val[r.K.ptr[i] + (j - r.K.fc[i])];
-                Kff[(size_t)(a - d) * nf + (b - d)] = v;
+                Kff[(size_t)nat[a] * nf + nat[b]] = v;
             }
         }
         st = sky_ldlt(&r.K);
         if (!st) {
             double* x = (double*)malloc(sizeof(double) * (nf ? nf : 1));
-            for (int a = d; a < ndof; ++a) x[r.dof[a]] = -R[a];
+            for (int a = 0; a < ndof; ++a) if (nat[a] >= 0) x[r.dof[a]] = -R[a];
             sky_solve(&r.K, x);
-            for (int a = d; a < ndof; ++a) dw[a - d] = x[r.dof[a]];
+            for (int a = 0; a < ndof; ++a) if (nat[a] >= 0) dw[nat[a]] = x[r.dof[a]];
             free(x);
         }
     }
+    free(nat);
     free(R);
     rve_sys_free(&r);
     return st;
