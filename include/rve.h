@@ -81,6 +81,14 @@ int rve_lame(double E, double nu, double* lambda_out, double* mu_out);
  *              (small strain, sigma = lambda tr(eps) 1 + 2 mu eps takes the place
  *              of P; A is the constant elasticity tensor).  The J > 0 guard of the
  *              Newton update applies to every law.
+ *   bc         micro boundary conditions (RVE_BC_*; Sec. 3.2, the energetically
+ *              consistent couplings): periodic fluctuations (default, 0; node 0
+ *              pinned against translation), or linear displacements u = Fbar X
+ *              on the cell boundary (KUBC, the coupling of the paper's 3D
+ *              example): the fluctuation vanishes on every boundary node, so
+ *              only the (n-1)^d interior nodes are free.  Fluctuations keep the
+ *              n^d node layout either way (boundary nodes -- every node with
+ *              some grid index 0 -- hold 0).
  * The symbolic factorization plan for (ndim, n) is built on first use and shared
  * by every mesh of that size. */
 typedef struct {
@@ -93,7 +101,11 @@ typedef struct {
     double incl_radius;
     int32_t incl_phase;
     int32_t law;
+    int32_t bc;
 } rve_mesh_desc;
+
+#define RVE_BC_PERIODIC 0
+#define RVE_BC_LINEAR 1
 
 #define RVE_LAW_NEOHOOKE 0
 #define RVE_LAW_SVK 1

@@ -5,7 +5,8 @@ import numpy as np
 from . import rve
 
 
-def build_batch(d, n_list, radius_list, ratio_list, nu=0.3, E=1.0, center=None, law=rve.LAW_NEOHOOKE):
+def build_batch(d, n_list, radius_list, ratio_list, nu=0.3, E=1.0, center=None, law=rve.LAW_NEOHOOKE,
+                bc=rve.BC_PERIODIC):
     """One mesh per distinct (n, radius, ratio); returns (Batch, meshes)."""
     cache = {}
     meshes = []
@@ -13,7 +14,7 @@ def build_batch(d, n_list, radius_list, ratio_list, nu=0.3, E=1.0, center=None, 
         key = (int(n), float(r), float(q))
         if key not in cache:
             cache[key] = rve.Mesh(d, int(n), rve.two_phase_lame(float(q), E=E, nu=nu), radius=float(r),
-                                  center=center, law=law)
+                                  center=center, law=law, bc=bc)
         meshes.append(cache[key])
     return rve.Batch(meshes), meshes
 

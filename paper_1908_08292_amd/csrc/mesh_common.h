@@ -45,4 +45,16 @@ FEHMM_HD int element_of_node(int d, int n, int v, int a) {
     return id;
 }
 
+// the nodes whose fluctuation is held at zero: node 0 under periodic coupling
+// (bc 0); under linear displacements (bc 1, KUBC) the boundary, i.e. on the n^d
+// numbering every node with some grid index 0 (the faces x_k = 1 wrap onto them)
+FEHMM_HD bool plan_pinned(int bc, int d, int n, int v) {
+    if (bc == 0) return v == 0;
+    for (int k = 0; k < d; ++k) {
+        if (v % n == 0) return true;
+        v /= n;
+    }
+    return false;
+}
+
 }  // namespace fehmm

@@ -173,25 +173,34 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
     if (!(d == 2 || d == 3) || n < 2) throw std::runtime_error("unsupported mesh size");
     if (prm.leaf < 0 || prm.wave_max_m < 0 || prm.wave_max_m > kWaveFrontMaxM)
         throw std::runtime_error("plan parameters out of range");
+    if (prm.bc != 0 && prm.bc != 1) throw std::runtime_error("unknown micro boundary conditions");
     PlanHost P;
     P.d = d;
     P.n = n;
+    P.bc = prm.bc;
     int nn = 1;
     for (int k = 0; k < d; ++k) nn *= n;
     P.nnode = nn;
     P.nelem = nn;
-    P.nfree = d * (nn - 1);
+    std::vector<char> pinned(nn);
+    int nfree_nodes = 0;
+    for (int v = 0; v < nn; ++v) {
+        pinned[v] = plan_pinned(prm.bc, d, n, v) ? 1 : 0;
+        nfree_nodes += pinned[v] ? 0 : 1;
+    }
+    if (nfree_nodes == 0) throw std::runtime_error("no free node");
+    P.nfree = d * nfree_nodes;
 
     NDBuilder nd{d, n, prm.leaf > 0 ? prm.leaf : (d == 2 ? 16 : 27), {}};
     Box root;
     for (int k = 0; k < 3; ++k) { root.lo[k] = 0; root.hi[k] = (k < d) ? n : 1; root.per[k] = k < d; }
     nd.rec(root);
 
-    // drop the pinned node 0
+    // drop the pinned nodes
     std::vector<std::vector<int>> sup0;
     for (auto& s : nd.sup) {
         std::vector<int> t;
-        for (int v : s) if (v != 0) t.push_back(v);
+        for (int v : s) if (!pinned[v]) t.push_back(v);
         if (!t.empty()) sup0.push_back(t);
     }
     // the supernodal tree of the dissection order, then a depth-first postorder
@@ -206,12 +215,13 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
         for (int v : sup[s]) { pos[v] = cur++; owner[v] = s; }
         endp[s] = cur;
     }
-    if (cur != nn - 1) throw std::runtime_error("nested dissection lost nodes");
+    if (cur != nfree_nodes) throw std::runtime_error("nested dissection lost nodes");
 
     auto neighbours = [&](int v) { return periodic_neighbours(d, n, v); };
 
-    std::vector<int> node_at(nn - 1);
-    for (int v = 1; v < nn; ++v) node_at[pos[v]] = v;
+    std::vector<int> node_at(nfree_nodes);
+    for (int v = 0; v < nn; ++v)
+        if (!pinned[v]) node_at[pos[v]] = v;
     auto node_at_pos = [&](int q) { return node_at[q]; };
 
     // symbolic factorization over supernodes (structures kept as sorted positions)
@@ -221,7 +231,7 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
     for (int s = 0; s < ns; ++s) {
         for (int v : sup[s])
             for (int u : neighbours(v))
-                if (u != 0 && pos[u] >= endp[s]) st[s].insert(pos[u]);
+                if (!pinned[u] && pos[u] >= endp[s]) st[s].insert(pos[u]);
         for (int c : kids[s])
             for (int q : st[c])
                 if (q >= endp[s]) st[s].insert(q);
@@ -266,7 +276,7 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
         for (int ia = 0; ia < pn; ++ia) {
             int a = fnodes[ia];
             for (int b : neighbours(a)) {
-                if (b == 0 || pos[b] < pos[a]) continue;
+                if (pinned[b] || pos[b] < pos[a]) continue;
                 KPair kp;
                 kp.row_node = loc.at(b);
                 kp.col_node = ia;

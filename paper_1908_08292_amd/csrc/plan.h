@@ -48,7 +48,7 @@ struct KContrib {
 };
 
 struct PlanHost {
-    int d = 0, n = 0;
+    int d = 0, n = 0, bc = 0;
     int nnode = 0, nelem = 0, nfree = 0;
     std::vector<FrontHost> fronts;     // postorder (children before parents)
     std::vector<int32_t> rows, relind, children;
@@ -90,7 +90,9 @@ constexpr int kStepFronts = 4;  // fronts per workgroup-front step at most
 struct PlanParams {
     int leaf = 0;        // largest leaf box of the nested dissection (nodes); 0: 16 in 2D, 27 in 3D
     int wave_max_m = kWaveFrontMaxM;  // largest front factored by one wave (0: none)
+    int bc = 0;          // 0 periodic (node 0 pinned), 1 linear displacements (every node with a grid index 0 pinned)
 };
+
 
 PlanHost build_plan(int d, int n, const PlanParams& prm = PlanParams{});
 

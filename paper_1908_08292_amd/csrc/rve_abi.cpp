@@ -56,7 +56,7 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 // ---------------------------------------------------------------- plan cache
-using PlanKey = std::tuple<int, int, int, int>;  // d, n, leaf, wave_max_m
+using PlanKey = std::tuple<int, int, int, int, int>;  // d, n, leaf, wave_max_m, bc
 
 struct PlanEntry {
     PlanKey key;
@@ -118,11 +118,12 @@ void free_plan_dev(PlanEntry& e) {
     e.d_fronts = nullptr;
 }
 
-// the plan of (d, n) under the current tuning (default parameters if untuned)
-int get_plan(int d, int n, PlanEntry** out) {
+// the plan of (d, n) under the current tuning for micro boundary conditions bc
+int get_plan(int d, int n, PlanEntry** out, int bc = RVE_BC_PERIODIC) {
     std::lock_guard<std::mutex> lk(g_mu);
-    const PlanParams prm = params_for(d, n);
-    const PlanKey key(d, n, prm.leaf, prm.wave_max_m);
+    PlanParams prm = params_for(d, n);
+    prm.bc = bc;
+    const PlanKey key(d, n, prm.leaf, prm.wave_max_m, bc);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         *out = it->second.get();
@@ -165,6 +166,7 @@ int plan_device(PlanEntry* e) {
                      (int32_t)P.wave_hbeg.size() - 1, (int32_t)P.wave_slice, e->d_wg_steps,
                      (int32_t)(P.wg_steps.size() / kStepFronts)};
     if (P.wave_hbeg.empty()) e->dev.nwave_h = 0;
+    e->dev.bc = P.bc;
     // whole fronts in LDS when the largest packed front plus its rhs rows fit;
     // the front region also hosts the FP64 scratch of the triangular solves
     // (m d^2 + 3 m doubles)
@@ -199,6 +201,7 @@ struct rve_mesh_s {
     PlanEntry* plan = nullptr;
     double mu_max = 0;
     int law = RVE_LAW_NEOHOOKE;
+    int bc = RVE_BC_PERIODIC;
     bool alive = true;
 };
 
@@ -295,8 +298,11 @@ int rve_mesh_create(const rve_mesh_desc* d, rve_mesh* out) {
     }
     if (d->law < RVE_LAW_NEOHOOKE || d->law > RVE_LAW_LINEAR)
         return fail(RVE_EINVAL, "rve_mesh_create: unknown constitutive law");
+    if (d->bc != RVE_BC_PERIODIC && d->bc != RVE_BC_LINEAR)
+        return fail(RVE_EINVAL, "rve_mesh_create: unknown micro boundary conditions");
     auto m = std::make_unique<rve_mesh_s>();
     m->law = d->law;
+    m->bc = d->bc;
     m->d = d->ndim;
     m->n = d->n;
     m->nphase = d->nphase;
@@ -325,7 +331,7 @@ int rve_mesh_create(const rve_mesh_desc* d, rve_mesh* out) {
         }
     }
     for (int q = 0; q < m->nphase; ++q) m->mu_max = std::max(m->mu_max, m->lame[2 * q + 1]);
-    int st = get_plan(m->d, m->n, &m->plan);
+    int st = get_plan(m->d, m->n, &m->plan, m->bc);
     if (st) return st;
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -809,6 +815,7 @@ int rve_autotune(rve_mesh m, const double* F, int64_t nF, const rve_opts* o, rve
         try {
             PlanParams pp;
             pp.leaf = leaf;
+            pp.bc = m->bc;
             lds = build_plan(d, n, pp).lds_path;
         } catch (const std::exception& ex) {
             err = fail(RVE_EINVAL, std::string("rve_autotune: ") + ex.what());
@@ -826,6 +833,7 @@ int rve_autotune(rve_mesh m, const double* F, int64_t nF, const rve_opts* o, rve
                 md.lame = m->lame.data();
                 md.phase = m->phase.data();
                 md.law = m->law;
+                md.bc = m->bc;
                 rve_mesh cm = nullptr;
                 if ((err = rve_mesh_create(&md, &cm))) break;
                 std::vector<rve_mesh> ms((size_t)nF, cm);

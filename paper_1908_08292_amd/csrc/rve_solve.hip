@@ -149,6 +149,23 @@ struct RveCtx {
     double* S;
 };
 
+// node v holds w = 0: node 0 under periodic coupling, every boundary node
+// (some grid index 0) under linear displacements
+__device__ inline bool is_pinned(const DevPlan& pl, int v) { return plan_pinned(pl.bc, pl.d, pl.n, v); }
+
+// zero x at the pinned nodes' dofs (node-major [dof][nc]): the triangular
+// solves write the free rows only
+template <int D>
+__device__ inline void zero_pinned(const RveCtx& c, double* x, int nc) {
+    const DevPlan& pl = *c.plan;
+    if (pl.bc == 0) {
+        for (int t = threadIdx.x; t < D * nc; t += NT) x[t] = 0.0;
+        return;
+    }
+    for (int t = threadIdx.x; t < c.nn * D * nc; t += NT)
+        if (is_pinned(pl, t / (D * nc))) x[t] = 0.0;
+}
+
 // P and A = dP/dF (row-major [(i*D+J)*D*D + k*D+L]) of the St. Venant-Kirchhoff
 // law (law 1) or of the fully linear law (law 2) at F; plane strain in 2D
 template <int D>
@@ -1112,7 +1129,7 @@ template <int D, int NRHS, typename T>
 __device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& sm, double* xo) {
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int t = tid; t < D * NRHS; t += NT) xo[t] = 0.0;  // pinned node
+    zero_pinned<D>(c, xo, NRHS);
     __syncthreads();
     double* const cL = uni(c.L);
     xo = uni(xo);
@@ -1882,7 +1899,7 @@ __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* r
                                          int wave_slice) {
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, wave = tid >> 6;
-    for (int t = tid; t < D * NRHS; t += NT) x[t] = 0.0;  // pinned node
+    zero_pinned<D>(c, x, NRHS);
     // large fronts (the top of the tree) in the plan's steps, then the small
     // subtrees wave by wave
     for (int st = pl.nwg_steps - 1; st >= 0; --st) {
@@ -2063,7 +2080,8 @@ __device__ void residual_ke(const RveCtx& c, const double* b, const double* x, d
         double acc[NRHS];
 #pragma unroll
         for (int q = 0; q < NRHS; ++q) acc[q] = 0.0;
-        if (v != 0) {
+        const bool pin = is_pinned(*c.plan, v);
+        if (!pin) {
 #pragma unroll
             for (int a = 0; a < NEN; ++a) {
                 const int e = element_of_node(D, c.n, v, a);
@@ -2082,14 +2100,15 @@ __device__ void residual_ke(const RveCtx& c, const double* b, const double* x, d
             }
         }
 #pragma unroll
-        for (int q = 0; q < NRHS; ++q) out[(int64_t)vi * NRHS + q] = (v != 0) ? b[(int64_t)vi * NRHS + q] - acc[q] : 0.0;
+        for (int q = 0; q < NRHS; ++q) out[(int64_t)vi * NRHS + q] = pin ? 0.0 : b[(int64_t)vi * NRHS + q] - acc[q];
     }
 }
 
 template <int D>
 __device__ double free_norm2(const RveCtx& c, Smem& sm, const double* R) {
     double v[1] = {0.0};
-    for (int t = D + threadIdx.x; t < c.nn * D; t += NT) v[0] += R[t] * R[t];
+    for (int t = threadIdx.x; t < c.nn * D; t += NT)
+        if (!is_pinned(*c.plan, t / D)) v[0] += R[t] * R[t];
     block_sum<1>(v, sm);
     return sm.outv[0];
 }
@@ -2188,7 +2207,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
 #pragma unroll
         for (int q = 0; q < D2; ++q) finite_in = finite_in && isfinite(sm.Fbar[q]);
         double* wst = a.wstate ? a.wstate + a.state_off[rve] : nullptr;
-        for (int t = threadIdx.x; t < ndof; t += NT) c.w[t] = (wst && t >= D) ? wst[t] : 0.0;
+        for (int t = threadIdx.x; t < ndof; t += NT) c.w[t] = (wst && !is_pinned(*c.plan, t / D)) ? wst[t] : 0.0;
         __syncthreads();
         int status = 0, it = 0;
         bool capped = false, restarted = false;
@@ -2326,7 +2345,8 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                     double acc[D2 * D2];
 #pragma unroll
                     for (int q = 0; q < D2 * D2; ++q) acc[q] = 0;
-                    for (int t = D + threadIdx.x; t < ndof; t += NT) {
+                    for (int t = threadIdx.x; t < ndof; t += NT) {
+                        if (is_pinned(*c.plan, t / D)) continue;
 #pragma unroll
                         for (int g = 0; g < D2; ++g)
 #pragma unroll
@@ -2400,7 +2420,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_assembly_kernel(SolveArgs a)
         rve_setup<D>(a, rve, base, c, sm);
         const int ndof = c.nn * D;
         const double* wst = a.wstate ? a.wstate + a.state_off[rve] : nullptr;
-        for (int t = threadIdx.x; t < ndof; t += NT) c.w[t] = (wst && t >= D) ? wst[t] : 0.0;
+        for (int t = threadIdx.x; t < ndof; t += NT) c.w[t] = (wst && !is_pinned(*c.plan, t / D)) ? wst[t] : 0.0;
         __syncthreads();
         element_pass<D>(c, sm, c.w, 0, nullptr, nullptr);
         __syncthreads();

@@ -28,6 +28,7 @@ struct DevPlan {
     int32_t wave_slice;    // doubles per wave slice
     const int32_t* wg_steps;  // [nwg_steps][kStepFronts] workgroup-front steps (-1 padded)
     int32_t nwg_steps;
+    int32_t bc;               // micro boundary conditions: 0 periodic, 1 linear displacements
 };
 
 // offsets (in doubles) of the per-slot workspace regions
