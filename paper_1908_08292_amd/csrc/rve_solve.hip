@@ -1394,8 +1394,10 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
         // trailing lower triangle -= L D L^T (MFMA), two independent tiles in flight
         const int nT = nRT;
         const int ntile = nT * (nT + 1) / 2;
+        // (MFMA of the factor type: v_mfma_f64_16x16x4 or v_mfma_f32_16x16x4)
+        typedef Mfma16<T> M;
         for (int t0 = 0; t0 < ntile; t0 += 2) {
-            dbl4 acc[2];
+            typename M::V acc[2];
             int Ii[2], Jj[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -1403,34 +1405,33 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
                 while (rem > I) { rem -= I + 1; ++I; }
                 Ii[u] = I;
                 Jj[u] = rem;
-                acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+                acc[u] = M::zero();
             }
             // operands from clamped addresses inside the front (column K and row
             // m - 1 stand in past the block, the front or the last tile) times 0/1
             // masks: every read of both tiles issues without branches
-            double av[4][2], bv[4][2];
+            T av[4][2], bv[4][2];
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
                 const int kk = 4 * ks + (lane >> 4);
                 const int kc = kk < kb ? K + kk : K;
                 const int base = cpk(kc, m) - kc;
-                const double dk = F[base + kc];
+                const T dk = F[base + kc];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     const int ra = R0 + 16 * Ii[u] + (lane & 15), rb = R0 + 16 * Jj[u] + (lane & 15);
                     const bool live = (t0 + u < ntile) && kk < kb;
-                    const double ma = (live && ra < m) ? 1.0 : 0.0, mb = (live && rb < m) ? 1.0 : 0.0;
-                    av[ks][u] = (double)F[base + min(ra, m - 1)] * dk * ma;
-                    bv[ks][u] = (double)F[base + min(rb, m - 1)] * mb;
+                    const T ma = (live && ra < m) ? T(1) : T(0), mb = (live && rb < m) ? T(1) : T(0);
+                    av[ks][u] = F[base + min(ra, m - 1)] * dk * ma;
+                    bv[ks][u] = F[base + min(rb, m - 1)] * mb;
                 }
             }
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
-                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][u], bv[ks][u], acc[u], 0, 0, 0);
+                for (int u = 0; u < 2; ++u) acc[u] = M::mma(av[ks][u], bv[ks][u], acc[u]);
             // the tiles' targets are distinct: all eight read (clamped), then written
-            double o[2][4];
+            T o[2][4];
             int bs[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -1438,7 +1439,7 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
                 bs[u] = cpk(ccl, m) - ccl;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int rr = R0 + 16 * Ii[u] + (lane >> 4) + 4 * v;
+                    const int rr = R0 + 16 * Ii[u] + M::row(lane, v);
                     o[u][v] = F[bs[u] + min(max(rr, ccl), m - 1)];
                 }
             }
@@ -1447,7 +1448,7 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
                 const int cc = R0 + 16 * Jj[u] + (lane & 15);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int rr = R0 + 16 * Ii[u] + (lane >> 4) + 4 * v;
+                    const int rr = R0 + 16 * Ii[u] + M::row(lane, v);
                     if (t0 + u < ntile && cc < m && rr < m && rr >= cc) F[bs[u] + rr] = o[u][v] - acc[u][v];
                 }
             }
@@ -1597,32 +1598,34 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
             // operands from clamped addresses inside the front (column K and row
             // m - 1 stand in past the block or the front) times 0/1 masks, so all
             // twelve reads issue together without branches
-            double a[4], bb[4];
+            // (MFMA of the factor type: v_mfma_f64_16x16x4 or v_mfma_f32_16x16x4)
+            typedef Mfma16<T> M;
+            T a[4], bb[4];
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
                 const int kk = 4 * ks + (lane >> 4);
                 const int kc = kk < kb ? K + kk : K;
                 const int base = cpk(kc, m) - kc;
-                const double dk = F[base + kc];
-                const double ma = (kk < kb && ra < m) ? 1.0 : 0.0, mb = (kk < kb && rb < m) ? 1.0 : 0.0;
-                a[ks] = (double)F[base + min(ra, m - 1)] * dk * ma;
-                bb[ks] = (double)F[base + min(rb, m - 1)] * mb;
+                const T dk = F[base + kc];
+                const T ma = (kk < kb && ra < m) ? T(1) : T(0), mb = (kk < kb && rb < m) ? T(1) : T(0);
+                a[ks] = F[base + min(ra, m - 1)] * dk * ma;
+                bb[ks] = F[base + min(rb, m - 1)] * mb;
             }
-            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+            typename M::V acc = M::zero();
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], bb[ks], acc, 0, 0, 0);
+            for (int ks = 0; ks < 4; ++ks) acc = M::mma(a[ks], bb[ks], acc);
             // the tile's targets are distinct: all four read (clamped), then written
             const int cc = T0 + 16 * J + (lane & 15), ccl = min(cc, m - 1);
             const int base = cpk(ccl, m) - ccl;
-            double o[4];
+            T o[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int rr = T0 + 16 * I + (lane >> 4) + 4 * v;
+                const int rr = T0 + 16 * I + M::row(lane, v);
                 o[v] = F[base + min(max(rr, ccl), m - 1)];
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int rr = T0 + 16 * I + (lane >> 4) + 4 * v;
+                const int rr = T0 + 16 * I + M::row(lane, v);
                 if (cc < m && rr < m && rr >= cc) F[base + rr] = o[v] - acc[v];
             }
         }
