@@ -68,6 +68,9 @@ def _setup(L):
     L.oracle_law_sc.restype = C.c_int
     L.oracle_law_sc.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p]
+    L.oracle_set_element.restype = None
+    L.oracle_set_element.argtypes = [C.c_int]
+    L.oracle_get_element.restype = C.c_int
     L.oracle_set_bc.restype = None
     L.oracle_set_bc.argtypes = [C.c_int]
     L.oracle_get_bc.restype = C.c_int
@@ -110,6 +113,19 @@ def _setup(L):
     L.oracle_macro_get_qp.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.oracle_macro_get_nodes.restype = None
     L.oracle_macro_get_nodes.argtypes = [C.c_void_p, C.c_void_p]
+    L.oracle_macro_nelem.restype = C.c_int
+    L.oracle_macro_nelem.argtypes = [C.c_void_p]
+    L.oracle_macro_get_conn.restype = None
+    L.oracle_macro_get_conn.argtypes = [C.c_void_p, C.c_void_p]
+    L.oracle_macro_get_state.restype = None
+    L.oracle_macro_get_state.argtypes = [C.c_void_p, C.c_void_p]
+    L.oracle_macro_set_qp.restype = None
+    L.oracle_macro_set_qp.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.oracle_macro_element_stiffness.restype = C.c_int
+    L.oracle_macro_element_stiffness.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    L.oracle_rve_transfer_states.restype = C.c_int
+    L.oracle_rve_transfer_states.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                             C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
 
 
 def _p(a):
@@ -211,6 +227,33 @@ class bc:
         set_bc(self.prev)
 
 
+ELEM_Q1, ELEM_P1 = 0, 1
+
+
+def set_element(kind):
+    """Micro element kind of every later oracle call (process-wide)."""
+    lib().oracle_set_element(int(kind))
+
+
+def get_element():
+    return lib().oracle_get_element()
+
+
+class element_kind:
+    """Context manager: `with oracle.element_kind(oracle.ELEM_P1): ...`."""
+
+    def __init__(self, which):
+        self.which = which
+
+    def __enter__(self):
+        self.prev = get_element()
+        set_element(self.which)
+        return self
+
+    def __exit__(self, *exc):
+        set_element(self.prev)
+
+
 def n_free_nodes(d, n):
     """Free nodes of the n^d grid under the current micro boundary conditions."""
     return n ** d - 1 if get_bc() == BC_PERIODIC else (n - 1) ** d
@@ -284,6 +327,18 @@ def rve_solve_batch(d, n, phases, lame, F, w=None, opts=None, nthreads=0, **kw):
     return dict(status=status, P=P, A=A, iters=iters, w=wv)
 
 
+def transfer_states(d, n, phase, lame_, Fbar, w, G, t=None):
+    """T^T K T [nstate, nstate] for prescribed gradient states G [nstate, d, d]
+    (translations t [nstate, d] or None) at the micro state (Fbar, w)."""
+    G = _f64(G).reshape(-1, d * d)
+    ns = G.shape[0]
+    kT = np.zeros((ns, ns))
+    tt = None if t is None else _f64(t).reshape(ns, d)
+    st = lib().oracle_rve_transfer_states(d, n, _p(np.ascontiguousarray(phase, np.uint8)), _p(_f64(lame_)),
+                                          _p(_f64(Fbar)), _p(_f64(w)), ns, _p(G), _p(tt), _p(kT))
+    return st, kT
+
+
 def linear_homogenized(d, n, phase, lame):
     Ch = np.zeros((d * d, d * d))
     st = lib().oracle_linear_homogenized(d, n, _p(np.ascontiguousarray(phase, np.uint8)), _p(_f64(lame)), _p(Ch))
@@ -325,6 +380,31 @@ class Macro:
         F = np.zeros((self.nqp, 2, 2)); P = np.zeros((self.nqp, 2, 2)); A = np.zeros((self.nqp, 4, 4))
         lib().oracle_macro_get_qp(self.h, _p(F), _p(P), _p(A))
         return F, P, A
+
+    def nelem(self):
+        return lib().oracle_macro_nelem(self.h)
+
+    def conn(self):
+        c = np.zeros((self.nelem(), 4), np.int32)
+        lib().oracle_macro_get_conn(self.h, _p(c))
+        return c
+
+    def state(self):
+        w = np.zeros((self.nqp, 2 * self.desc.n ** 2))
+        lib().oracle_macro_get_state(self.h, _p(w))
+        return w
+
+    def set_qp(self, F=None, P=None, A=None, w=None):
+        lib().oracle_macro_set_qp(self.h, *[None if x is None else _p(_f64(x)) for x in (F, P, A, w)])
+
+    def element_stiffness(self, e, literal=True):
+        """[8, 8] macro element stiffness at the stored micro states: the literal
+        T^T K T transfer of the unit nodal states, or B^T Abar B."""
+        k = np.zeros((8, 8))
+        st = lib().oracle_macro_element_stiffness(self.h, int(e), 1 if literal else 0, _p(k))
+        if st:
+            raise RuntimeError(f"element stiffness failed: {st}")
+        return k
 
     def close(self):
         if self.h:

@@ -23,6 +23,8 @@
 
 int oracle__rve_one_step(int d, int n, const uint8_t* phase, const double* lame, const double* Fbar, double* w,
                          const oracle_opts* o, double* P, double* A, double* rnorm);
+int oracle_rve_transfer_states(int d, int n, const uint8_t* phase, const double* lame, const double* Fbar,
+                               const double* w, int nstate, const double* G, const double* tvec, double* kT);
 
 struct oracle_macro {
     oracle_macro_desc desc;
@@ -296,4 +298,65 @@ int oracle_macro_step(oracle_macro* m, int step, int* macro_iters, double* res_h
     if (macro_iters) *macro_iters = it;
     if (micro_iters) *micro_iters = mic;
     return status;
+}
+
+/* Macro element stiffness of element e at the stored micro states, two ways.
+ * Literal (eqs. k-mac-element-5..7): at each Gauss point the 4 x 2 unit nodal
+ * displacement states (I, x_i) of the element, linearized at the point
+ * (eq. linearization-uH: translation N_I(x_qp) e_i, gradient e_i (x) grad N_I),
+ * drive the micro problem; k = sum_qp omega_qp T^T K T / |K_delta|.
+ * Condensed: k = sum_qp omega_qp B^T Abar B with the stored Abar of the point.
+ * Both [8][8] in the element's (node, direction) order. */
+static double q1_N(int a, int p) {
+    static const int sx[4] = {-1, 1, 1, -1}, sy[4] = {-1, -1, 1, 1};
+    double g = 1.0 / sqrt(3.0), xi = sx[p] * g, eta = sy[p] * g;
+    return 0.25 * (1 + sx[a] * xi) * (1 + sy[a] * eta);
+}
+
+int oracle_macro_element_stiffness(const oracle_macro* m, int e, int literal, double* k) {
+    if (e < 0 || e >= m->nelem) return -1;
+    memset(k, 0, sizeof(double) * 64);
+    for (int p = 0; p < 4; ++p) {
+        const int q = 4 * e + p;
+        if (literal) {
+            double G[8 * 4], t[8 * 2], kT[64];
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 2; ++i) {
+                    const int j = 2 * a + i;
+                    for (int c = 0; c < 4; ++c) G[j * 4 + c] = 0.0;
+                    for (int J = 0; J < 2; ++J) G[j * 4 + i * 2 + J] = m->dN[p][a][J];
+                    t[j * 2 + 0] = i == 0 ? q1_N(a, p) : 0.0;
+                    t[j * 2 + 1] = i == 1 ? q1_N(a, p) : 0.0;
+                }
+            int st = oracle_rve_transfer_states(2, m->desc.n, m->desc.phase, m->desc.lame, m->Fq + 4 * q,
+                                                m->wq + (size_t)q * m->nw, 8, G, t, kT);
+            if (st) return st;
+            for (int c = 0; c < 64; ++c) k[c] += kT[c] * m->wdet;
+        } else {
+            const double* A = m->Aq + 16 * q;
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 2; ++i)
+                    for (int b = 0; b < 4; ++b)
+                        for (int kk = 0; kk < 2; ++kk) {
+                            double v = 0;
+                            for (int J = 0; J < 2; ++J)
+                                for (int L = 0; L < 2; ++L)
+                                    v += m->dN[p][a][J] * A[(i * 2 + J) * 4 + kk * 2 + L] * m->dN[p][b][L];
+                            k[(2 * a + i) * 8 + 2 * b + kk] += v * m->wdet;
+                        }
+        }
+    }
+    return 0;
+}
+
+int oracle_macro_nelem(const oracle_macro* m) { return m->nelem; }
+void oracle_macro_get_conn(const oracle_macro* m, int* conn) { memcpy(conn, m->conn, sizeof(int) * 4 * m->nelem); }
+void oracle_macro_get_state(const oracle_macro* m, double* w) {
+    memcpy(w, m->wq, sizeof(double) * (size_t)m->nqp * m->nw);
+}
+void oracle_macro_set_qp(oracle_macro* m, const double* F, const double* P, const double* A, const double* w) {
+    if (F) memcpy(m->Fq, F, sizeof(double) * 4 * m->nqp);
+    if (P) memcpy(m->Pq, P, sizeof(double) * 4 * m->nqp);
+    if (A) memcpy(m->Aq, A, sizeof(double) * 16 * m->nqp);
+    if (w) memcpy(m->wq, w, sizeof(double) * (size_t)m->nqp * m->nw);
 }

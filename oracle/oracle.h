@@ -60,6 +60,15 @@ enum { ORC_BC_PERIODIC = 0, ORC_BC_LINEAR = 1 };
 void oracle_set_bc(int bc);
 int oracle_get_bc(void);
 
+/* Micro element kind of every later call (process-wide; default Q1).
+ * ORC_ELEM_P1: the paper's linear simplices -- each grid cell split into d!
+ * simplices along its (0..0)-(1..1) diagonal (Kuhn), one integration point each
+ * (the gradient is constant); the cell's phase, node numbering and unknowns are
+ * unchanged. */
+enum { ORC_ELEM_Q1 = 0, ORC_ELEM_P1 = 1 };
+void oracle_set_element(int kind);
+int oracle_get_element(void);
+
 /* Phase of every element by centroid: phase = incl_phase iff |centroid - c| < r. */
 void oracle_phase_by_centroid(int d, int n, const double* center, double r, int incl_phase,
                               int base_phase, uint8_t* phase);
@@ -139,6 +148,25 @@ int oracle_macro_step(oracle_macro* m, int step, int* macro_iters, double* res_h
 void oracle_macro_get_u(const oracle_macro* m, double* u);
 void oracle_macro_get_qp(const oracle_macro* m, double* F, double* P, double* A);
 void oracle_macro_get_nodes(const oracle_macro* m, double* xy);
+int oracle_macro_nelem(const oracle_macro* m);
+void oracle_macro_get_conn(const oracle_macro* m, int* conn);
+/* micro states [nqp][2 n^2] of the last solves; set_qp overwrites the stored
+ * Fbar, Pbar, Abar and micro states (each may be NULL) */
+void oracle_macro_get_state(const oracle_macro* m, double* w);
+void oracle_macro_set_qp(oracle_macro* m, const double* F, const double* P, const double* A, const double* w);
+/* Macro element stiffness [8][8] of element e at the stored micro states:
+ * literal = 1, the FE-HMM transfer of eqs. (k-mac-element-5..7) -- the unit
+ * nodal displacement states (I, x_i) of the element, linearized at each Gauss
+ * point, drive the micro problem and k = sum omega T^T K T / |K_delta|;
+ * literal = 0, sum omega B^T Abar B with the stored tangents Abar. */
+int oracle_macro_element_stiffness(const oracle_macro* m, int e, int literal, double* k);
+
+/* The micro responses to nstate prescribed linearized displacement states
+ * (gradient G [nstate][d*d], translation tvec [nstate][d] or NULL) at the micro
+ * state (Fbar, w), and T^T K T / |K_delta| [nstate][nstate] with the tangent
+ * there (eq. Lagrange-Functional-for-StiffnessTransfer, eqs. k-mac-element-5..7). */
+int oracle_rve_transfer_states(int d, int n, const uint8_t* phase, const double* lame, const double* Fbar,
+                               const double* w, int nstate, const double* G, const double* tvec, double* kT);
 
 #ifdef __cplusplus
 }

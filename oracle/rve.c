@@ -209,29 +209,78 @@ void oracle_phase_by_centroid(int d, int n, const double* center, double r, int 
     }
 }
 
-/* Shape-function gradients (material frame) of the 2^d nodes at the 2^d Gauss
- * points xi = +-1/sqrt(3); weight * |J| = (h/2)^d. */
-static void shape_grads(int d, int n, double dN[MAXNE][MAXNE][MAXD], double* wJ) {
-    double g = 1.0 / sqrt(3.0), h = 1.0 / n;
+/* Micro element kind.  ORC_ELEM_Q1: bilinear quadrilaterals / trilinear
+ * hexahedra with 2^d Gauss points.  ORC_ELEM_P1: the paper's linear simplices
+ * (P1, Sec. 3.1 micro spaces), here the Kuhn triangulation of every grid cell
+ * into d! simplices sharing the cell's diagonal from local corner (0..0) to
+ * (1..1) (conforming across cells): the simplex of axis order s visits
+ * 0, e_s0, e_s0 + e_s1, ..., 1; its barycentric gradients are -e_s0 / h,
+ * (e_s(k-1) - e_sk) / h and e_s(d-1) / h.  The phase of a simplex is its cell's. */
+static int g_elem = ORC_ELEM_Q1;
+
+void oracle_set_element(int kind) { g_elem = kind; }
+int oracle_get_element(void) { return g_elem; }
+
+/* Integration points of one cell: gradients dN[p][a][k] of the cell's 2^d local
+ * nodes (zero for a node the point's simplex does not contain, P1) and the weight
+ * wJ of each point; returns the number of points. */
+static int shape_grads(int d, int n, double dN[MAXNE][MAXNE][MAXD], double* wJ) {
+    double h = 1.0 / n;
     int nen = 1 << d;
+    if (g_elem == ORC_ELEM_P1) {
+        int perm[6][3], np = 0;
+        if (d == 2) {
+            int q[2][2] = {{0, 1}, {1, 0}};
+            for (int t = 0; t < 2; ++t) { perm[t][0] = q[t][0]; perm[t][1] = q[t][1]; }
+            np = 2;
+        } else {
+            int q[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+            for (int t = 0; t < 6; ++t) for (int k = 0; k < 3; ++k) perm[t][k] = q[t][k];
+            np = 6;
+        }
+        for (int p = 0; p < np; ++p) {
+            for (int a = 0; a < nen; ++a) for (int k = 0; k < d; ++k) dN[p][a][k] = 0.0;
+            int v[MAXD] = {0, 0, 0};
+            for (int j = 0; j <= d; ++j) {  /* vertex j of the simplex */
+                if (j > 0) v[perm[p][j - 1]] = 1;
+                int a = -1;
+                for (int b = 0; b < nen; ++b) {
+                    int o[MAXD];
+                    local_offset(d, b, o);
+                    int same = 1;
+                    for (int k = 0; k < d; ++k) same &= o[k] == v[k];
+                    if (same) a = b;
+                }
+                double g[MAXD] = {0, 0, 0};
+                if (j == 0) g[perm[p][0]] = -1.0;
+                else if (j == d) g[perm[p][d - 1]] = 1.0;
+                else { g[perm[p][j - 1]] = 1.0; g[perm[p][j]] = -1.0; }
+                for (int k = 0; k < d; ++k) dN[p][a][k] = g[k] / h;
+            }
+        }
+        *wJ = pow(h, d) / (d == 2 ? 2.0 : 6.0);
+        return np;
+    }
+    double gq = 1.0 / sqrt(3.0);
     for (int p = 0; p < nen; ++p) {
         int op[MAXD];
         local_offset(d, p, op);
         double xi[MAXD];
-        for (int k = 0; k < d; ++k) xi[k] = op[k] ? g : -g;
+        for (int k = 0; k < d; ++k) xi[k] = op[k] ? gq : -gq;
         for (int a = 0; a < nen; ++a) {
             int oa[MAXD];
             local_offset(d, a, oa);
             double sa[MAXD];
             for (int k = 0; k < d; ++k) sa[k] = oa[k] ? 1.0 : -1.0;
             for (int k = 0; k < d; ++k) {
-                double v = 1.0;
-                for (int m = 0; m < d; ++m) v *= (m == k) ? 0.5 * sa[m] : 0.5 * (1.0 + sa[m] * xi[m]);
-                dN[p][a][k] = v * 2.0 / h; /* dN/dX = dN/dxi * 2/h */
+                double vv = 1.0;
+                for (int m = 0; m < d; ++m) vv *= (m == k) ? 0.5 * sa[m] : 0.5 * (1.0 + sa[m] * xi[m]);
+                dN[p][a][k] = vv * 2.0 / h; /* dN/dX = dN/dxi * 2/h */
             }
         }
     }
     *wJ = pow(0.5 * h, d);
+    return nen;
 }
 
 /* Voigt pairs (engineering shear) */
@@ -249,17 +298,18 @@ static int voigt_pairs(int d, int pr[MAXV][2]) {
 int oracle_element(int d, int n, const uint8_t* phase, const double* lame, int e, const double* Fbar,
                    const double* w, double* fe, double* ke, double* energy) {
     double dN[MAXNE][MAXNE][MAXD], wJ;
-    shape_grads(d, n, dN, &wJ);
+    const int npt = shape_grads(d, n, dN, &wJ);
     int nen = 1 << d, nd = nen * d;
     int nodes[MAXNE];
     element_nodes(d, n, e, nodes);
+    /* (npt integration points: the Q1 Gauss points or the cell's P1 simplices) */
     double lam = lame[2 * phase[e]], mu = lame[2 * phase[e] + 1];
     int pr[MAXV][2];
     int nv = voigt_pairs(d, pr);
     if (fe) memset(fe, 0, sizeof(double) * nd);
     if (ke) memset(ke, 0, sizeof(double) * nd * nd);
     double en = 0;
-    for (int p = 0; p < nen; ++p) {
+    for (int p = 0; p < npt; ++p) {
         double F[9];
         for (int i = 0; i < d; ++i)
             for (int J = 0; J < d; ++J) {
@@ -439,12 +489,12 @@ static int all_J_positive(const rve_sys* r, const uint8_t* phase, const double* 
                           const double* w) {
     double dN[MAXNE][MAXNE][MAXD], wJ;
     int d = r->d, nen = 1 << d;
-    shape_grads(d, r->n, dN, &wJ);
+    const int npt = shape_grads(d, r->n, dN, &wJ);
     (void)phase; (void)lame;
     for (int e = 0; e < r->ne; ++e) {
         int nodes[MAXNE];
         element_nodes(d, r->n, e, nodes);
-        for (int p = 0; p < nen; ++p) {
+        for (int p = 0; p < npt; ++p) {
             double F[9];
             for (int i = 0; i < d; ++i)
                 for (int J = 0; J < d; ++J) {
@@ -464,13 +514,13 @@ static void average_P(const rve_sys* r, const uint8_t* phase, const double* lame
                       const double* w, double* P) {
     double dN[MAXNE][MAXNE][MAXD], wJ;
     int d = r->d, nen = 1 << d;
-    shape_grads(d, r->n, dN, &wJ);
+    const int npt = shape_grads(d, r->n, dN, &wJ);
     memset(P, 0, sizeof(double) * d * d);
     for (int e = 0; e < r->ne; ++e) {
         int nodes[MAXNE];
         element_nodes(d, r->n, e, nodes);
         double lam = lame[2 * phase[e]], mu = lame[2 * phase[e] + 1];
-        for (int p = 0; p < nen; ++p) {
+        for (int p = 0; p < npt; ++p) {
             double F[9], S[9];
             for (int i = 0; i < d; ++i)
                 for (int J = 0; J < d; ++J) {
@@ -670,7 +720,7 @@ int oracle_linear_homogenized(int d, int n, const uint8_t* phase, const double* 
     rve_sys r;
     if (rve_sys_init(&r, d, n)) return ORC_SINGULAR;
     double dN[MAXNE][MAXNE][MAXD], wJ;
-    shape_grads(d, n, dN, &wJ);
+    const int npt = shape_grads(d, n, dN, &wJ);
     int nen = 1 << d, nd = nen * d, pr[MAXV][2];
     int nv = voigt_pairs(d, pr);
     double* rhs = (double*)calloc((size_t)nv * r.nf, sizeof(double));
@@ -689,7 +739,7 @@ int oracle_linear_homogenized(int d, int n, const uint8_t* phase, const double* 
                     int na = pr[a][0] == pr[a][1], nb2 = pr[b][0] == pr[b][1];
                     Cl[a][b] = (na && nb2 ? lam : 0.0) + (a == b ? (na ? 2.0 * mu : mu) : 0.0);
                 }
-            for (int p = 0; p < nen; ++p) {
+            for (int p = 0; p < npt; ++p) {
                 double BL[MAXV][MAXNE * MAXD];
                 for (int v = 0; v < nv; ++v) {
                     int I = pr[v][0], J = pr[v][1];
@@ -763,6 +813,90 @@ int oracle_linear_homogenized(int d, int n, const uint8_t* phase, const double* 
     return ORC_OK;
 }
 
+
+/* The literal stiffness transfer of eqs. (k-mac-element-5..7): for each of
+ * nstate prescribed linearized displacement states (eq. linearization-uH) --
+ * a constant gradient G_j (d x d) plus a translation t_j (d) -- the micro
+ * response D_j solves the linear constrained problem of
+ * eq. (Lagrange-Functional-for-StiffnessTransfer) with the tangent K_T^h at the
+ * micro state (Fbar, w): D_j = t_j + G_j X + w_j with the admissible fluctuation
+ * w_j from K_ff w_j = -K_f(t_j + G_j X).  The output is the nstate x nstate
+ * matrix T^T K T / |K_delta| with T = [D_1 ... D_nstate] and |K_delta| = 1,
+ * computed element by element with the full element tangents (k_e annihilates
+ * translations, so each element takes its affine part in local coordinates). */
+int oracle_rve_transfer_states(int d, int n, const uint8_t* phase, const double* lame, const double* Fbar,
+                               const double* w, int nstate, const double* G, const double* tvec, double* kT) {
+    rve_sys r;
+    if (rve_sys_init(&r, d, n)) return ORC_SINGULAR;
+    int nen = 1 << d, nd = nen * d, ndof = d * r.nn;
+    double h = 1.0 / n;
+    double* R = (double*)malloc(sizeof(double) * ndof);
+    double* rhs = (double*)calloc((size_t)nstate * (r.nf ? r.nf : 1), sizeof(double));
+    double* wS = (double*)calloc((size_t)nstate * ndof, sizeof(double));
+    double* Daff = (double*)malloc(sizeof(double) * (size_t)nstate * nd);
+    double ke[MAXNE * MAXD * MAXNE * MAXD];
+    int st = rve_assemble(&r, phase, lame, Fbar, w, R, 1);
+    if (!st) st = sky_ldlt(&r.K);
+    /* element-local affine part of every state */
+    for (int j = 0; j < nstate && !st; ++j)
+        for (int a = 0; a < nen; ++a) {
+            int o[MAXD];
+            local_offset(d, a, o);
+            for (int i = 0; i < d; ++i) {
+                double v = tvec ? tvec[j * d + i] : 0.0;
+                for (int J = 0; J < d; ++J) v += G[(j * d + i) * d + J] * o[J] * h;
+                Daff[j * nd + a * d + i] = v;
+            }
+        }
+    for (int e = 0; e < r.ne && !st; ++e) {
+        int nodes[MAXNE];
+        st = oracle_element(d, n, phase, lame, e, Fbar, w, NULL, ke, NULL);
+        element_nodes(d, n, e, nodes);
+        for (int j = 0; j < nstate && !st; ++j)
+            for (int q1 = 0; q1 < nd; ++q1) {
+                int g1 = r.dof[nodes[q1 / d] * d + q1 % d];
+                if (g1 < 0) continue;
+                double v = 0;
+                for (int q2 = 0; q2 < nd; ++q2) v += ke[q1 * nd + q2] * Daff[j * nd + q2];
+                rhs[(size_t)j * r.nf + g1] -= v;
+            }
+    }
+    for (int j = 0; j < nstate && !st; ++j) {
+        sky_solve(&r.K, rhs + (size_t)j * r.nf);
+        for (int i = 0; i < ndof; ++i)
+            wS[(size_t)j * ndof + i] = r.dof[i] < 0 ? 0.0 : rhs[(size_t)j * r.nf + r.dof[i]];
+    }
+    if (!st) {
+        memset(kT, 0, sizeof(double) * nstate * nstate);
+        double* De = (double*)malloc(sizeof(double) * (size_t)nstate * nd);
+        double* kD = (double*)malloc(sizeof(double) * nd);
+        for (int e = 0; e < r.ne; ++e) {
+            int nodes[MAXNE];
+            oracle_element(d, n, phase, lame, e, Fbar, w, NULL, ke, NULL);
+            element_nodes(d, n, e, nodes);
+            for (int j = 0; j < nstate; ++j)
+                for (int q = 0; q < nd; ++q)
+                    De[j * nd + q] = Daff[j * nd + q] + wS[(size_t)j * ndof + nodes[q / d] * d + q % d];
+            for (int k = 0; k < nstate; ++k) {
+                for (int q1 = 0; q1 < nd; ++q1) {
+                    double v = 0;
+                    for (int q2 = 0; q2 < nd; ++q2) v += ke[q1 * nd + q2] * De[k * nd + q2];
+                    kD[q1] = v;
+                }
+                for (int j = 0; j < nstate; ++j) {
+                    double v = 0;
+                    for (int q = 0; q < nd; ++q) v += De[j * nd + q] * kD[q];
+                    kT[j * nstate + k] += v;
+                }
+            }
+        }
+        free(De);
+        free(kD);
+    }
+    free(R); free(rhs); free(wS); free(Daff);
+    rve_sys_free(&r);
+    return st;
+}
 
 /* One micro Newton iteration for the alternating scheme (Algorithm 2, Sec. 5.2):
  * from the stored fluctuation w, one update D_{K,0} -> D_{K,1} (skipped when the
