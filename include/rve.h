@@ -89,6 +89,12 @@ int rve_lame(double E, double nu, double* lambda_out, double* mu_out);
  *              only the (n-1)^d interior nodes are free.  Fluctuations keep the
  *              n^d node layout either way (boundary nodes -- every node with
  *              some grid index 0 -- hold 0).
+ *   elem       micro element kind (RVE_ELEM_*): bilinear quadrilaterals /
+ *              trilinear hexahedra with 2^d Gauss points (default, 0), or the
+ *              paper's linear simplices P1 (Sec. 3.1): every grid cell split into
+ *              d! simplices along its (0..0)-(1..1) diagonal (a conforming Kuhn
+ *              triangulation), one integration point each, the cell's phase.
+ *              Nodes and unknowns are the same for both kinds.
  * The symbolic factorization plan for (ndim, n) is built on first use and shared
  * by every mesh of that size. */
 typedef struct {
@@ -102,7 +108,11 @@ typedef struct {
     int32_t incl_phase;
     int32_t law;
     int32_t bc;
+    int32_t elem;
 } rve_mesh_desc;
+
+#define RVE_ELEM_Q1 0
+#define RVE_ELEM_P1 1
 
 #define RVE_BC_PERIODIC 0
 #define RVE_BC_LINEAR 1

@@ -6,7 +6,7 @@ from . import rve
 
 
 def build_batch(d, n_list, radius_list, ratio_list, nu=0.3, E=1.0, center=None, law=rve.LAW_NEOHOOKE,
-                bc=rve.BC_PERIODIC):
+                bc=rve.BC_PERIODIC, elem=rve.ELEM_Q1):
     """One mesh per distinct (n, radius, ratio); returns (Batch, meshes)."""
     cache = {}
     meshes = []
@@ -14,7 +14,7 @@ def build_batch(d, n_list, radius_list, ratio_list, nu=0.3, E=1.0, center=None, 
         key = (int(n), float(r), float(q))
         if key not in cache:
             cache[key] = rve.Mesh(d, int(n), rve.two_phase_lame(float(q), E=E, nu=nu), radius=float(r),
-                                  center=center, law=law, bc=bc)
+                                  center=center, law=law, bc=bc, elem=elem)
         meshes.append(cache[key])
     return rve.Batch(meshes), meshes
 

@@ -202,6 +202,7 @@ struct rve_mesh_s {
     double mu_max = 0;
     int law = RVE_LAW_NEOHOOKE;
     int bc = RVE_BC_PERIODIC;
+    int elem = RVE_ELEM_Q1;
     bool alive = true;
 };
 
@@ -224,7 +225,7 @@ struct rve_batch_s {
     int64_t* d_rve_phase = nullptr;
     uint8_t* d_phase_pool = nullptr;
     int32_t* d_rve_lame = nullptr;
-    int32_t* d_rve_law = nullptr;
+    int32_t* d_rve_kind = nullptr;
     double* d_lame_pool = nullptr;
     int64_t* d_state_off = nullptr;
     double* d_atol = nullptr;
@@ -300,9 +301,12 @@ int rve_mesh_create(const rve_mesh_desc* d, rve_mesh* out) {
         return fail(RVE_EINVAL, "rve_mesh_create: unknown constitutive law");
     if (d->bc != RVE_BC_PERIODIC && d->bc != RVE_BC_LINEAR)
         return fail(RVE_EINVAL, "rve_mesh_create: unknown micro boundary conditions");
+    if (d->elem != RVE_ELEM_Q1 && d->elem != RVE_ELEM_P1)
+        return fail(RVE_EINVAL, "rve_mesh_create: unknown element kind");
     auto m = std::make_unique<rve_mesh_s>();
     m->law = d->law;
     m->bc = d->bc;
+    m->elem = d->elem;
     m->d = d->ndim;
     m->n = d->n;
     m->nphase = d->nphase;
@@ -365,7 +369,7 @@ int rve_mesh_get_phase(rve_mesh m, uint8_t* host_phase) {
 
 static void free_batch(rve_batch_s* b) {
     (void)hipFree(b->d_plans); (void)hipFree(b->d_rve_plan); (void)hipFree(b->d_rve_phase); (void)hipFree(b->d_phase_pool);
-    (void)hipFree(b->d_rve_lame); (void)hipFree(b->d_rve_law); (void)hipFree(b->d_lame_pool); (void)hipFree(b->d_state_off); (void)hipFree(b->d_atol);
+    (void)hipFree(b->d_rve_lame); (void)hipFree(b->d_rve_kind); (void)hipFree(b->d_lame_pool); (void)hipFree(b->d_state_off); (void)hipFree(b->d_atol);
     (void)hipFree(b->d_order); (void)hipFree(b->d_ws); (void)hipFree(b->d_counter);
     b->d_ws = nullptr;
 }
@@ -406,7 +410,7 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
     std::map<rve_mesh, std::pair<int64_t, int32_t>> mesh_off;  // phase offset, lame offset
     std::vector<uint8_t> phase_pool;
     std::vector<double> lame_pool;
-    std::vector<int32_t> rve_plan(B), rve_lame(B), rve_law(B);
+    std::vector<int32_t> rve_plan(B), rve_lame(B), rve_kind(B);
     std::vector<int64_t> rve_phase(B);
     std::vector<double> atol(B);
     b->state_off.resize(B + 1);
@@ -428,7 +432,7 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
         rve_plan[r] = plan_id[m->plan];
         rve_phase[r] = it->second.first;
         rve_lame[r] = it->second.second;
-        rve_law[r] = m->law;
+        rve_kind[r] = m->law | (m->elem << 8);
         atol[r] = 1e-12 * m->mu_max * std::pow(1.0 / m->n, d - 1);
         b->state_off[r + 1] = b->state_off[r] + (int64_t)d * m->plan->host.nnode;
         cost[r] = m->plan->host.factor_flops;
@@ -503,7 +507,7 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
     int st;
     if ((st = upload(dplans, &b->d_plans)) || (st = upload(rve_plan, &b->d_rve_plan)) ||
         (st = upload(rve_phase, &b->d_rve_phase)) || (st = upload(phase_pool, &b->d_phase_pool)) ||
-        (st = upload(rve_lame, &b->d_rve_lame)) || (st = upload(rve_law, &b->d_rve_law)) ||
+        (st = upload(rve_lame, &b->d_rve_lame)) || (st = upload(rve_kind, &b->d_rve_kind)) ||
         (st = upload(lame_pool, &b->d_lame_pool)) ||
         (st = upload(b->state_off, &b->d_state_off)) || (st = upload(atol, &b->d_atol)) ||
         (st = upload(order, &b->d_order))) {
@@ -573,7 +577,7 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
     a.rve_phase = b->d_rve_phase;
     a.phase_pool = b->d_phase_pool;
     a.rve_lame = b->d_rve_lame;
-    a.rve_law = b->d_rve_law;
+    a.rve_kind = b->d_rve_kind;
     a.lame_pool = b->d_lame_pool;
     a.state_off = b->d_state_off;
     a.rve_atol = b->d_atol;
@@ -648,7 +652,7 @@ int rve_assemble_batch(rve_batch b, const double* F, const double* w_state, int3
     a.rve_phase = b->d_rve_phase;
     a.phase_pool = b->d_phase_pool;
     a.rve_lame = b->d_rve_lame;
-    a.rve_law = b->d_rve_law;
+    a.rve_kind = b->d_rve_kind;
     a.lame_pool = b->d_lame_pool;
     a.state_off = b->d_state_off;
     a.rve_atol = b->d_atol;
@@ -834,6 +838,7 @@ int rve_autotune(rve_mesh m, const double* F, int64_t nF, const rve_opts* o, rve
                 md.phase = m->phase.data();
                 md.law = m->law;
                 md.bc = m->bc;
+                md.elem = m->elem;
                 rve_mesh cm = nullptr;
                 if ((err = rve_mesh_create(&md, &cm))) break;
                 std::vector<rve_mesh> ms((size_t)nF, cm);

@@ -134,6 +134,7 @@ struct RveCtx {
     const DevPlan* plan;
     int d, n, ne, nn, nen, nd;
     int law;  // RVE_LAW_*: 0 neo-Hookean, 1 St. Venant-Kirchhoff, 2 fully linear
+    int elem; // RVE_ELEM_*: 0 Q1 / hex8 with 2^d Gauss points, 1 P1 (d! Kuhn simplices per cell)
     const uint8_t* phase;
     const double* lame;
     double* w;
@@ -262,7 +263,7 @@ __device__ inline void load_wl(const RveCtx& c, const double* w, int e, double* 
 // contracted with the material gradients,
 //     f_(a,i) = sum P_iJ dN_a,J w|J|,  k_(a,i),(b,k) = sum dN_a,J A_iJkL dN_b,L w|J|,
 //     Y_(a,i),(kL) = sum dN_a,J A_iJkL w|J|.
-template <int D>
+template <int D, int NPT>
 __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP,
                                               double* accA) {
     constexpr int NEN = 1 << D, ND = NEN * D, D2 = D * D, RPI = (D == 2) ? 2 : 1;
@@ -289,7 +290,7 @@ __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const d
 #pragma unroll
             for (int q = 0; q < D2; ++q) yr[r][q] = 0;
         }
-        for (int gp = 0; gp < NEN; ++gp) {
+        for (int gp = 0; gp < NPT; ++gp) {
             double F[D2], Fi[D2], J;
             gp_F<D>(c, sm, wl, gp, F);
             inv_det<D>(F, Fi, J);
@@ -362,7 +363,7 @@ __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const d
 // Element pass of the neo-Hookean law.  mode 0: residual + tangent rows
 // (Newton); mode 1: J > 0 check only (on w); mode 2: final outputs (Pbar, <A>,
 // Y rows).  Work item = (e, a) in 2D (rows i = 0,1), (e, a, i) in 3D.
-template <int D>
+template <int D, int NPT>
 __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP,
                                              double* accA) {
     constexpr int NEN = 1 << D, ND = NEN * D, RPI = (D == 2) ? 2 : 1;
@@ -389,7 +390,7 @@ __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const do
 #pragma unroll
             for (int q = 0; q < D * D; ++q) yr[r][q] = 0;
         }
-        for (int gp = 0; gp < NEN; ++gp) {
+        for (int gp = 0; gp < NPT; ++gp) {
             double F[D * D], Fi[D * D], J;
             gp_F<D>(c, sm, wl, gp, F);
             inv_det<D>(F, Fi, J);
@@ -480,13 +481,18 @@ __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const do
     }
 }
 
-// the element pass of the RVE's law (neo-Hookean closed forms, or the generic path)
+// the element pass of the RVE's law (neo-Hookean closed forms, or the generic
+// path) and element kind (2^d Gauss points of Q1 / hex8, or d! P1 simplices)
 template <int D>
 __device__ inline void element_pass(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP, double* accA) {
-    if (c.law != 0)
-        element_pass_law<D>(c, sm, w, mode, accP, accA);
-    else
-        element_pass_nh<D>(c, sm, w, mode, accP, accA);
+    constexpr int NQ1 = 1 << D, NP1 = D == 2 ? 2 : 6;
+    if (c.elem == 0) {
+        if (c.law != 0) element_pass_law<D, NQ1>(c, sm, w, mode, accP, accA);
+        else element_pass_nh<D, NQ1>(c, sm, w, mode, accP, accA);
+    } else {
+        if (c.law != 0) element_pass_law<D, NP1>(c, sm, w, mode, accP, accA);
+        else element_pass_nh<D, NP1>(c, sm, w, mode, accP, accA);
+    }
 }
 
 // node gather of element vectors: out[(v*D+i)*nc + col] = sum_a src[e_a(v)][(a*D+i)*nc + col]
@@ -2130,7 +2136,9 @@ __device__ inline void rve_setup(const SolveArgs& a, int rve, double* base, RveC
     c.nd = ND;
     c.phase = a.phase_pool + a.rve_phase[rve];
     c.lame = a.lame_pool + a.rve_lame[rve];
-    c.law = a.rve_law ? a.rve_law[rve] : 0;
+    const int kind = a.rve_kind ? a.rve_kind[rve] : 0;
+    c.law = kind & 0xff;
+    c.elem = (kind >> 8) & 0xff;
     c.w = base + a.lay.w;
     c.wt = base + a.lay.wt;
     c.R = base + a.lay.R;
@@ -2142,8 +2150,35 @@ __device__ inline void rve_setup(const SolveArgs& a, int rve, double* base, RveC
     c.L = base + a.lay.L;
     c.U = base + a.lay.U;
     c.S = base + a.lay.S;
-    // constants of the uniform grid: grad N at the Gauss points, w|J|
-    if (threadIdx.x < NEN * NEN) {
+    // constants of the uniform grid: grad N at the integration points, w|J|.
+    // P1: point p is the Kuhn simplex of axis order perm(p), vertices 0,
+    // e_s0, e_s0 + e_s1, ..., 1; a cell corner o is its vertex j when o holds j
+    // ones, at s0 .. s(j-1); barycentric gradients -e_s0, e_s(j-1) - e_sj,
+    // e_s(d-1) (over h), zero at the corners the simplex misses
+    if (c.elem == 1 && threadIdx.x < 8 * NEN) {
+        const int p = threadIdx.x / NEN, an = threadIdx.x % NEN;
+        // the d! axis orders (p < D!: 2 in 2D, 6 in 3D), lexicographic
+        const int perm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+        const int perm2[2][3] = {{0, 1, 2}, {1, 0, 2}};
+        const int npt = D == 2 ? 2 : 6;
+        int oa[3] = {0, 0, 0};
+        local_offset(D, an, oa);
+        double g[3] = {0.0, 0.0, 0.0};
+        if (p < npt) {
+            const int* pm = D == 2 ? perm2[p] : perm3[p];
+            int ones = 0;
+            for (int k = 0; k < D; ++k) ones += oa[k];
+            bool vert = true;
+            for (int q = 0; q < ones; ++q) vert = vert && oa[pm[q]] == 1;
+            if (vert) {
+                const double ih = (double)c.n;
+                if (ones == 0) g[pm[0]] = -ih;
+                else if (ones == D) g[pm[D - 1]] = ih;
+                else { g[pm[ones - 1]] = ih; g[pm[ones]] = -ih; }
+            }
+        }
+        for (int k = 0; k < 3; ++k) sm.dN[(p * 8 + an) * 3 + k] = g[k];
+    } else if (c.elem == 0 && threadIdx.x < NEN * NEN) {
         const int gp = threadIdx.x / NEN, an = threadIdx.x % NEN;
         const double gq = 0.57735026918962576451, h = 1.0 / c.n;
         int og[3] = {0, 0, 0}, oa[3] = {0, 0, 0};
@@ -2161,7 +2196,8 @@ __device__ inline void rve_setup(const SolveArgs& a, int rve, double* base, RveC
     if (threadIdx.x < D2) sm.Fbar[threadIdx.x] = a.F[(int64_t)rve * D2 + threadIdx.x];
     if (threadIdx.x == 0) {
         double h = 1.0 / c.n, wj = 1.0;
-        for (int k = 0; k < D; ++k) wj *= 0.5 * h;
+        for (int k = 0; k < D; ++k) wj *= (c.elem == 1 ? h : 0.5 * h);
+        if (c.elem == 1) wj /= (D == 2 ? 2.0 : 6.0);  // simplex volume h^d / d!
         sm.wJ = wj;
         sm.flag = 0;
         sm.atol = a.atol >= 0 ? a.atol : a.rve_atol[rve];

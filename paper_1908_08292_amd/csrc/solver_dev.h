@@ -42,7 +42,7 @@ struct SolveArgs {
     const int64_t* rve_phase;    // [B] offset into phase_pool
     const uint8_t* phase_pool;
     const int32_t* rve_lame;     // [B] offset (in doubles) into lame_pool
-    const int32_t* rve_law;      // [B] RVE_LAW_* of each RVE's mesh
+    const int32_t* rve_kind;     // [B] RVE_LAW_* | RVE_ELEM_* << 8 of each RVE's mesh
     const double* lame_pool;
     const int64_t* state_off;    // [B+1]
     const double* rve_atol;      // [B] default absolute tolerance

@@ -20,6 +20,7 @@ S_CONVERGED, S_NOCONV, S_DETF, S_SINGULAR, S_NONFINITE = 0, 1, 2, 3, 4
 PREC_FP64, PREC_FP32_IR = 0, 1
 LAW_NEOHOOKE, LAW_SVK, LAW_LINEAR = 0, 1, 2
 BC_PERIODIC, BC_LINEAR = 0, 1
+ELEM_Q1, ELEM_P1 = 0, 1
 
 
 class RveError(RuntimeError):
@@ -31,7 +32,8 @@ class RveError(RuntimeError):
 class MeshDesc(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("n", C.c_int32), ("nphase", C.c_int32), ("lame", C.c_void_p),
                 ("phase", C.c_void_p), ("incl_center", C.c_double * 3), ("incl_radius", C.c_double),
-                ("incl_phase", C.c_int32), ("law", C.c_int32), ("bc", C.c_int32)]
+                ("incl_phase", C.c_int32), ("law", C.c_int32), ("bc", C.c_int32),
+                ("elem", C.c_int32)]
 
 
 class Opts(C.Structure):
@@ -202,17 +204,17 @@ class Mesh:
     """rve_mesh handle: phase field by explicit array or centred inclusion."""
 
     def __init__(self, d, n, lame_tab, phase=None, radius=0.0, center=None, incl_phase=1, law=LAW_NEOHOOKE,
-                 bc=BC_PERIODIC):
+                 bc=BC_PERIODIC, elem=ELEM_Q1):
         self._lame = np.ascontiguousarray(lame_tab, np.float64)
         self._phase = None if phase is None else np.ascontiguousarray(phase, np.uint8)
         c = center if center is not None else [0.5, 0.5, 0.5]
         desc = MeshDesc(d, n, self._lame.shape[0], self._lame.ctypes.data_as(C.c_void_p),
                         None if self._phase is None else self._phase.ctypes.data_as(C.c_void_p),
                         (C.c_double * 3)(*[float(x) for x in list(c) + [0.5] * (3 - len(c))]), float(radius),
-                        incl_phase, int(law), int(bc))
+                        incl_phase, int(law), int(bc), int(elem))
         h = C.c_void_p()
         check(lib().rve_mesh_create(C.byref(desc), C.byref(h)), "rve_mesh_create")
-        self.h, self.d, self.n, self.law, self.bc = h, d, n, law, bc
+        self.h, self.d, self.n, self.law, self.bc, self.elem = h, d, n, law, bc, elem
 
     def phase(self):
         out = np.zeros(self.n ** self.d, np.uint8)
