@@ -4,7 +4,9 @@
  *
  * Macro problem: bilinear quadrilaterals on the rectangle [0,Lx] x [0,Ly]
  * (nx x ny elements, optionally without the elements whose centroid lies in a
- * centred hole of radius hole_r), 2 x 2 Gauss points, plane strain.  At every
+ * centred hole of radius hole_r), 2 x 2 Gauss points, plane strain; or the
+ * paper's linear triangles (P1, Sec. 3.1): every cell split along its
+ * (0,0)-(1,1) diagonal, one quadrature point per triangle (qp = 2 e + t).  At every
  * macro Gauss point the displacement is linearized (eq. linearization-uH) and a
  * periodic RVE (rve.h) is driven by Fbar = I + grad u^H.  The macro residual is
  * R_H = sum_qp B_mac^T Pbar w|J|, i.e. f_I^int = int B_I^T S^H with
@@ -67,7 +69,12 @@ typedef struct {
     int32_t scheme;         /* FEHMM_NESTED or FEHMM_ALTERNATING */
     rve_mesh micro;         /* 2D RVE shared by every quadrature point (must outlive the driver) */
     rve_opts micro_opts;    /* Newton options of the micro solves */
+    int32_t elem;           /* FEHMM_ELEM_Q1 (2 x 2 Gauss points) or FEHMM_ELEM_P1 (each grid cell split
+                               into the triangles of its (0,0)-(1,1) diagonal, one point each) */
 } fehmm_desc;
+
+#define FEHMM_ELEM_Q1 0
+#define FEHMM_ELEM_P1 1
 
 typedef struct {
     int32_t status;                      /* FEHMM_STEP_* */

@@ -53,7 +53,7 @@ class MacroDesc(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("Lx", C.c_double), ("Ly", C.c_double),
                 ("hole_r", C.c_double), ("bc", C.c_int), ("stretch", C.c_double), ("nsteps", C.c_int),
                 ("rtol_macro", C.c_double), ("scheme", C.c_int), ("max_macro_iter", C.c_int),
-                ("n", C.c_int), ("phase", C.c_void_p), ("lame", C.c_void_p)]
+                ("n", C.c_int), ("phase", C.c_void_p), ("lame", C.c_void_p), ("elem", C.c_int)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -349,11 +349,11 @@ class Macro:
     """Macro FE-HMM driver of the oracle (2D, Q1 macro, 2x2 Gauss)."""
 
     def __init__(self, nx, ny, n, phase, lame, Lx=1.0, Ly=1.0, hole_r=0.0, bc=0, stretch=1.1, nsteps=10,
-                 rtol_macro=1e-10, scheme=0, max_macro_iter=30, micro_opts=None):
+                 rtol_macro=1e-10, scheme=0, max_macro_iter=30, micro_opts=None, elem=0):
         self._phase = np.ascontiguousarray(phase, np.uint8)
         self._lame = _f64(lame)
         self.desc = MacroDesc(nx, ny, Lx, Ly, hole_r, bc, stretch, nsteps, rtol_macro, scheme, max_macro_iter,
-                              n, _p(self._phase), _p(self._lame))
+                              n, _p(self._phase), _p(self._lame), int(elem))
         self.opts = micro_opts if micro_opts is not None else make_opts(self._lame, n, 2)
         self.h = lib().oracle_macro_create(C.byref(self.desc), C.byref(self.opts))
         self.ndof = lib().oracle_macro_ndof(self.h)

@@ -37,22 +37,41 @@ struct oracle_macro {
     double* u;        /* [ndof] */
     double* wq;       /* [nqp][nw] micro fluctuations */
     double* Fq; double* Pq; double* Aq;
+    int npt;              /* quadrature points per grid cell: 4 (Q1) or 2 (P1 triangles) */
     double dN[4][4][2];   /* [gp][node][dir] for the (uniform) element size */
+    double Nv[4][4];      /* shape values [gp][node] */
     double wdet;
     skyline K;
 };
 
-static void q1_grads(double hx, double hy, double dN[4][4][2], double* wdet) {
+/* Q1: 2x2 Gauss points.  P1: the cell's triangles (0,1,2) and (0,2,3) in its
+ * counter-clockwise node order, one point each at the centroid (linear shape
+ * functions: constant gradients, value 1/3 at the centroid), weight hx hy / 2. */
+static int macro_points(int elem, double hx, double hy, double dN[4][4][2], double Nv[4][4], double* wdet) {
     static const int sx[4] = {-1, 1, 1, -1}, sy[4] = {-1, -1, 1, 1};
+    memset(dN, 0, sizeof(double) * 32);
+    memset(Nv, 0, sizeof(double) * 16);
+    if (elem == 1) {
+        /* triangle 0: (0,0) (hx,0) (hx,hy); triangle 1: (0,0) (hx,hy) (0,hy) */
+        dN[0][0][0] = -1.0 / hx;                         dN[0][1][0] = 1.0 / hx; dN[0][1][1] = -1.0 / hy;
+        dN[0][2][1] = 1.0 / hy;
+        dN[1][0][1] = -1.0 / hy; dN[1][2][0] = 1.0 / hx; dN[1][3][0] = -1.0 / hx; dN[1][3][1] = 1.0 / hy;
+        Nv[0][0] = Nv[0][1] = Nv[0][2] = 1.0 / 3.0;
+        Nv[1][0] = Nv[1][2] = Nv[1][3] = 1.0 / 3.0;
+        *wdet = 0.5 * hx * hy;
+        return 2;
+    }
     double g = 1.0 / sqrt(3.0);
     for (int p = 0; p < 4; ++p) {
         double xi = sx[p] * g, eta = sy[p] * g;
         for (int a = 0; a < 4; ++a) {
             dN[p][a][0] = 0.25 * sx[a] * (1 + sy[a] * eta) * 2.0 / hx;
             dN[p][a][1] = 0.25 * sy[a] * (1 + sx[a] * xi) * 2.0 / hy;
+            Nv[p][a] = 0.25 * (1 + sx[a] * xi) * (1 + sy[a] * eta);
         }
     }
     *wdet = 0.25 * hx * hy;
+    return 4;
 }
 
 oracle_macro* oracle_macro_create(const oracle_macro_desc* d, const oracle_opts* micro) {
@@ -61,7 +80,7 @@ oracle_macro* oracle_macro_create(const oracle_macro_desc* d, const oracle_opts*
     m->micro = *micro;
     int nx = d->nx, ny = d->ny;
     double hx = d->Lx / nx, hy = d->Ly / ny;
-    q1_grads(hx, hy, m->dN, &m->wdet);
+    m->npt = macro_points(d->elem, hx, hy, m->dN, m->Nv, &m->wdet);
     int* keep = (int*)malloc(sizeof(int) * nx * ny);
     int* used = (int*)calloc((nx + 1) * (ny + 1), sizeof(int));
     m->nelem = 0;
@@ -156,7 +175,7 @@ oracle_macro* oracle_macro_create(const oracle_macro_desc* d, const oracle_opts*
     free(fc); free(pos); free(perm); free(adjc); free(cnt); free(adj); free(xadj);
     free(id); free(used); free(keep);
     m->u = (double*)calloc(m->ndof, sizeof(double));
-    m->nqp = 4 * m->nelem;
+    m->nqp = m->npt * m->nelem;
     m->nw = 2 * d->n * d->n;
     m->wq = (double*)calloc((size_t)m->nqp * m->nw, sizeof(double));
     m->Fq = (double*)calloc((size_t)m->nqp * 4, sizeof(double));
@@ -185,8 +204,8 @@ void oracle_macro_get_qp(const oracle_macro* m, double* F, double* P, double* A)
 
 static void macro_gather_F(oracle_macro* m) {
     for (int e = 0; e < m->nelem; ++e)
-        for (int p = 0; p < 4; ++p) {
-            double* F = m->Fq + 4 * (4 * e + p);
+        for (int p = 0; p < m->npt; ++p) {
+            double* F = m->Fq + 4 * (m->npt * e + p);
             F[0] = 1; F[1] = 0; F[2] = 0; F[3] = 1;
             for (int a = 0; a < 4; ++a) {
                 int v = m->conn[4 * e + a];
@@ -225,9 +244,9 @@ static double macro_assemble(oracle_macro* m, double* R, const double* dud) {
     memset(R, 0, sizeof(double) * (m->nfree ? m->nfree : 1));
     memset(m->K.val, 0, sizeof(double) * m->K.ptr[m->K.N]);
     for (int e = 0; e < m->nelem; ++e)
-        for (int p = 0; p < 4; ++p) {
-            const double* P = m->Pq + 4 * (4 * e + p);
-            const double* A = m->Aq + 16 * (4 * e + p);
+        for (int p = 0; p < m->npt; ++p) {
+            const double* P = m->Pq + 4 * (m->npt * e + p);
+            const double* A = m->Aq + 16 * (m->npt * e + p);
             for (int a = 0; a < 4; ++a)
                 for (int i = 0; i < 2; ++i) {
                     int g = m->dofmap[2 * m->conn[4 * e + a] + i];
@@ -300,24 +319,18 @@ int oracle_macro_step(oracle_macro* m, int step, int* macro_iters, double* res_h
     return status;
 }
 
-/* Macro element stiffness of element e at the stored micro states, two ways.
- * Literal (eqs. k-mac-element-5..7): at each Gauss point the 4 x 2 unit nodal
+/* Macro element stiffness of element (grid cell) e at the stored micro states,
+ * two ways.  Literal (eqs. k-mac-element-5..7): at each quadrature point the 4 x 2 unit nodal
  * displacement states (I, x_i) of the element, linearized at the point
  * (eq. linearization-uH: translation N_I(x_qp) e_i, gradient e_i (x) grad N_I),
  * drive the micro problem; k = sum_qp omega_qp T^T K T / |K_delta|.
  * Condensed: k = sum_qp omega_qp B^T Abar B with the stored Abar of the point.
  * Both [8][8] in the element's (node, direction) order. */
-static double q1_N(int a, int p) {
-    static const int sx[4] = {-1, 1, 1, -1}, sy[4] = {-1, -1, 1, 1};
-    double g = 1.0 / sqrt(3.0), xi = sx[p] * g, eta = sy[p] * g;
-    return 0.25 * (1 + sx[a] * xi) * (1 + sy[a] * eta);
-}
-
 int oracle_macro_element_stiffness(const oracle_macro* m, int e, int literal, double* k) {
     if (e < 0 || e >= m->nelem) return -1;
     memset(k, 0, sizeof(double) * 64);
-    for (int p = 0; p < 4; ++p) {
-        const int q = 4 * e + p;
+    for (int p = 0; p < m->npt; ++p) {
+        const int q = m->npt * e + p;
         if (literal) {
             double G[8 * 4], t[8 * 2], kT[64];
             for (int a = 0; a < 4; ++a)
@@ -325,8 +338,8 @@ int oracle_macro_element_stiffness(const oracle_macro* m, int e, int literal, do
                     const int j = 2 * a + i;
                     for (int c = 0; c < 4; ++c) G[j * 4 + c] = 0.0;
                     for (int J = 0; J < 2; ++J) G[j * 4 + i * 2 + J] = m->dN[p][a][J];
-                    t[j * 2 + 0] = i == 0 ? q1_N(a, p) : 0.0;
-                    t[j * 2 + 1] = i == 1 ? q1_N(a, p) : 0.0;
+                    t[j * 2 + 0] = i == 0 ? m->Nv[p][a] : 0.0;
+                    t[j * 2 + 1] = i == 1 ? m->Nv[p][a] : 0.0;
                 }
             int st = oracle_rve_transfer_states(2, m->desc.n, m->desc.phase, m->desc.lame, m->Fq + 4 * q,
                                                 m->wq + (size_t)q * m->nw, 8, G, t, kT);

@@ -130,6 +130,8 @@ typedef struct {
     int n;                 /* RVE elements per edge (2D only) */
     const uint8_t* phase;  /* n^2 phases shared by every RVE */
     const double* lame;    /* [nphase][2] */
+    int elem;              /* macro elements: 0 Q1 with 2x2 Gauss points; 1 P1 triangles (each grid cell split
+                              along its (0,0)-(1,1) diagonal, one point per triangle) */
 } oracle_macro_desc;
 
 typedef struct oracle_macro oracle_macro;

@@ -23,8 +23,9 @@ namespace {
 constexpr int NTB = 1024;  // threads of the banded solver
 
 struct MacroGeom {
-    double dN[4][4][2];  // [gp][node][dir]
-    double wdet;
+    double dN[4][4][2];  // [point][node][dir]
+    double wdet;         // weight of each point
+    int npt;             // points per grid cell: 4 (Q1, 2x2 Gauss) or 2 (P1 triangles)
 };
 
 // F at every Gauss point: F = I + sum_a u_a (x) grad N_a
@@ -32,8 +33,8 @@ __global__ void macro_gather_F(const int* __restrict__ conn, int nelem, const do
                                double* __restrict__ F, const int* __restrict__ done) {
     if (*done) return;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= 4 * nelem) return;
-    const int e = q >> 2, gp = q & 3;
+    if (q >= g.npt * nelem) return;
+    const int e = q / g.npt, gp = q % g.npt;
     double f[4] = {1.0, 0.0, 0.0, 1.0};
     for (int a = 0; a < 4; ++a) {
         const int v = conn[4 * e + a];
@@ -51,9 +52,9 @@ __global__ void macro_element(int nelem, const double* __restrict__ P, const dou
     if (t >= nelem * 8) return;
     const int e = t >> 3, r = t & 7, a = r >> 1, i = r & 1;
     double fr = 0.0, kr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int gp = 0; gp < 4; ++gp) {
-        const double* Pq = P + 4 * (4 * e + gp);
-        const double* Aq = A + 16 * (4 * e + gp);
+    for (int gp = 0; gp < g.npt; ++gp) {
+        const double* Pq = P + 4 * (g.npt * e + gp);
+        const double* Aq = A + 16 * (g.npt * e + gp);
         for (int J = 0; J < 2; ++J) fr += Pq[i * 2 + J] * g.dN[gp][a][J] * g.wdet;
         for (int b = 0; b < 4; ++b)
             for (int k = 0; k < 2; ++k) {
@@ -612,6 +613,8 @@ int fehmm_create(const fehmm_desc* d, fehmm* out) {
         return set_error(RVE_EINVAL, "fehmm_create: bad macro grid");
     if (d->bc != FEHMM_BC_CLAMPED_PULL && d->bc != FEHMM_BC_UNIAXIAL)
         return set_error(RVE_EINVAL, "fehmm_create: unknown boundary condition");
+    if (d->elem != FEHMM_ELEM_Q1 && d->elem != FEHMM_ELEM_P1)
+        return set_error(RVE_EINVAL, "fehmm_create: unknown macro element kind");
     if (d->scheme != FEHMM_NESTED && d->scheme != FEHMM_ALTERNATING)
         return set_error(RVE_EINVAL, "fehmm_create: unknown scheme");
     if (d->nsteps < 1 || !(d->rtol_macro > 0) || d->max_macro_iter < 1 || d->max_macro_iter > FEHMM_MAX_HIST - 1)
@@ -632,8 +635,23 @@ int fehmm_create(const fehmm_desc* d, fehmm* out) {
     h->desc = *d;
     const int nx = d->nx, ny = d->ny;
     const double hx = d->Lx / nx, hy = d->Ly / ny;
-    // Q1 gradients at the 2 x 2 Gauss points of a rectangle hx x hy
-    {
+    // shape gradients at the integration points of a rectangle hx x hy: Q1 at
+    // its 2 x 2 Gauss points, or the P1 triangles (0,1,2), (0,2,3) of the
+    // counter-clockwise cell nodes, one point each (constant gradients)
+    std::memset(h->geom.dN, 0, sizeof(h->geom.dN));
+    if (d->elem == FEHMM_ELEM_P1) {
+        h->geom.npt = 2;
+        h->geom.dN[0][0][0] = -1.0 / hx;
+        h->geom.dN[0][1][0] = 1.0 / hx;
+        h->geom.dN[0][1][1] = -1.0 / hy;
+        h->geom.dN[0][2][1] = 1.0 / hy;
+        h->geom.dN[1][0][1] = -1.0 / hy;
+        h->geom.dN[1][2][0] = 1.0 / hx;
+        h->geom.dN[1][3][0] = -1.0 / hx;
+        h->geom.dN[1][3][1] = 1.0 / hy;
+        h->geom.wdet = 0.5 * hx * hy;
+    } else {
+        h->geom.npt = 4;
         const int sx[4] = {-1, 1, 1, -1}, sy[4] = {-1, -1, 1, 1};
         const double g = 1.0 / std::sqrt(3.0);
         for (int p = 0; p < 4; ++p) {
@@ -679,7 +697,7 @@ int fehmm_create(const fehmm_desc* d, fehmm* out) {
                 h->colour[(i & 1) + 2 * (j & 1)].push_back(e);
             }
     h->ndof = 2 * h->nnode;
-    h->nqp = 4 * h->nelem;
+    h->nqp = h->geom.npt * h->nelem;
     h->fixed.assign(h->ndof, 0);
     for (int j = 0; j <= ny; ++j)
         for (int i = 0; i <= nx; ++i) {

@@ -10,6 +10,7 @@ from . import rve
 HEADER = os.path.join(os.path.dirname(rve.HERE), "include", "fehmm.h")
 BC_CLAMPED_PULL, BC_UNIAXIAL = 0, 1
 NESTED, ALTERNATING = 0, 1
+ELEM_Q1, ELEM_P1 = 0, 1
 STEP_CONVERGED, STEP_NOCONV, STEP_RVE_FAILED = 0, 1, 2
 MAX_HIST = 64
 
@@ -18,7 +19,7 @@ class Desc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("Lx", C.c_double), ("Ly", C.c_double),
                 ("hole_r", C.c_double), ("bc", C.c_int32), ("stretch", C.c_double), ("nsteps", C.c_int32),
                 ("rtol_macro", C.c_double), ("max_macro_iter", C.c_int32), ("scheme", C.c_int32),
-                ("micro", C.c_void_p), ("micro_opts", rve.Opts)]
+                ("micro", C.c_void_p), ("micro_opts", rve.Opts), ("elem", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -59,11 +60,11 @@ class Driver:
     """FE-HMM macro driver over one RVE mesh (kept alive by the driver)."""
 
     def __init__(self, mesh, nx, ny, Lx=1.0, Ly=1.0, hole_r=0.0, bc=BC_CLAMPED_PULL, stretch=1.1, nsteps=10,
-                 rtol_macro=1e-10, max_macro_iter=30, scheme=NESTED, micro_opts=None):
+                 rtol_macro=1e-10, max_macro_iter=30, scheme=NESTED, micro_opts=None, elem=ELEM_Q1):
         self.mesh = mesh
         o = micro_opts if micro_opts is not None else rve.default_opts()
         self.desc = Desc(nx, ny, Lx, Ly, hole_r, bc, stretch, nsteps, rtol_macro, max_macro_iter, scheme,
-                         mesh.h.value, o)
+                         mesh.h.value, o, int(elem))
         h = C.c_void_p()
         rve.check(lib().fehmm_create(C.byref(self.desc), C.byref(h)), "fehmm_create")
         self.h = h

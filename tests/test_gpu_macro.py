@@ -145,3 +145,26 @@ def test_graph_step_matches_eager(scheme):
         assert sa["macro_iters"] == sb["macro_iters"] and sa["micro_iters"] == sb["micro_iters"]
         assert np.array_equal(sa["res_hist"], sb["res_hist"])
         assert np.array_equal(a.u(), b.u()), k
+
+
+@pytest.mark.parametrize("scheme", [fehmm.NESTED, fehmm.ALTERNATING])
+def test_p1_macro_parity(scheme):
+    """P1 macro triangles (Sec. 3.1 macro spaces; each cell split along its
+    (0,0)-(1,1) diagonal, one point per triangle) against the oracle's driver."""
+    need_gpu()
+    print(f"case P1 macro 4x4, RVE 8x8, scheme {scheme}", flush=True)
+    lame = rve.two_phase_lame(10.0)
+    n, r = 8, 0.25
+    mesh = rve.Mesh(2, n, lame, radius=r)
+    drv = fehmm.Driver(mesh, 4, 4, bc=fehmm.BC_CLAMPED_PULL, stretch=1.1, nsteps=3, scheme=scheme,
+                       elem=fehmm.ELEM_P1)
+    orc = oracle.Macro(4, 4, n, oracle.phase_by_centroid(2, n, r), oracle.two_phase_lame(10.0), bc=0, stretch=1.1,
+                       nsteps=3, scheme=scheme, elem=1)
+    assert drv.nqp == orc.nqp == 32
+    for k in (1, 2, 3):
+        g, o = drv.step(k), orc.step(k)
+        assert g["status"] == 0 and o["status"] == 0 and g["macro_iters"] == o["macro_iters"]
+        uo = match_u(drv.nodes(), drv.u(), orc.nodes(), orc.u())
+        assert np.abs(drv.u() - uo).max() <= 1e-8 * np.abs(uo).max()
+    drv.destroy()
+    orc.close()

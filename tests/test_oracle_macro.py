@@ -8,7 +8,33 @@ from tests import fe_ref
 LAME = oracle.two_phase_lame(10.0)
 
 
-def single_scale_fe(nx, ny, lam, mu, stretch, nsteps, bc, through_solve=False, hist=None):
+def _cell_points(elem, hx, hy):
+    """Integration points of one cell: (gradients [4 nodes, 2], weight) each.
+    Q1: 2x2 Gauss; P1: the triangles (0,1,2) and (0,2,3) of the counter-clockwise
+    cell nodes, gradients from the inverted edge matrix of the vertex coordinates."""
+    X = np.array([[0.0, 0.0], [hx, 0.0], [hx, hy], [0.0, hy]])
+    pts = []
+    if elem == 0:
+        g = 1 / np.sqrt(3)
+        sx, sy = np.array([-1, 1, 1, -1]), np.array([-1, -1, 1, 1])
+        for xi, eta in [(-g, -g), (g, -g), (g, g), (-g, g)]:
+            dN = np.zeros((4, 2))
+            dN[:, 0] = 0.25 * sx * (1 + sy * eta) * 2 / hx
+            dN[:, 1] = 0.25 * sy * (1 + sx * xi) * 2 / hy
+            pts.append((dN, hx * hy / 4))
+    else:
+        for tri in ((0, 1, 2), (0, 2, 3)):
+            E = np.array([X[tri[1]] - X[tri[0]], X[tri[2]] - X[tri[0]]]).T
+            Gi = np.linalg.inv(E)
+            G = np.vstack([-Gi.sum(axis=0), Gi])
+            dN = np.zeros((4, 2))
+            for k, a in enumerate(tri):
+                dN[a] = G[k]
+            pts.append((dN, abs(np.linalg.det(E)) / 2))
+    return pts
+
+
+def single_scale_fe(nx, ny, lam, mu, stretch, nsteps, bc, through_solve=False, hist=None, elem=0):
     """Independent dense single-scale Q1 neo-Hookean FE with the same BCs.
     through_solve: the step's prescribed increment enters the first Newton
     iteration as an inhomogeneous Dirichlet condition of the linear system
@@ -19,13 +45,7 @@ def single_scale_fe(nx, ny, lam, mu, stretch, nsteps, bc, through_solve=False, h
     xy = np.array([[i * hx, j * hy] for j in range(ny + 1) for i in range(nx + 1)])
     conn = np.array([[j * (nx + 1) + i, j * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i]
                      for j in range(ny) for i in range(nx)])
-    g = 1 / np.sqrt(3)
-    sx, sy = np.array([-1, 1, 1, -1]), np.array([-1, -1, 1, 1])
-    dN = np.zeros((4, 4, 2))
-    for p, (xi, eta) in enumerate([(-g, -g), (g, -g), (g, g), (-g, g)]):
-        dN[p, :, 0] = 0.25 * sx * (1 + sy * eta) * 2 / hx
-        dN[p, :, 1] = 0.25 * sy * (1 + sx * xi) * 2 / hy
-    wdet = hx * hy / 4
+    pts = _cell_points(elem, hx, hy)
     fixed = np.zeros(2 * nn, bool)
     for v, (x, y) in enumerate(xy):
         if x == 0:
@@ -49,12 +69,12 @@ def single_scale_fe(nx, ny, lam, mu, stretch, nsteps, bc, through_solve=False, h
             R = np.zeros(2 * nn); K = np.zeros((2 * nn, 2 * nn))
             for e in conn:
                 dofs = np.ravel([[2 * a, 2 * a + 1] for a in e])
-                for p in range(4):
-                    F = np.eye(2) + np.einsum("ai,aJ->iJ", u[dofs].reshape(4, 2), dN[p])
+                for dN, wdet in pts:
+                    F = np.eye(2) + np.einsum("ai,aJ->iJ", u[dofs].reshape(4, 2), dN)
                     P = fe_ref.P_closed(F, lam, mu)
                     A = fe_ref.A_closed(F, lam, mu).reshape(2, 2, 2, 2)
-                    R[dofs] += np.einsum("iJ,aJ->ai", P, dN[p]).ravel() * wdet
-                    K[np.ix_(dofs, dofs)] += np.einsum("aJ,iJkL,bL->aibk", dN[p], A, dN[p]).reshape(8, 8) * wdet
+                    R[dofs] += np.einsum("iJ,aJ->ai", P, dN).ravel() * wdet
+                    K[np.ix_(dofs, dofs)] += np.einsum("aJ,iJkL,bL->aibk", dN, A, dN).reshape(8, 8) * wdet
             free = ~fixed
             if it == 0:
                 R[free] += K[np.ix_(free, fixed)] @ dud[fixed]
@@ -179,3 +199,50 @@ def test_holed_plate_mesh_counts():
     want = {(i, j) for j, i in zip(*np.nonzero(used))}
     assert got == want
     m.close()
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_p1_macro_triangles_equal_single_scale_fe(bc):
+    """P1 macro triangles (each grid cell split along its (0,0)-(1,1) diagonal,
+    one point per triangle, Sec. 3.1 macro spaces): with a one-phase RVE the
+    FE-HMM solution is the single-scale P1 FE solution, residual history by
+    residual history, and the literal transfer equals B^T Abar B."""
+    nx = ny = 3
+    m = oracle.Macro(nx, ny, 2, np.zeros(4, np.uint8), LAME, bc=bc, stretch=1.1, nsteps=2, rtol_macro=1e-12,
+                     elem=1)
+    assert m.nqp == 2 * nx * ny
+    hist = []
+    xy_ref, u_ref = single_scale_fe(nx, ny, *LAME[0], 1.1, 2, bc, through_solve=True, hist=hist, elem=1)
+    for k in (1, 2):
+        st = m.step(k)
+        assert st["status"] == 0 and st["macro_iters"] == len(hist[k - 1]) - 1
+    xy = m.nodes()
+    order = [int(np.argmin(np.abs(xy_ref - p).sum(axis=1))) for p in xy]
+    u_ref = u_ref.reshape(-1, 2)[order].reshape(-1)
+    assert np.abs(m.u() - u_ref).max() < 1e-10 * np.abs(u_ref).max()
+    # with the clamped edge the field is not affine and the P1 and Q1 solutions
+    # differ; under uniaxial stretch both spaces hold the uniform solution
+    _, u_q1 = single_scale_fe(nx, ny, *LAME[0], 1.1, 2, bc, through_solve=True)
+    diff = np.abs(u_q1.reshape(-1, 2)[order].reshape(-1) - u_ref).max()
+    if bc == 0:
+        assert diff > 1e-8 * np.abs(u_ref).max()
+    else:
+        assert diff < 1e-12 * np.abs(u_ref).max()
+    m.close()
+
+
+def test_p1_macro_literal_transfer_and_uniform_state():
+    n = 4
+    ph = oracle.phase_by_centroid(2, n, 0.3)
+    m = oracle.Macro(3, 3, n, ph, LAME, bc=0, stretch=1.1, nsteps=2, elem=1)
+    for k in (1, 2):
+        assert m.step(k)["status"] == 0
+    for e in range(m.nelem()):
+        kl, kc = m.element_stiffness(e, True), m.element_stiffness(e, False)
+        assert np.abs(kl - kc).max() <= 1e-11 * np.abs(kc).max()
+    m.close()
+    u = oracle.Macro(2, 2, n, ph, LAME, bc=1, stretch=1.08, nsteps=1, elem=1)
+    assert u.step(1)["status"] == 0
+    F, _, _ = u.qp()
+    assert np.abs(F - F[0]).max() < 1e-10 and F[0, 0, 0] == pytest.approx(1.08, abs=1e-12)
+    u.close()
