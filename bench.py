@@ -97,12 +97,12 @@ def kernel_source_hash():
     return hashlib.sha256(blob).hexdigest()[:16]
 
 
-def measured_traffic(workload, precision="fp64"):
+def measured_traffic(workload, precision="fp64", kernel="rve_solve_kernel"):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary of this workload, scaled by the copy-kernel calibration; None when
     the kernel sources changed since the counters were taken."""
     tag = "" if precision == "fp64" else "_" + precision
-    path = os.path.join(ROOT, "profiles", f"rve_solve_kernel_{workload}{tag}.hbm.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}{tag}.hbm.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -407,6 +407,7 @@ def assembly_block(s, wl, meta, reps=20):
     return {"kernel": f"rve_assembly_kernel<{d}>", "ms_per_launch": ms, "rves": B,
             "roofline": {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": ach / PEAK_HBM_GBS, "bytes_per_assembly": alg,
+                         "traffic": measured_traffic(meta["workload"], "fp64", "rve_assembly_kernel"),
                          "bytes_counted": "w + phase + R + symmetric node-block K (algorithmic)"},
             "moved_bytes_per_assembly": moved, "achieved_gbs_on_moved_bytes": ach_moved}
 
