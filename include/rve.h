@@ -219,23 +219,27 @@ int rve_solve_batch_static(rve_batch b, const double* F, double* P, double* A, d
  * Choices that shape the solve of one mesh size: the leaf size of the nested
  * dissection (largest leaf box, in nodes: front sizes and tree depth), the
  * largest front that one wave factors on its own (small subtrees run
- * wave-per-front, larger fronts use the whole workgroup), and the number of
- * persistent workgroups of a batch.  rve_autotune times candidates on the
- * caller's own deformation gradients and keeps the fastest for (ndim, n);
- * meshes and batches created afterwards use it.  Results stay within the
- * parity bar for any choice (only the elimination order changes). */
+ * wave-per-front, larger fronts use the whole workgroup), the number of
+ * persistent workgroups of a batch, and the workgroup size (four waves, or eight
+ * waves for 2D plans whose fronts live in LDS).  rve_autotune times candidates
+ * on the caller's own deformation gradients and keeps the fastest for (ndim,
+ * n); meshes and batches created afterwards use it.  Results stay within the
+ * parity bar for any choice (only the elimination order and the schedule
+ * change). */
 typedef struct {
     int32_t leaf;        /* 0: default (16 nodes in 2D, 27 in 3D) */
     int32_t wave_max_m;  /* 0 .. 64; 64 is the default */
     int32_t slots;       /* 0: default (min(B, 1024)) */
-    int32_t pad;
+    int32_t threads;     /* 0: by front size (eight waves when the fronts leave room for one four-wave
+                            workgroup per CU only), 256 or 512 */
     double ms;           /* measured time of the tuning batch (rve_autotune), else 0 */
 } rve_tuning;
 
 /* Times every candidate (leaf in {8, 16, 32} (2D) or {8, 27, 64} (3D), wave
- * limit in {0, 32, 64} where fronts fit LDS, slots in {512, 1024}) with
- * rve_solve_batch on nF RVEs of mesh m's microstructure driven by F (device,
- * [nF][d^2]) and options o, keeps the fastest for (ndim, n) and returns it in
+ * limit in {0, 32, 64} where fronts fit LDS, slots in {512, 1024}, threads in
+ * {256, 512} for 2D plans with fronts in LDS) with rve_solve_batch on nF RVEs
+ * of mesh m's microstructure driven by F (device, [nF][d^2]) and options o
+ * (timed in o's precision), keeps the fastest for (ndim, n) and returns it in
  * best.  Host-blocking; allocates its own buffers. */
 int rve_autotune(rve_mesh m, const double* F, int64_t nF, const rve_opts* o, rve_tuning* best, void* hip_stream);
 /* Current choice for (ndim, n) (defaults when untuned); set installs one (e.g.

@@ -102,6 +102,12 @@ int tuned_slots(int d, int n) {
     return it != g_tuning.end() ? it->second.slots : 0;
 }
 
+int tuned_threads(int d, int n) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tuning.find(std::make_pair(d, n));
+    return it != g_tuning.end() ? it->second.threads : 0;
+}
+
 template <typename T>
 int upload(const std::vector<T>& v, T** out) {
     size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
@@ -463,6 +469,7 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
             if (p->dev.lds_ok) rl = std::max(rl, p->rl_elems);
         bool glb = false;
         for (PlanEntry* p : plans) glb = glb || !p->dev.lds_ok;
+        const int threads = tuned_threads(d, meshes[0]->n);
         for (int k = 0; k < 2; ++k) {
             const int64_t es = k == 0 ? 8 : 4;
             int64_t elems = std::max(b->lds_front[k] + rl, NWAVE_ * b->wave_slice);
@@ -471,9 +478,12 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
             // condensation factorization of global-front plans is FP64)
             if (glb) bytes = std::max<int64_t>(bytes, (int64_t)kTileLdsElems * 8);
             b->dyn_bytes[k] = (size_t)bytes;
+            // eight waves: 2D plans with fronts in LDS, by default where the
+            // fronts leave room for one four-wave workgroup per CU only
             const int64_t wide_bytes = std::max(b->lds_front[k] + rl, 2 * NWAVE_ * b->wave_slice) * es;
-            b->wide[k] = d == 2 && !glb && bytes + nt256::lds_static_bytes() > kLdsBytesMax / 2 &&
-                         wide_bytes + nt512::lds_static_bytes() + 1024 <= kLdsBytesMax;
+            const bool wide_fits = d == 2 && !glb && wide_bytes + nt512::lds_static_bytes() + 1024 <= kLdsBytesMax;
+            const bool wide_rule = bytes + nt256::lds_static_bytes() > kLdsBytesMax / 2;
+            b->wide[k] = wide_fits && (threads == 512 || (threads == 0 && wide_rule));
             b->dyn_bytes_wide[k] = (size_t)wide_bytes;
         }
     }
@@ -769,7 +779,7 @@ int rve_tuning_get(int32_t ndim, int32_t n, rve_tuning* out) {
 int rve_tuning_set(int32_t ndim, int32_t n, const rve_tuning* t) {
     if (!t || !(ndim == 2 || ndim == 3) || n < 2) return fail(RVE_EINVAL, "rve_tuning_set: invalid argument");
     if (t->leaf < 0 || t->leaf > 4096 || t->wave_max_m < 0 || t->wave_max_m > kWaveFrontMaxM || t->slots < 0 ||
-        t->slots > 65536)
+        t->slots > 65536 || !(t->threads == 0 || t->threads == 256 || t->threads == 512))
         return fail(RVE_EINVAL, "rve_tuning_set: value out of range");
     std::lock_guard<std::mutex> lk(g_mu);
     g_tuning[std::make_pair((int)ndim, (int)n)] = *t;
@@ -825,10 +835,13 @@ int rve_autotune(rve_mesh m, const double* F, int64_t nF, const rve_opts* o, rve
             err = fail(RVE_EINVAL, std::string("rve_autotune: ") + ex.what());
             break;
         }
+        // eight-wave workgroups exist for 2D plans with fronts in LDS only
+        const std::vector<int> threads = lds && d == 2 ? std::vector<int>{256, 512} : std::vector<int>{0};
         for (int wave : waves) {
             if (!lds && wave != kWaveFrontMaxM) continue;
-            for (int sl : slots) {
-                rve_tuning cand{leaf, wave, sl, 0, 0.0};
+            for (size_t c = 0; c < slots.size() * threads.size() && !err; ++c) {
+                const int sl = slots[c / threads.size()], th = threads[c % threads.size()];
+                rve_tuning cand{leaf, wave, sl, th, 0.0};
                 if ((err = rve_tuning_set(d, n, &cand))) break;
                 rve_mesh_desc md{};
                 md.ndim = d;
@@ -860,7 +873,7 @@ int rve_autotune(rve_mesh m, const double* F, int64_t nF, const rve_opts* o, rve
                 rve_batch_destroy(cb);
                 rve_mesh_destroy(cm);
                 if (err) break;
-                if (ms_best < win.ms) win = rve_tuning{leaf, wave, sl, 0, (double)ms_best};
+                if (ms_best < win.ms) win = rve_tuning{leaf, wave, sl, th, (double)ms_best};
             }
             if (err) break;
         }

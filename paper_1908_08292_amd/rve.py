@@ -42,7 +42,7 @@ class Opts(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("leaf", C.c_int32), ("wave_max_m", C.c_int32), ("slots", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("leaf", C.c_int32), ("wave_max_m", C.c_int32), ("slots", C.c_int32), ("threads", C.c_int32),
                 ("ms", C.c_double)]
 
 
@@ -128,7 +128,7 @@ def two_phase_lame(ratio, E=1.0, nu=0.3):
 
 
 def _tuning_dict(t):
-    return dict(leaf=t.leaf, wave_max_m=t.wave_max_m, slots=t.slots, ms=t.ms)
+    return dict(leaf=t.leaf, wave_max_m=t.wave_max_m, slots=t.slots, threads=t.threads, ms=t.ms)
 
 
 def tuning_get(d, n):
@@ -137,8 +137,8 @@ def tuning_get(d, n):
     return _tuning_dict(t)
 
 
-def tuning_set(d, n, leaf=0, wave_max_m=64, slots=0):
-    t = Tuning(leaf, wave_max_m, slots, 0, 0.0)
+def tuning_set(d, n, leaf=0, wave_max_m=64, slots=0, threads=0):
+    t = Tuning(leaf, wave_max_m, slots, threads, 0.0)
     check(lib().rve_tuning_set(d, n, C.byref(t)), "rve_tuning_set")
 
 

@@ -245,7 +245,7 @@ def test_tuned_plans_drive_a_correct_multifrontal_solve(d, n, leaf, wave):
         assert np.abs(x[d:] - ref).max() < 1e-9 * np.abs(ref).max()
     finally:
         rve.tuning_reset(d, n)
-    assert rve.tuning_get(d, n) == dict(leaf=0, wave_max_m=64, slots=0, ms=0.0)
+    assert rve.tuning_get(d, n) == dict(leaf=0, wave_max_m=64, slots=0, threads=0, ms=0.0)
 
 
 def test_tuning_validation():
@@ -253,6 +253,13 @@ def test_tuning_validation():
         rve.tuning_set(2, 8, leaf=-1)
     with pytest.raises(rve.RveError):
         rve.tuning_set(2, 8, wave_max_m=65)
+    with pytest.raises(rve.RveError):
+        rve.tuning_set(2, 8, threads=384)
+    rve.tuning_set(2, 8, threads=512)
+    try:
+        assert rve.tuning_get(2, 8)["threads"] == 512
+    finally:
+        rve.tuning_reset(2, 8)
     with pytest.raises(rve.RveError):
         rve.tuning_get(4, 8)
     assert "rve_autotune" in rve.declared_functions()

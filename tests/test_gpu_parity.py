@@ -256,9 +256,27 @@ def test_autotuned_plan_matches_oracle():
     try:
         print("tuned:", t)
         assert t["leaf"] in (8, 16, 32) and t["wave_max_m"] in (0, 32, 64) and t["slots"] in (512, 1024)
+        assert t["threads"] in (256, 512)
         assert t["ms"] > 0
         assert rve.tuning_get(d, n)["leaf"] == t["leaf"]
         out = run_gpu(d, np.full(B, n), np.full(B, 0.25), np.full(B, 10.0), F)
         compare(d, np.full(B, n), np.full(B, 0.25), np.full(B, 10.0), F, out, idx=range(0, B, 8))
+    finally:
+        rve.tuning_reset(d, n)
+
+
+@pytest.mark.parametrize("n,threads", [(8, 512), (32, 256)])
+def test_workgroup_size_choice_matches_oracle(n, threads):
+    """Either workgroup size runs every mesh whose fronts fit LDS: eight waves on a
+    small mesh (four by default) and four waves on the 32 x 32 mesh (eight by
+    default) meet the parity bar."""
+    torch_cuda()
+    d, B = 2, 64
+    F = workloads.draw_F(np.random.default_rng(43 + n), B, d, 0.15)
+    rve.tuning_set(d, n, threads=threads)
+    print(f"case 2d n={n} B={B} threads={threads}", flush=True)
+    try:
+        out = run_gpu(d, np.full(B, n), np.full(B, 0.3), np.full(B, 10.0), F)
+        compare(d, np.full(B, n), np.full(B, 0.3), np.full(B, 10.0), F, out, idx=range(0, B, 4))
     finally:
         rve.tuning_reset(d, n)
