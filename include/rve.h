@@ -137,7 +137,14 @@ int rve_batch_destroy(rve_batch b);
 int rve_batch_state_offsets(rve_batch b, int64_t* host_off /* [B+1] */);
 
 #define RVE_PREC_FP64 0
-#define RVE_PREC_FP32_IR 1 /* FP32 factorization, FP64 residuals + refinement */
+/* FP32: the Newton element tangents are stored in FP32 and factored in FP32 (MFMA
+ * trailing updates); the Newton residual, its norm, the det F guard and the
+ * refinement residual b - K x stay FP64, with K x applied matrix-free by the
+ * element kernel in FP64 (no FP64 matrix is stored); the tangent condensation
+ * takes FP64 element tangents of the converged state.  (The paper's method is
+ * FP64 throughout; this is an acceleration whose outputs meet the FP64 bar:
+ * Newton counts may differ by one from the FP64 solve's.) */
+#define RVE_PREC_FP32_IR 1 /* FP32 assembly and factorization, FP64 residuals + refinement */
 
 typedef struct {
     double rtol;           /* Newton: stop when ||R_f||_2 <= rtol ||R_f^0||_2 + atol */

@@ -34,6 +34,8 @@
 // substitution walks the fronts in reverse.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "mesh_common.h"
 #include "solver_dev.h"
 
@@ -135,6 +137,7 @@ struct RveCtx {
     int d, n, ne, nn, nen, nd;
     int law;  // RVE_LAW_*: 0 neo-Hookean, 1 St. Venant-Kirchhoff, 2 fully linear
     int elem; // RVE_ELEM_*: 0 Q1 / hex8 with 2^d Gauss points, 1 P1 (d! Kuhn simplices per cell)
+    int ke32; // Newton element tangents stored in FP32 (FP32 factors); FP64 at the converged state
     const uint8_t* phase;
     const double* lame;
     double* w;
@@ -258,6 +261,60 @@ __device__ inline void load_wl(const RveCtx& c, const double* w, int e, double* 
         for (int i = 0; i < D; ++i) wl[b * D + i] = w[nodes[b] * D + i];
 }
 
+// Outputs of an element pass work item (element e, rows row0 .. row0 + RPI - 1):
+// mode 0 the internal forces and tangent rows (FP32 when c.ke32, the factors'
+// input); mode 2 the Y rows and, when c.ke32, the FP64 tangent rows at the
+// converged state (the condensation's input); mode 3 the FP64 product of the
+// tangent rows with xv at the element's nodes, into the force slots.
+template <int D, int RPI>
+__device__ inline void element_store(const RveCtx& c, int e, int row0, int mode, const double (&fr)[RPI],
+                                     const double (&kr)[RPI][(1 << D) * D], const double (&yr)[RPI][D * D],
+                                     const double* xv, const int* nodes) {
+    constexpr int NEN = 1 << D, ND = NEN * D, D2 = D * D;
+    if (mode == 0) {
+#pragma unroll
+        for (int r = 0; r < RPI; ++r) {
+            const int64_t row = (int64_t)e * ND + row0 + r;
+            c.fe[row] = fr[r];
+            if (c.ke32) {
+                float* kd = reinterpret_cast<float*>(c.ke) + row * ND;
+#pragma unroll
+                for (int q = 0; q < ND; ++q) kd[q] = (float)kr[r][q];
+            } else {
+                double* kd = c.ke + row * ND;
+#pragma unroll
+                for (int q = 0; q < ND; ++q) kd[q] = kr[r][q];
+            }
+        }
+    } else if (mode == 2) {
+#pragma unroll
+        for (int r = 0; r < RPI; ++r) {
+            const int64_t row = (int64_t)e * ND + row0 + r;
+            double* yd = c.re + row * D2;
+#pragma unroll
+            for (int q = 0; q < D2; ++q) yd[q] = yr[r][q];
+            if (c.ke32) {
+                double* kd = c.ke + row * ND;
+#pragma unroll
+                for (int q = 0; q < ND; ++q) kd[q] = kr[r][q];
+            }
+        }
+    } else if (mode == 3) {
+        double xl[ND];
+#pragma unroll
+        for (int b = 0; b < NEN; ++b)
+#pragma unroll
+            for (int k = 0; k < D; ++k) xl[b * D + k] = xv[nodes[b] * D + k];
+#pragma unroll
+        for (int r = 0; r < RPI; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < ND; ++q) s += kr[r][q] * xl[q];
+            c.fe[(int64_t)e * ND + row0 + r] = s;
+        }
+    }
+}
+
 // Element pass of the St. Venant-Kirchhoff and fully linear laws: as
 // element_pass_nh, with P and A evaluated at each Gauss point (law_PA) and the rows
 // contracted with the material gradients,
@@ -265,7 +322,7 @@ __device__ inline void load_wl(const RveCtx& c, const double* w, int e, double* 
 //     Y_(a,i),(kL) = sum dN_a,J A_iJkL w|J|.
 template <int D, int NPT>
 __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP,
-                                              double* accA) {
+                                              double* accA, const double* xv) {
     constexpr int NEN = 1 << D, ND = NEN * D, D2 = D * D, RPI = (D == 2) ? 2 : 1;
     const int nitems = c.ne * NEN * (D / RPI);
     const double wJ = sm.wJ;
@@ -313,6 +370,8 @@ __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const d
 #pragma unroll
                     for (int Jj = 0; Jj < D; ++Jj) f += Pg[i * D + Jj] * dNa[Jj];
                     fr[r] += f * wJ;
+                }
+                if (mode == 0 || mode == 3 || (mode == 2 && c.ke32)) {
 #pragma unroll
                     for (int b = 0; b < NEN; ++b) {
                         const double* dNb = &sm.dN[(gp * 8 + b) * 3];
@@ -326,7 +385,8 @@ __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const d
                             kr[r][b * D + k] += v * wJ;
                         }
                     }
-                } else {
+                }
+                if (mode == 2) {
 #pragma unroll
                     for (int k = 0; k < D; ++k)
 #pragma unroll
@@ -339,33 +399,17 @@ __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const d
                 }
             }
         }
-        if (mode == 0) {
-#pragma unroll
-            for (int r = 0; r < RPI; ++r) {
-                const int row = a * D + i0 + r;
-                c.fe[(int64_t)e * ND + row] = fr[r];
-                double* kd = c.ke + ((int64_t)e * ND + row) * ND;
-#pragma unroll
-                for (int q = 0; q < ND; ++q) kd[q] = kr[r][q];
-            }
-        } else if (mode == 2) {
-#pragma unroll
-            for (int r = 0; r < RPI; ++r) {
-                const int row = a * D + i0 + r;
-                double* yd = c.re + ((int64_t)e * ND + row) * D2;
-#pragma unroll
-                for (int q = 0; q < D2; ++q) yd[q] = yr[r][q];
-            }
-        }
+        element_store<D, RPI>(c, e, a * D + i0, mode, fr, kr, yr, xv, nodes);
     }
 }
 
 // Element pass of the neo-Hookean law.  mode 0: residual + tangent rows
 // (Newton); mode 1: J > 0 check only (on w); mode 2: final outputs (Pbar, <A>,
-// Y rows).  Work item = (e, a) in 2D (rows i = 0,1), (e, a, i) in 3D.
+// Y rows); mode 3: the FP64 tangent applied to xv, matrix-free (refinement of
+// FP32 solves).  Work item = (e, a) in 2D (rows i = 0,1), (e, a, i) in 3D.
 template <int D, int NPT>
 __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP,
-                                             double* accA) {
+                                             double* accA, const double* xv) {
     constexpr int NEN = 1 << D, ND = NEN * D, RPI = (D == 2) ? 2 : 1;
     const int nitems = c.ne * NEN * (D / RPI);
     const double wJ = sm.wJ;
@@ -441,6 +485,8 @@ __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const do
 #pragma unroll
                     for (int Jj = 0; Jj < D; ++Jj) FdN += F[i * D + Jj] * dNa[Jj];
                     fr[r] += (mu * FdN - c1 * ga[i]) * wJ;
+                }
+                if (mode == 0 || mode == 3 || (mode == 2 && c.ke32)) {
 #pragma unroll
                     for (int b = 0; b < NEN; ++b) {
                         double dab = 0.0;
@@ -450,7 +496,8 @@ __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const do
                         for (int k = 0; k < D; ++k)
                             kr[r][b * D + k] += ((i == k ? mu * dab : 0.0) + c1 * ga[k] * g[b][i] + c2 * ga[i] * g[b][k]) * wJ;
                     }
-                } else {
+                }
+                if (mode == 2) {
 #pragma unroll
                     for (int k = 0; k < D; ++k)
 #pragma unroll
@@ -460,38 +507,36 @@ __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const do
                 }
             }
         }
-        if (mode == 0) {
-#pragma unroll
-            for (int r = 0; r < RPI; ++r) {
-                const int row = a * D + i0 + r;
-                c.fe[(int64_t)e * ND + row] = fr[r];
-                double* kd = c.ke + ((int64_t)e * ND + row) * ND;
-#pragma unroll
-                for (int q = 0; q < ND; ++q) kd[q] = kr[r][q];
-            }
-        } else if (mode == 2) {
-#pragma unroll
-            for (int r = 0; r < RPI; ++r) {
-                const int row = a * D + i0 + r;
-                double* yd = c.re + ((int64_t)e * ND + row) * (D * D);
-#pragma unroll
-                for (int q = 0; q < D * D; ++q) yd[q] = yr[r][q];
-            }
-        }
+        element_store<D, RPI>(c, e, a * D + i0, mode, fr, kr, yr, xv, nodes);
     }
 }
 
 // the element pass of the RVE's law (neo-Hookean closed forms, or the generic
 // path) and element kind (2^d Gauss points of Q1 / hex8, or d! P1 simplices)
 template <int D>
-__device__ inline void element_pass(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP, double* accA) {
+__device__ inline void element_pass(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP, double* accA,
+                                    const double* xv = nullptr) {
     constexpr int NQ1 = 1 << D, NP1 = D == 2 ? 2 : 6;
     if (c.elem == 0) {
-        if (c.law != 0) element_pass_law<D, NQ1>(c, sm, w, mode, accP, accA);
-        else element_pass_nh<D, NQ1>(c, sm, w, mode, accP, accA);
+        if (c.law != 0) element_pass_law<D, NQ1>(c, sm, w, mode, accP, accA, xv);
+        else element_pass_nh<D, NQ1>(c, sm, w, mode, accP, accA, xv);
     } else {
-        if (c.law != 0) element_pass_law<D, NP1>(c, sm, w, mode, accP, accA);
-        else element_pass_nh<D, NP1>(c, sm, w, mode, accP, accA);
+        if (c.law != 0) element_pass_law<D, NP1>(c, sm, w, mode, accP, accA, xv);
+        else element_pass_nh<D, NP1>(c, sm, w, mode, accP, accA, xv);
+    }
+}
+
+// out = b - K x on the free dofs (0 on the pinned ones), from the element
+// products k_e x_e that element pass mode 3 left in the force slots
+template <int D>
+__device__ void residual_act(const RveCtx& c, const double* b, double* out) {
+    constexpr int NEN = 1 << D, ND = NEN * D;
+    for (int vi = threadIdx.x; vi < c.nn * D; vi += NT) {
+        const int v = vi / D, i = vi % D;
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < NEN; ++a) s += c.fe[(int64_t)element_of_node(D, c.n, v, a) * ND + a * D + i];
+        out[vi] = is_pinned(*c.plan, v) ? 0.0 : b[vi] - s;
     }
 }
 
@@ -510,6 +555,15 @@ __device__ void node_gather(const RveCtx& c, const double* src, int nc, double* 
         }
         out[t] = sign * s;
     }
+}
+
+// The element tangents a factorization with NRHS right-hand sides reads: the
+// Newton factorizations (one rhs) read them in the factor type (FP32 for FP32
+// factors), the condensation factorizations (d^2 rhs) in FP64.  (The global
+// path factors the condensation in FP64 and passes NRHS = 1 with T = double.)
+template <int NRHS, typename T>
+__device__ inline const typename std::conditional<NRHS == 1, T, double>::type* ke_of(const RveCtx& c) {
+    return reinterpret_cast<const typename std::conditional<NRHS == 1, T, double>::type*>(c.ke);
 }
 
 // ---------------------------------------------------------------- LDS fronts
@@ -902,7 +956,8 @@ __device__ __attribute__((noinline)) void factorize_glb(const RveCtx& c, Smem& s
             double v = 0;
 #pragma unroll
             for (int q = 0; q < NEN; ++q) {
-                const double kv = c.ke[((int64_t)cbs[q].elem * ND + cbs[q].lb * D + k) * ND + cbs[q].la * D + l];
+                const double kv = (double)ke_of<1, T>(c)[((int64_t)cbs[q].elem * ND + cbs[q].lb * D + k) * ND +
+                                                         cbs[q].la * D + l];
                 v += (q < kp.c_count) ? kv : 0.0;
             }
             Fp[(int64_t)col * m + r] = (T)v;
@@ -1227,8 +1282,8 @@ __device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& s
 // caller's lane (wave-level) or thread (workgroup-level) numbering.  D0 (LDS)
 // receives the original diagonal of the pivot columns, the scale of the
 // vanishing-pivot test.
-template <int NEN, typename T>
-__device__ inline void gather_original(const DevPlan& pl, const double* ke, int a0, int a1, int first, int stride,
+template <int NEN, typename KT, typename T>
+__device__ inline void gather_original(const DevPlan& pl, const KT* ke, int a0, int a1, int first, int stride,
                                        T* F, int m, T* D0) {
     for (int t0 = a0 + first; t0 < a1; t0 += 4 * stride) {
         int rc[4], src[4][NEN];
@@ -1245,7 +1300,7 @@ __device__ inline void gather_original(const DevPlan& pl, const double* ke, int 
             v[u] = 0.0;
 #pragma unroll
             for (int q = 0; q < NEN; ++q) {
-                const double kv = ke[max(src[u][q], 0)];
+                const double kv = (double)ke[max(src[u][q], 0)];
                 v[u] += (src[u][q] >= 0) ? kv : 0.0;
             }
         }
@@ -1320,7 +1375,7 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
     }
     __builtin_amdgcn_wave_barrier();
     T* const D0 = rl + m * NRHS;
-    gather_original<NEN>(pl, c.ke, fr.asm_begin, fr.asm_end, lane, 64, F, m, D0);
+    gather_original<NEN>(pl, ke_of<NRHS, T>(c), fr.asm_begin, fr.asm_end, lane, 64, F, m, D0);
     __builtin_amdgcn_wave_barrier();
     for (int q = fr.child_begin; q < fr.child_end; ++q) {
         const DevFront ch = pl.fronts[pl.children[q]];
@@ -1510,7 +1565,7 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
     __syncthreads();
     // original entries: one gather level, every source load in flight at once
     T* const D0 = rl + m * nrhs;  // original diagonal, after the rhs rows
-    gather_original<NEN>(pl, c.ke, fr.asm_begin, fr.asm_end, gt, GT, F, m, D0);
+    gather_original<NEN>(pl, ke_of<NRHS, T>(c), fr.asm_begin, fr.asm_end, gt, GT, F, m, D0);
     __syncthreads();
     for (int q = fr.child_begin; q < fr.child_end; ++q) {
         const DevFront ch = pl.fronts[pl.children[q]];
@@ -2139,6 +2194,7 @@ __device__ inline void rve_setup(const SolveArgs& a, int rve, double* base, RveC
     const int kind = a.rve_kind ? a.rve_kind[rve] : 0;
     c.law = kind & 0xff;
     c.elem = (kind >> 8) & 0xff;
+    c.ke32 = 0;
     c.w = base + a.lay.w;
     c.wt = base + a.lay.wt;
     c.R = base + a.lay.R;
@@ -2238,6 +2294,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
         if (rve < 0) return;
         RveCtx c;
         rve_setup<D>(a, rve, base, c, sm);
+        c.ke32 = IR ? 1 : 0;
         double* ir1 = base + a.lay.ir1;
         double* ir2 = base + a.lay.ir2;
         const int ndof = c.nn * D;
@@ -2294,9 +2351,12 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
             else backsolve_glb<D, 1, T>(c, sm, c.x);
             PROF_MARK(PH_BACK);
             if constexpr (IR) {
-                // refinement against the FP64 tangent: dx = K32^-1 (b - K64 x)
+                // refinement against the FP64 tangent: dx = K32^-1 (b - K64 x), with
+                // K64 x computed matrix-free by the element pass in FP64
                 for (int ref = 0; ref < a.ir_max; ++ref) {
-                    residual_ke<D, 1>(c, c.rhs, c.x, ir1);
+                    element_pass<D>(c, sm, c.w, 3, nullptr, nullptr, c.x);
+                    __syncthreads();
+                    residual_act<D>(c, c.rhs, ir1);
                     __syncthreads();
                     const double rl2 = sqrt(free_norm2<D>(c, sm, ir1));
                     if (!(rl2 > a.ir_eta * rn)) break;
