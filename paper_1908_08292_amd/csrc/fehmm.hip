@@ -340,6 +340,77 @@ inline size_t band_lds_bytes(int bw) {
     return sizeof(double) * (std::max(panel, rows) + kRing + 4 * 64);
 }
 
+// Both triangular solves of K du = -R on a stored band factor (L below the
+// diagonal and D on it in K's rows, the transposed copy in Kt), by one
+// workgroup of kBandNT threads: forward (pass 0) L y = -R on K, backward (pass
+// 1) x = D^-1 y - L^T x on Kt; blocks of 64 rows staged in LDS (band_lds, of
+// band_lds_bytes(bw) bytes).
+__device__ void band_solves(const double* __restrict__ K, const double* __restrict__ Kt, const double* __restrict__ R,
+                            int n, int bw, double* __restrict__ du, double* band_lds) {
+    const int ld = bw + 1, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const size_t big = std::max<size_t>(2 * (size_t)(kPanel + kBandMaxBw) * kPanelStride, 64 * (size_t)ld);
+    double* Kb = band_lds;
+    double* ring = band_lds + big;
+    double* red = ring + kRing;
+    for (int pass = 0; pass < 2; ++pass) {
+        const double* Src = pass == 0 ? K : Kt;
+        const int nblk64 = (n + 63) / 64;
+        for (int bi = 0; bi < nblk64; ++bi) {
+            const int i0 = (pass == 0 ? bi : nblk64 - 1 - bi) * 64;
+            const int rows = min(64, n - i0);
+            const int64_t base = (int64_t)i0 * ld;
+            const int cnt = rows * ld;
+            for (int e = tid; e < cnt; e += kBandNT) Kb[e] = Src[base + e];
+            __syncthreads();
+            // contributions of rows outside the block, split over the waves
+            const int i = i0 + lane;
+            double sdot = 0.0;
+            if (lane < rows) {
+                if (pass == 0) {
+                    // t = i - j with j < i0
+                    const int tmax = min(i, bw);
+                    for (int t = lane + 1 + wave; t <= tmax; t += 4)
+                        sdot += Kb[lane * ld + t] * ring[(i - t) & (kRing - 1)];
+                } else {
+                    // t = j - i with j >= i0 + 64
+                    const int tmax = min(n - 1 - i, bw);
+                    for (int t = 64 - lane + wave; t <= tmax; t += 4)
+                        sdot += Kb[lane * ld + t] * ring[(i + t) & (kRing - 1)];
+                }
+            }
+            red[wave * 64 + lane] = sdot;
+            __syncthreads();
+            if (wave == 0) {
+                double acc = 0.0;
+                if (lane < rows) {
+                    const double s4 = red[lane] + red[64 + lane] + red[128 + lane] + red[192 + lane];
+                    acc = pass == 0 ? -R[i] - s4 : du[i] / Kb[lane * ld] - s4;  // du[i]: stored by this lane
+                }
+                if (pass == 0) {
+                    for (int k = 0; k < rows; ++k) {
+                        const double yk = rdlane(acc, k);
+                        const int off = lane - k;
+                        const double l = Kb[lane * ld + ((off > 0 && off <= bw && lane < rows) ? off : 0)];
+                        if (off > 0 && off <= bw && lane < rows) acc -= l * yk;
+                    }
+                } else {
+                    for (int k = rows - 1; k >= 0; --k) {
+                        const double xk = rdlane(acc, k);
+                        const int off = k - lane;
+                        const double l = Kb[lane * ld + ((off > 0 && off <= bw) ? off : 0)];
+                        if (off > 0 && off <= bw) acc -= l * xk;
+                    }
+                }
+                if (lane < rows) {
+                    ring[i & (kRing - 1)] = acc;
+                    du[i] = acc;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 template <int SLOTS>
 __global__ __launch_bounds__(kBandNT) void macro_band_solve_blocked(double* __restrict__ K, double* __restrict__ Kt,
                                                                     const double* __restrict__ R, int n, int bw,
@@ -351,10 +422,7 @@ __global__ __launch_bounds__(kBandNT) void macro_band_solve_blocked(double* __re
     const size_t big = std::max<size_t>(2 * (size_t)(kPanel + kBandMaxBw) * kPanelStride, 64 * (size_t)ld);
     double* Ls = band_lds;                                          // scaled panel columns L[r][c]
     double* Ws = band_lds + (kPanel + kBandMaxBw) * kPanelStride;   // L[r][c] * D[c]
-    double* Kb = band_lds;                                          // staged solve rows (after the factorization)
-    double* ring = band_lds + big;
-    double* red = ring + kRing;
-    const int64_t last = (int64_t)n * ld - 1;
+    (void)big;
     for (int k0 = 0; k0 < n; k0 += kPanel) {
         const int nb = min(kPanel, n - k0);
         const int m = min(n - k0, nb + bw);  // rows touched by the panel
@@ -469,35 +537,380 @@ __global__ __launch_bounds__(kBandNT) void macro_band_solve_blocked(double* __re
         }
         __syncthreads();
     }
-    // triangular solves: forward (pass 0) L y = -R on K, backward (pass 1)
-    // x = D^-1 y - L^T x on Kt; blocks of 64 rows staged in LDS
-    for (int pass = 0; pass < 2; ++pass) {
-        const double* Src = pass == 0 ? K : Kt;
-        const int nblk64 = (n + 63) / 64;
-        for (int bi = 0; bi < nblk64; ++bi) {
-            const int i0 = (pass == 0 ? bi : nblk64 - 1 - bi) * 64;
-            const int rows = min(64, n - i0);
-            const int64_t base = (int64_t)i0 * ld;
-            const int cnt = rows * ld;
-            for (int e = tid; e < cnt; e += kBandNT) Kb[e] = Src[base + e];
-            __syncthreads();
-            // contributions of rows outside the block, split over the waves
-            const int i = i0 + lane;
-            double sdot = 0.0;
-            if (lane < rows) {
-                if (pass == 0) {
-                    // t = i - j with j < i0
-                    const int tmax = min(i, bw);
-                    for (int t = lane + 1 + wave; t <= tmax; t += 4)
-                        sdot += Kb[lane * ld + t] * ring[(i - t) & (kRing - 1)];
-                } else {
-                    // t = j - i with j >= i0 + 64
-                    const int tmax = min(n - 1 - i, bw);
-                    for (int t = 64 - lane + wave; t <= tmax; t += 4)
-                        sdot += Kb[lane * ld + t] * ring[(i + t) & (kRing - 1)];
+    band_solves(K, Kt, R, n, bw, du, band_lds);
+}
+
+// Banded LDL^T with the active window held in LDS, for bandwidths whose window
+// spans at most kWinMax tile rows.  The band is cut into 16 x 16 tiles.  The
+// part that later panels still update -- below panel kt, tile rows kt .. kt +
+// ntw - 1 (ntw = (bw + 15) / 16 + 1), lower triangle, at most 55 tiles -- stays
+// in LDS for the whole factorization: diagonal d = I - J keeps its ntw - d tiles
+// of the window in a ring, tile (I, J) at slot base(d) + J mod (ntw - d), so the
+// row that enters when the window moves on takes exactly the slots of the
+// retired panel column.  Per panel (tile column kt), one workgroup of four
+// waves: wave 0 factors the diagonal tile (lane = row, readlane broadcasts) and
+// forms W = L11^-T D^-1; the tiles below become L = A W on MFMA (in place); the
+// factor goes out to K and Kt (band entries only); the trailing tiles take -L(I)
+// D L(J)^T on MFMA; the entering tile row, read from K while the panel is
+// processed (no earlier panel reaches it), is stored.  The matrix is read once
+// and the factor written once, and no global round trip sits on the panel
+// chain.  Rows and columns past n are padded with the identity.
+constexpr int kWinMax = 10;                                  // tile rows of the window (bw <= 144)
+constexpr int kWinSlots = kWinMax * (kWinMax + 1) / 2;       // window tiles
+constexpr int kWinWaves = 4;
+constexpr int kWinNT = 64 * kWinWaves;
+constexpr int kWinStride = 17;                               // LDS row stride of a tile (doubles)
+constexpr int kWinTile = 16 * kWinStride;
+inline size_t band_win_lds_bytes() {
+    return sizeof(double) * ((size_t)(kWinSlots + kWinMax) * kWinTile + 256 + 16) +
+           sizeof(int) * (2 * kWinMax * kWinMax);
+}
+inline bool band_win_fits(int bw) { return (bw + 15) / 16 + 1 <= kWinMax; }
+
+__device__ inline int win_slot(int I, int J, int ntw) {
+    const int d = I - J;
+    return d * ntw - ((d * (d - 1)) >> 1) + J % (ntw - d);
+}
+
+// entry (r, c) of the band matrix (lower band from K, identity past n); the
+// read is unconditional, at a clamped address
+__device__ inline double band_at(const double* __restrict__ K, int n, int bw, int r, int c) {
+    const int off = r - c;
+    const bool in = (r < n) & (c < n) & (off >= 0) & (off <= bw);
+    const double x = K[in ? (int64_t)r * (bw + 1) + off : 0];
+    return in ? x : (((r == c) & (r >= n)) ? 1.0 : 0.0);
+}
+
+__device__ inline double recip_nr64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+// B. by one wave: LDL^T of the diagonal tile T of panel kt (lane = row, readlane
+// broadcasts), W = L11^-T D^-1 from the rows of L11^-1 into Wm, the pivots into
+// Dv, the tile's factor rows out to K and Kt
+__device__ __forceinline__ void win_diag(const double* T, double* Wm, double* Dv, int kt, int n, int bw,
+                                         double* __restrict__ K, double* __restrict__ Kt, int* __restrict__ flag,
+                                         int lane) {
+    const int ld = bw + 1;
+    const bool own = lane < 16;
+    double a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) a[c] = (own && c <= lane) ? T[(lane & 15) * kWinStride + c] : 0.0;
+    double dpiv = 1.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const double piv = rdlane(a[j], j);
+        if (lane == j) {
+            dpiv = piv;
+            if (!(fabs(piv) > 0.0) || !isfinite(piv)) *flag = 1;
+        }
+        const double l = (own && lane > j) ? a[j] * recip_nr64(piv) : 0.0;
+        const double lp = l * piv;
+#pragma unroll
+        for (int cc = j + 1; cc < 16; ++cc) a[cc] -= lp * rdlane(l, cc);
+        if (lane > j) a[j] = l;
+    }
+    // row `lane` of L11^-1 (unit lower), by forward substitution
+    double li[16];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) li[cc] = (cc == lane) ? 1.0 : 0.0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const double le = (own && lane > e) ? a[e] : 0.0;
+#pragma unroll
+        for (int cc = 0; cc <= e; ++cc) li[cc] -= le * rdlane(li[cc], e);
+    }
+    if (own) {
+        const double rd = recip_nr64(dpiv);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) Wm[k * 16 + lane] = li[k] * rd;
+        Dv[lane] = dpiv;
+        const int r = 16 * kt + lane;
+        if (r < n) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int off = lane - c;
+                if (off >= 0 && off <= bw) {
+                    const double v = off == 0 ? dpiv : a[c];
+                    K[(int64_t)r * ld + off] = v;
+                    Kt[(int64_t)(16 * kt + c) * ld + off] = v;
                 }
             }
-            red[wave * 64 + lane] = sdot;
+        }
+    }
+}
+
+// C. the panel tiles below the diagonal owned by wave W (o = W + 1, W + 5, ...):
+// L = A W on MFMA, in place, L D to LDp, the factor out to K and Kt
+template <int W>
+__device__ __forceinline__ void win_panel(double* Wn, double* LDp, const double* Wm, const double* Dv,
+                                          const int* slot, int rows_w, int kt, int n, int bw,
+                                          double* __restrict__ K, double* __restrict__ Kt, int lane) {
+    constexpr int NO = (kWinMax - 1 - W + kWinWaves - 1) / kWinWaves;  // tiles of this wave
+    const int ld = bw + 1, c = lane & 15, gc = 16 * kt + c;
+    double av[NO > 0 ? NO : 1][4];
+    double* T[NO > 0 ? NO : 1];
+    double wv[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) wv[ks] = Wm[(4 * ks + (lane >> 4)) * 16 + c];
+#pragma unroll
+    for (int q = 0; q < NO; ++q) {
+        const int o = W + 1 + kWinWaves * q;
+        T[q] = Wn + slot[min(o, rows_w - 1) * kWinMax] * kWinTile;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) av[q][ks] = T[q][c * kWinStride + 4 * ks + (lane >> 4)];
+    }
+    const double dc = Dv[c];
+#pragma unroll
+    for (int q = 0; q < NO; ++q) {
+        const int o = W + 1 + kWinWaves * q;
+        if (o < rows_w) {
+            band_dbl4 t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) t = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q][ks], wv[ks], t, 0, 0, 0);
+            double* LDt = LDp + o * kWinTile;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = (lane >> 4) + 4 * v, r = 16 * (kt + o) + rr, off = r - gc;
+                T[q][rr * kWinStride + c] = t[v];
+                LDt[rr * kWinStride + c] = t[v] * dc;
+                if (r < n && off <= bw) {
+                    K[(int64_t)r * ld + off] = t[v];
+                    Kt[(int64_t)gc * ld + off] = t[v];
+                }
+            }
+        }
+    }
+}
+
+// D. the trailing tiles owned by wave W: tile (kt + oi, kt + oj), 1 <= oj <= oi,
+// numbered t = (oi - 1) oi / 2 + oj - 1; wave 0 takes t = 0 (the next diagonal
+// tile, which it factors right after), waves 1 .. 3 the others in turn.  Every
+// operand is read first, then the MFMAs run, then the tiles are stored.
+__device__ constexpr bool win_owns(int W, int t) { return W == 0 ? t == 0 : (t > 0 && (t - 1) % (kWinWaves - 1) == W - 1); }
+
+template <int W>
+__device__ __forceinline__ void win_trailing(double* Wn, const double* LDp, const int* slot, int rows_w, int lane) {
+    const int c = lane & 15, kq = lane >> 4;
+    double aI[kWinMax][4], bJ[kWinMax][4];
+#pragma unroll
+    for (int o = 1; o < (W == 0 ? 2 : kWinMax); ++o) {
+        const double* LDt = LDp + min(o, rows_w - 1) * kWinTile;
+        const double* Lt = Wn + slot[min(o, rows_w - 1) * kWinMax] * kWinTile;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            aI[o][ks] = -LDt[c * kWinStride + 4 * ks + kq];
+            bJ[o][ks] = Lt[c * kWinStride + 4 * ks + kq];
+        }
+    }
+    constexpr int NTT = (kWinMax - 1) * kWinMax / 2;
+    constexpr int NT = W == 0 ? 1 : (NTT - 1 - (W - 1) + kWinWaves - 2) / (kWinWaves - 1);
+    band_dbl4 acc[NT];
+    double* C[NT];
+    {
+        int q = 0;
+#pragma unroll
+        for (int oi = 1; oi < kWinMax; ++oi)
+#pragma unroll
+            for (int oj = 1; oj <= oi; ++oj)
+                if (win_owns(W, (oi - 1) * oi / 2 + oj - 1)) {
+                    C[q] = Wn + slot[min(oi, rows_w - 1) * kWinMax + min(oj, rows_w - 1)] * kWinTile;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[q][v] = C[q][(kq + 4 * v) * kWinStride + c];
+                    ++q;
+                }
+    }
+    {
+        int q = 0;
+#pragma unroll
+        for (int oi = 1; oi < kWinMax; ++oi)
+#pragma unroll
+            for (int oj = 1; oj <= oi; ++oj)
+                if (win_owns(W, (oi - 1) * oi / 2 + oj - 1)) {
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks)
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(aI[oi][ks], bJ[oj][ks], acc[q], 0, 0, 0);
+                    ++q;
+                }
+    }
+    {
+        int q = 0;
+#pragma unroll
+        for (int oi = 1; oi < kWinMax; ++oi)
+#pragma unroll
+            for (int oj = 1; oj <= oi; ++oj)
+                if (win_owns(W, (oi - 1) * oi / 2 + oj - 1)) {
+                    if (oi < rows_w) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) C[q][(kq + 4 * v) * kWinStride + c] = acc[q][v];
+                    }
+                    ++q;
+                }
+    }
+}
+
+__global__ __launch_bounds__(kWinNT) void macro_band_factor_window(double* __restrict__ K, double* __restrict__ Kt,
+                                                                  int n, int bw, int* __restrict__ flag,
+                                                                  const int* __restrict__ done) {
+    if (*done) return;
+    extern __shared__ double win_lds[];
+    double* Wn = win_lds;                        // window tiles, [kWinSlots][16][kWinStride]
+    double* LDp = Wn + kWinSlots * kWinTile;     // the panel's L tiles with column c scaled by D[c]
+    double* Wm = LDp + kWinMax * kWinTile;       // W[k * 16 + c]
+    double* Dv = Wm + 256;                       // the panel's pivots
+    int* slots = reinterpret_cast<int*>(Dv + 16);  // two buffers of the panel's window-tile slots
+    const int ld = bw + 1, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int ntw = (bw + 15) / 16 + 1, nt = (n + 15) / 16;
+    const int pr = tid >> 4, pc = tid & 15;      // this thread's element of a staged tile
+    for (int I = 0; I < min(ntw, nt); ++I)
+        for (int J = 0; J <= I; ++J)
+            Wn[win_slot(I, J, ntw) * kWinTile + pr * kWinStride + pc] = band_at(K, n, bw, 16 * I + pr, 16 * J + pc);
+    // slots of panel kt's window tiles: slot[oi * kWinMax + oj] holds tile (kt +
+    // oi, kt + oj); two buffers (a panel's E still reads its own while the next
+    // table is written)
+    auto fill_slots = [&](int kt) {
+        int* slot = slots + (kt & 1) * kWinMax * kWinMax;
+        if (tid < kWinMax * kWinMax) {
+            const int oi = tid / kWinMax, oj = tid - oi * kWinMax;
+            if (oj <= oi && oi < ntw) slot[tid] = win_slot(kt + oi, kt + oj, ntw);
+        }
+    };
+    fill_slots(0);
+    __syncthreads();
+    if (wave == 0) win_diag(Wn + slots[0] * kWinTile, Wm, Dv, 0, n, bw, K, Kt, flag, lane);
+    __syncthreads();
+    // per panel kt (its diagonal tile already factored): C, then D with the next
+    // panel's diagonal tile updated and factored by wave 0 while the other waves
+    // update the rest of the window, then E
+    for (int kt = 0; kt < nt; ++kt) {
+        const int rows_w = min(ntw, nt - kt);
+        const int* slot = slots + (kt & 1) * kWinMax * kWinMax;
+        // the tile row that enters after this panel: tiles (In, In - d), d < ntw;
+        // it takes the slots of the retired panel tiles (kt + d, kt)
+        const int In = kt + ntw;
+        const bool enter = In < nt;
+        double pf[kWinMax];
+#pragma unroll
+        for (int d = 0; d < kWinMax; ++d) pf[d] = band_at(K, enter ? n : 0, bw, 16 * In + pr, 16 * (In - d) + pc);
+        // C. the tiles below the diagonal: L = A W, in place
+        switch (wave) {
+            case 0: win_panel<0>(Wn, LDp, Wm, Dv, slot, rows_w, kt, n, bw, K, Kt, lane); break;
+            case 1: win_panel<1>(Wn, LDp, Wm, Dv, slot, rows_w, kt, n, bw, K, Kt, lane); break;
+            case 2: win_panel<2>(Wn, LDp, Wm, Dv, slot, rows_w, kt, n, bw, K, Kt, lane); break;
+            default: win_panel<3>(Wn, LDp, Wm, Dv, slot, rows_w, kt, n, bw, K, Kt, lane); break;
+        }
+        __syncthreads();
+        // D. the trailing tiles; wave 0 then factors panel kt + 1's diagonal tile
+        //    (Wm and Dv are free: C has read them)
+        switch (wave) {
+            case 0:
+                win_trailing<0>(Wn, LDp, slot, rows_w, lane);
+                if (kt + 1 < nt) {
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    win_diag(Wn + slot[kWinMax + 1] * kWinTile, Wm, Dv, kt + 1, n, bw, K, Kt, flag, lane);
+                }
+                break;
+            case 1: win_trailing<1>(Wn, LDp, slot, rows_w, lane); break;
+            case 2: win_trailing<2>(Wn, LDp, slot, rows_w, lane); break;
+            default: win_trailing<3>(Wn, LDp, slot, rows_w, lane); break;
+        }
+        __syncthreads();
+        // E. the entering tile row into the retired panel tiles' slots; the next
+        //    panel's slot table
+        if (enter) {
+#pragma unroll
+            for (int d = 0; d < kWinMax; ++d)
+                if (d < ntw) Wn[slot[d * kWinMax] * kWinTile + pr * kWinStride + pc] = pf[d];
+        }
+        fill_slots(kt + 1);
+        __syncthreads();
+    }
+}
+
+// Both triangular solves of K du = -R on the band factor of
+// macro_band_factor_window (bw <= 144), one workgroup: forward L y = -R on K,
+// then x = D^-1 y - L^T x on Kt (row j of Kt holds column j of L), in blocks of
+// 64 rows.  Each block is staged in LDS while the previous one is solved
+// (double buffer; the next block's rows are read into registers first).  The
+// contributions of earlier (forward) or later (backward) rows are dot products
+// over the LDS ring of solved values, split over the four waves; the block's
+// own 64 x 64 triangle is a sweep in wave 0 (lane = row, readlane broadcasts)
+// with every factor entry of the lane's row read before the sweep.
+constexpr int kSolveBlk = 64;
+constexpr int kSolvePer = (kSolveBlk * (16 * kWinMax - 15) + kBandNT - 1) / kBandNT;  // staged doubles per thread
+inline size_t band_solve_win_lds_bytes(int bw) {
+    return sizeof(double) * (2 * (size_t)kSolveBlk * (bw + 1) + kRing + 4 * 64);
+}
+
+__global__ __launch_bounds__(kBandNT) void macro_band_solves_win(const double* __restrict__ K,
+                                                                const double* __restrict__ Kt,
+                                                                const double* __restrict__ R, int n, int bw,
+                                                                double* __restrict__ du,
+                                                                const int* __restrict__ done) {
+    if (*done) return;
+    extern __shared__ double sv_lds[];
+    const int ld = bw + 1, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int bsz = kSolveBlk * ld;
+    double* ring = sv_lds + 2 * bsz;
+    double* red = ring + kRing;
+    const int nb = (n + kSolveBlk - 1) / kSolveBlk;
+    double pre[kSolvePer];
+    for (int pass = 0; pass < 2; ++pass) {
+        const double* Src = pass == 0 ? K : Kt;
+        // the rows of block bi: forward in increasing, backward in decreasing order
+        auto row0 = [&](int bi) { return (pass == 0 ? bi : nb - 1 - bi) * kSolveBlk; };
+        auto fetch = [&](int bi) {
+            const int r0 = row0(bi), cnt = min(kSolveBlk, n - r0) * ld;
+            const double* src = Src + (int64_t)r0 * ld;
+#pragma unroll
+            for (int q = 0; q < kSolvePer; ++q) {
+                const int e = tid + kBandNT * q;
+                pre[q] = src[e < cnt ? e : 0];
+            }
+        };
+        auto stage = [&](int bi) {
+            const int r0 = row0(bi), cnt = min(kSolveBlk, n - r0) * ld;
+            double* dst = sv_lds + (bi & 1) * bsz;
+#pragma unroll
+            for (int q = 0; q < kSolvePer; ++q) {
+                const int e = tid + kBandNT * q;
+                if (e < cnt) dst[e] = pre[q];
+            }
+        };
+        fetch(0);
+        stage(0);
+        __syncthreads();
+        for (int bi = 0; bi < nb; ++bi) {
+            const double* Kb = sv_lds + (bi & 1) * bsz;
+            const int i0 = row0(bi), rows = min(kSolveBlk, n - i0), i = i0 + lane;
+            if (bi + 1 < nb) fetch(bi + 1);
+            // contributions of rows outside the block
+            double s0 = 0.0, s1 = 0.0;
+            if (lane < rows) {
+                if (pass == 0) {
+                    const int tmax = min(i, bw);  // t = i - j, j < i0
+                    int t = lane + 1 + wave;
+                    for (; t + 4 <= tmax; t += 8) {
+                        s0 += Kb[lane * ld + t] * ring[(i - t) & (kRing - 1)];
+                        s1 += Kb[lane * ld + t + 4] * ring[(i - t - 4) & (kRing - 1)];
+                    }
+                    if (t <= tmax) s0 += Kb[lane * ld + t] * ring[(i - t) & (kRing - 1)];
+                } else {
+                    const int tmax = min(n - 1 - i, bw);  // t = j - i, j >= i0 + 64
+                    int t = kSolveBlk - lane + wave;
+                    for (; t + 4 <= tmax; t += 8) {
+                        s0 += Kb[lane * ld + t] * ring[(i + t) & (kRing - 1)];
+                        s1 += Kb[lane * ld + t + 4] * ring[(i + t + 4) & (kRing - 1)];
+                    }
+                    if (t <= tmax) s0 += Kb[lane * ld + t] * ring[(i + t) & (kRing - 1)];
+                }
+            }
+            red[wave * 64 + lane] = s0 + s1;
             __syncthreads();
             if (wave == 0) {
                 double acc = 0.0;
@@ -505,26 +918,32 @@ __global__ __launch_bounds__(kBandNT) void macro_band_solve_blocked(double* __re
                     const double s4 = red[lane] + red[64 + lane] + red[128 + lane] + red[192 + lane];
                     acc = pass == 0 ? -R[i] - s4 : du[i] / Kb[lane * ld] - s4;  // du[i]: stored by this lane
                 }
+                const int lr = min(lane, rows - 1);
                 if (pass == 0) {
-                    for (int k = 0; k < rows; ++k) {
-                        const double yk = rdlane(acc, k);
+                    double l[kSolveBlk];
+#pragma unroll
+                    for (int k = 0; k < kSolveBlk; ++k) {
                         const int off = lane - k;
-                        const double l = Kb[lane * ld + ((off > 0 && off <= bw && lane < rows) ? off : 0)];
-                        if (off > 0 && off <= bw && lane < rows) acc -= l * yk;
+                        l[k] = ((off > 0) & (off <= bw)) ? Kb[lr * ld + (off > 0 && off <= bw ? off : 0)] : 0.0;
                     }
+#pragma unroll
+                    for (int k = 0; k < kSolveBlk; ++k) acc -= l[k] * rdlane(acc, k);
                 } else {
-                    for (int k = rows - 1; k >= 0; --k) {
-                        const double xk = rdlane(acc, k);
+                    double l[kSolveBlk];
+#pragma unroll
+                    for (int k = 0; k < kSolveBlk; ++k) {
                         const int off = k - lane;
-                        const double l = Kb[lane * ld + ((off > 0 && off <= bw) ? off : 0)];
-                        if (off > 0 && off <= bw) acc -= l * xk;
+                        l[k] = ((off > 0) & (off <= bw)) ? Kb[lr * ld + (off > 0 && off <= bw ? off : 0)] : 0.0;
                     }
+#pragma unroll
+                    for (int k = kSolveBlk - 1; k >= 0; --k) acc -= l[k] * rdlane(acc, k);
                 }
                 if (lane < rows) {
                     ring[i & (kRing - 1)] = acc;
                     du[i] = acc;
                 }
             }
+            if (bi + 1 < nb) stage(bi + 1);
             __syncthreads();
         }
     }
@@ -623,12 +1042,14 @@ int fehmm_create(const fehmm_desc* d, fehmm* out) {
     static bool band_prepared = false;
     if (!band_prepared) {
         const int lds = (int)band_lds_bytes(kBandMaxBw);
-        FH_HIP(hipFuncSetAttribute((const void*)macro_band_solve_blocked<2>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds));
         FH_HIP(hipFuncSetAttribute((const void*)macro_band_solve_blocked<3>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
         FH_HIP(hipFuncSetAttribute((const void*)macro_band_solve_blocked<4>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        FH_HIP(hipFuncSetAttribute((const void*)macro_band_solves_win, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)band_solve_win_lds_bytes(16 * kWinMax - 16)));
+        FH_HIP(hipFuncSetAttribute((const void*)macro_band_factor_window, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)band_win_lds_bytes()));
         band_prepared = true;
     }
     auto h = std::make_unique<fehmm_s>();
@@ -854,10 +1275,12 @@ static int enqueue_step(fehmm_s* h, int it_begin, int it_end, bool with_init) {
                            d.max_macro_iter);
         const int slots = (kPanel + h->bw + 63) / 64;  // panel rows per lane
         const size_t lds = band_lds_bytes(h->bw);
-        if (slots <= 2)
-            hipLaunchKernelGGL(macro_band_solve_blocked<2>, dim3(1), dim3(kBandNT), lds, s, h->d_K, h->d_Kt, h->d_R,
-                               h->ndof, h->bw, h->d_du, &st->band_flag, done);
-        else if (slots == 3)
+        if (band_win_fits(h->bw)) {
+            hipLaunchKernelGGL(macro_band_factor_window, dim3(1), dim3(kWinNT), band_win_lds_bytes(), s, h->d_K,
+                               h->d_Kt, h->ndof, h->bw, &st->band_flag, done);
+            hipLaunchKernelGGL(macro_band_solves_win, dim3(1), dim3(kBandNT), band_solve_win_lds_bytes(h->bw), s,
+                               h->d_K, h->d_Kt, h->d_R, h->ndof, h->bw, h->d_du, done);
+        } else if (slots <= 3)
             hipLaunchKernelGGL(macro_band_solve_blocked<3>, dim3(1), dim3(kBandNT), lds, s, h->d_K, h->d_Kt, h->d_R,
                                h->ndof, h->bw, h->d_du, &st->band_flag, done);
         else if (slots == 4)

@@ -56,6 +56,28 @@ def test_macro_parity_uniaxial_with_hole():
     assert drv.nqp == orc.nqp
 
 
+@pytest.mark.parametrize("nx,ny", [(70, 2), (90, 1), (120, 1)])
+def test_macro_parity_wide_band(nx, ny):
+    """The band solvers past the windowed one: an nx-element-wide plate has band
+    width 2 (nx + 2) + 1; 70 wide (bw 145) is just past the LDS window (tile rows
+    (bw + 15) / 16 + 1 <= 10), so the panel solver runs with three panel rows per
+    lane, 90 wide (bw 185) with four, and 120 wide (bw 245) takes the unblocked
+    solver.  (The 64 x 64 plate, bw 133, and every smaller plate run the windowed
+    solver.)"""
+    need_gpu()
+    print(f"case macro {nx}x{ny}, RVE 4x4, wide band", flush=True)
+    run_pair(nx, ny, 4, 0.3, 2, 1.05, fehmm.BC_UNIAXIAL, fehmm.NESTED)
+
+
+def test_macro_parity_window_edge():
+    """The widest band of the windowed solver: 64 elements wide, bw = 2 (65 + 1)
+    + 1 = 133, ten tile rows; a short plate so the window reaches its last panels
+    while still full."""
+    need_gpu()
+    print("case macro 64x3, RVE 4x4", flush=True)
+    run_pair(64, 3, 4, 0.3, 2, 1.05, fehmm.BC_UNIAXIAL, fehmm.NESTED)
+
+
 def test_config0_full():
     """Macro 4 x 4 Q1 on the unit square, RVE 8 x 8 (r = 0.25, ratio 10), left edge
     clamped, right edge stretched to 1.1 in 10 steps, both Newton levels 1e-10."""
