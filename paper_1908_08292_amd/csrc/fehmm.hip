@@ -573,12 +573,14 @@ __device__ inline int win_slot(int I, int J, int ntw) {
 }
 
 // entry (r, c) of the band matrix (lower band from K, identity past n); the
-// read is unconditional, at a clamped address
+// read is unconditional, at a clamped address, and its value enters through a
+// 0/1 factor (a select would let the compiler move the read under a branch and
+// wait for it there)
 __device__ inline double band_at(const double* __restrict__ K, int n, int bw, int r, int c) {
     const int off = r - c;
     const bool in = (r < n) & (c < n) & (off >= 0) & (off <= bw);
     const double x = K[in ? (int64_t)r * (bw + 1) + off : 0];
-    return in ? x : (((r == c) & (r >= n)) ? 1.0 : 0.0);
+    return fma(x, in ? 1.0 : 0.0, ((r == c) & (r >= n)) ? 1.0 : 0.0);
 }
 
 __device__ inline double recip_nr64(double x) {
