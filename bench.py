@@ -515,7 +515,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else "f32 factors + f64 refinement",
+        "dtype": "f64" if head == "fp64" else "f32 tangents and factors + f64 refinement",
         "data": "synthetic",
         "config": {"workload": meta["workload"], "rves": B, "dim": d, "elements_per_edge": meta["n"],
                    "precision": head, "newton_rtol": 1e-10,
@@ -531,8 +531,8 @@ def main():
                                       speedup_vs_fp64=ms / t["ms"], failed_rves=t["nbad"],
                                       traffic=measured_traffic(meta["workload"], "fp32ir"),
                                       mean_newton_iters=float(t["res"]["iters"].mean()),
-                                      dtype="f32 factors (LDL^T, solves) + f64 residuals, refinement, "
-                                            "norms, averages and condensation")
+                                      dtype="f32 element tangents and factors (LDL^T, solves) + f64 residuals "
+                                            "(matrix-free K x), refinement, norms, averages and condensation")
     if not args.no_assembly and d == 2:
         out["assembly"] = assembly_block(s, wl, meta)
         print(f"[bench] assembly: {out['assembly']['ms_per_launch']:.3f} ms", file=sys.stderr, flush=True)
