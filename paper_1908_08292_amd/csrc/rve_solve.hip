@@ -596,6 +596,19 @@ __device__ inline double readlane_d(double v, int l) {
     return u.d;
 }
 
+// the same in the factor type: LDS-front eliminations run in the precision the
+// front is stored in (FP32 fronts: one readlane per broadcast, FP32 arithmetic;
+// the Newton step is refined against the FP64 residual)
+__device__ inline double readlane_t(double v, int l) { return readlane_d(v, l); }
+__device__ inline float readlane_t(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double recip_t(double x) { return recip_nr(x); }
+__device__ inline float recip_t(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // ---------------------------------------------------------------- global fronts
 // Plans whose fronts exceed LDS (3D from 5^3 up) keep each front in the slot's
 // global workspace in the factor type T: the m x p panel column-major (column j
@@ -1401,14 +1414,14 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
         {
             const int r = lane;
             const bool act = r >= K && r < m;
-            double row[16];
-            double yv[NRHS];
+            T row[16];
+            T yv[NRHS];
             // (clamped reads inside the front, masked: no branch per entry)
 #pragma unroll
             for (int cc = 0; cc < 16; ++cc) {
                 const int col = min(K + cc, m - 1);
                 const int idx = min(max(cpk(col, m) + r - col, 0), cpk(m, m) - 1);
-                row[cc] = (double)F[idx] * ((act && cc < kb && K + cc <= r) ? 1.0 : 0.0);
+                row[cc] = F[idx] * ((act && cc < kb && K + cc <= r) ? T(1) : T(0));
             }
             // (clamped reads; lanes off the front never store or broadcast these,
             // and only the pivot's own lane tests its d0)
@@ -1418,25 +1431,25 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 if (j < kb) {
-                    const double piv = readlane_d(row[j], K + j);
-                    const double rp = recip_nr(piv);
-                    if (r == K + j && (!(fabs(piv) > 1e-14 * fabs(d0)) || !isfinite(piv))) sm.flag = 2;
+                    const T piv = readlane_t(row[j], K + j);
+                    const T rp = recip_t(piv);
+                    if (r == K + j && (!(fabs((double)piv) > 1e-14 * fabs(d0)) || !isfinite((double)piv))) sm.flag = 2;
                     const bool below = act && r > K + j;
-                    const double l = below ? row[j] * rp : 0.0;
-                    const double lpv = l * piv;
+                    const T l = below ? row[j] * rp : T(0);
+                    const T lpv = l * piv;
                     // unconditional updates: l = 0 off the rows below the pivot, and
                     // the only other entries touched, row[cc] with K + cc > r, lie
                     // above the diagonal and are neither stored nor read
 #pragma unroll
                     for (int cc = j + 1; cc < 16; ++cc) {
                         if (cc < kb) {
-                            const double lc = readlane_d(l, K + cc);
+                            const T lc = readlane_t(l, K + cc);
                             row[cc] -= lpv * lc;
                         }
                     }
 #pragma unroll
                     for (int q = 0; q < NRHS; ++q) {
-                        const double yj = readlane_d(yv[q], K + j);
+                        const T yj = readlane_t(yv[q], K + j);
                         yv[q] -= l * yj;
                     }
                     if (below) row[j] = l;
@@ -1444,7 +1457,7 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
             }
 #pragma unroll
             for (int cc = 0; cc < 16; ++cc)
-                if (act && cc < kb && K + cc <= r) F[cpk(K + cc, m) + r - K - cc] = (T)row[cc];
+                if (act && cc < kb && K + cc <= r) F[cpk(K + cc, m) + r - K - cc] = row[cc];
 #pragma unroll
             for (int q = 0; q < NRHS; ++q)
                 if (act) rl[q * m + r] = yv[q];
@@ -1591,8 +1604,8 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
         // forward-substituted rhs (double-buffered, one barrier per pivot)
         const int i = K + gt;
         const bool own = i < m;
-        double r[16];
-        double b[NRHS];
+        T r[16];
+        T b[NRHS];
         // (clamped reads inside the front, masked or unused: rows off the front
         // never publish, update or store these, and only a pivot's owner tests
         // its d0)
@@ -1600,7 +1613,7 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
         for (int cc = 0; cc < 16; ++cc) {
             const int col = min(K + cc, m - 1);
             const int idx = min(max(cpk(col, m) + min(i, m - 1) - col, 0), cpk(m, m) - 1);
-            r[cc] = (double)F[idx] * ((own && cc < kb && K + cc <= i) ? 1.0 : 0.0);
+            r[cc] = F[idx] * ((own && cc < kb && K + cc <= i) ? T(1) : T(0));
         }
 #pragma unroll
         for (int q = 0; q < NRHS; ++q) b[q] = rl[q * m + min(i, m - 1)];
@@ -1608,12 +1621,13 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             if (j < kb) {
-                double* P = pub[j & 1];  // [0] piv, [1] 1/piv, [2..17] g, [18..] y
+                // [0] piv, [1] 1/piv, [2..17] g, [18..] y, in the factor type
+                T* P = reinterpret_cast<T*>(pub[j & 1]);
                 if (i == K + j) {
-                    const double piv = r[j];
-                    if (!(fabs(piv) > 1e-14 * fabs(d0)) || !isfinite(piv)) sm.flag = 2;
+                    const T piv = r[j];
+                    if (!(fabs((double)piv) > 1e-14 * fabs(d0)) || !isfinite((double)piv)) sm.flag = 2;
                     P[0] = piv;
-                    P[1] = recip_nr(piv);
+                    P[1] = recip_t(piv);
 #pragma unroll
                     for (int q = 0; q < NRHS; ++q) P[18 + q] = b[q];
                 } else if (i > K + j && i < K + kb) {
@@ -1621,7 +1635,7 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
                 }
                 __syncthreads();
                 if (own && i > K + j) {
-                    const double l = r[j] * P[1];
+                    const T l = r[j] * P[1];
                     // every P entry is read (all within the buffer; entries past the
                     // block are stale) and the multiplier selected, so the reads
                     // need no branch of their own: r[cc] above the row's diagonal
@@ -1629,7 +1643,7 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
                     // bound masks the update
 #pragma unroll
                     for (int cc = j + 1; cc < 16; ++cc) {
-                        const double lc = cc < kb ? l : 0.0;
+                        const T lc = cc < kb ? l : T(0);
                         r[cc] -= lc * P[2 + cc];
                     }
                     r[j] = l;
