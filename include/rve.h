@@ -238,7 +238,8 @@ typedef struct {
     int32_t wave_max_m;  /* 0 .. 64; 64 is the default */
     int32_t slots;       /* 0: default (min(B, 1024)) */
     int32_t threads;     /* 0: by front size (eight waves when the fronts leave room for one four-wave
-                            workgroup per CU only), 256 or 512 */
+                            workgroup per CU only), 256 or 512; 512 applies to 2D plans with fronts
+                            in LDS and is taken as 256 elsewhere */
     double ms;           /* measured time of the tuning batch (rve_autotune), else 0 */
 } rve_tuning;
 
