@@ -306,7 +306,9 @@ __global__ __launch_bounds__(NTB) void macro_band_solve(double* __restrict__ K, 
 }
 
 // Blocked banded LDL^T and solve K du = -R in one workgroup of 4 waves, for
-// bandwidths up to kBandMaxBw.  Per block of kPanel columns: wave 0 factors the
+// bandwidths past the windowed solver's (macro_band_factor_window below) up to
+// kBandMaxBw; the unblocked macro_band_solve above takes wider bands.  The
+// factor stays in global memory.  Per block of kPanel columns: wave 0 factors the
 // panel (kPanel columns x up to kPanel + bw rows) in registers, one column
 // after the other with the pivot row's values broadcast by readlane (no
 // barrier inside a panel); then all waves apply the panel's rank-kPanel update
