@@ -20,10 +20,11 @@ def match_u(xy_a, u_a, xy_b, u_b):
     return u_b.reshape(-1, 2)[order].reshape(-1)
 
 
-def run_pair(nx, ny, n, r, nsteps, stretch, bc, scheme, hole_r=0.0, steps=None):
+def run_pair(nx, ny, n, r, nsteps, stretch, bc, scheme, hole_r=0.0, steps=None, micro_opts=None):
     lame = rve.two_phase_lame(10.0)
     mesh = rve.Mesh(2, n, lame, radius=r)
-    drv = fehmm.Driver(mesh, nx, ny, hole_r=hole_r, bc=bc, stretch=stretch, nsteps=nsteps, scheme=scheme)
+    drv = fehmm.Driver(mesh, nx, ny, hole_r=hole_r, bc=bc, stretch=stretch, nsteps=nsteps, scheme=scheme,
+                       micro_opts=micro_opts)
     orc = oracle.Macro(nx, ny, n, oracle.phase_by_centroid(2, n, r), oracle.two_phase_lame(10.0), hole_r=hole_r,
                        bc=bc, stretch=stretch, nsteps=nsteps, scheme=scheme)
     out = []
@@ -47,6 +48,17 @@ def test_macro_parity_small(scheme):
     need_gpu()
     print(f"case macro 3x3, RVE 4x4, scheme {scheme}", flush=True)
     run_pair(3, 3, 4, 0.3, 3, 1.1, fehmm.BC_CLAMPED_PULL, scheme)
+
+
+@pytest.mark.parametrize("scheme", [fehmm.NESTED, fehmm.ALTERNATING])
+def test_macro_parity_fp32_micro_solves(scheme):
+    """The driver with FP32 micro assembly and factors (FP64 refinement): the
+    micro outputs meet the FP64 bar, so the macro Newton takes the oracle's
+    iterations and reaches its displacements."""
+    need_gpu()
+    print(f"case macro 4x4, RVE 8x8, FP32 micro solves, scheme {scheme}", flush=True)
+    run_pair(4, 4, 8, 0.25, 3, 1.1, fehmm.BC_CLAMPED_PULL, scheme,
+             micro_opts=rve.default_opts(precision=rve.PREC_FP32_IR))
 
 
 def test_macro_parity_uniaxial_with_hole():
