@@ -20,8 +20,10 @@ Prints one JSON line.  Options:
                            macro grid / RVE 8 x 8 over 10 load steps, and the
                            64 x 64 plate with a hole (14288 RVEs of 16 x 16) over
                            all 20 load steps, nested and alternating two-level
-                           Newton, with the oracle's macro driver beside it (all
-                           steps of the 4 x 4 plate, step 1 of the 64 x 64 plate)
+                           Newton (and, on the plate, nested with FP32 micro
+                           assembly and factors), with the oracle's macro driver
+                           beside it (all steps of the 4 x 4 plate, step 1 of the
+                           64 x 64 plate)
   --no-assembly            skip the assembly phase timed alone (HBM roofline)
   --no-peaks               skip the measured FP64 / FP32 MFMA and HBM copy rates
   --no-cpu-3d              skip the oracle subsample of the uneven 3D batch
@@ -326,10 +328,15 @@ def macro_bench(oracle_baseline=True):
     from paper_1908_08292_amd import fehmm, rve
     res = {}
     lame = rve.two_phase_lame(10.0)
+    u_end = {}
     for name, kw, n, nrun in MACRO_CASES:
-        for scheme, sname in ((fehmm.NESTED, "nested"), (fehmm.ALTERNATING, "alternating")):
+        runs = [(fehmm.NESTED, "nested", rve.PREC_FP64), (fehmm.ALTERNATING, "alternating", rve.PREC_FP64)]
+        if nrun == 20:
+            runs.append((fehmm.NESTED, "nested_fp32_micro", rve.PREC_FP32_IR))
+        for scheme, sname, prec in runs:
             mesh = rve.Mesh(2, n, lame, radius=0.25)
-            drv = fehmm.Driver(mesh, scheme=scheme, max_macro_iter=40, **kw)
+            drv = fehmm.Driver(mesh, scheme=scheme, max_macro_iter=40, micro_opts=rve.default_opts(precision=prec),
+                               **kw)
             t0 = time.perf_counter()
             its, mic, ok = [], 0, True
             for k in range(1, nrun + 1):
@@ -344,6 +351,14 @@ def macro_bench(oracle_baseline=True):
                                           macro_iters=its, total_macro_iters=int(sum(its)),
                                           micro_updates=int(mic), converged=bool(ok), seconds=dt,
                                           u_max=float(st["u_max"]))
+            u_end[sname] = drv.u()
+            if sname == "nested_fp32_micro":
+                u64 = u_end["nested"]
+                res[f"{name}_{sname}"].update(
+                    micro_precision="f32 assembly and factors + f64 refinement",
+                    speedup_vs_fp64_micro=res[f"{name}_nested"]["seconds"] / dt,
+                    rel_displacement_diff_vs_fp64_micro=float(np.abs(u_end[sname] - u64).max() /
+                                                              max(np.abs(u64).max(), 1e-300)))
             drv.destroy()
     for name in ("plate4x4_rve8x8", "plate64x64_hole_rve16x16"):
         a, b = res[f"{name}_nested"], res[f"{name}_alternating"]
