@@ -265,6 +265,24 @@ def test_autotuned_plan_matches_oracle():
         rve.tuning_reset(d, n)
 
 
+def test_autotuned_plan_matches_oracle_3d():
+    """The autotuner on a 3D mesh whose fronts live in global memory (5^3):
+    leaves 8 / 27 / 64 and slots 512 / 1024; the tuned plan meets the parity bar
+    with equal Newton counts."""
+    torch = torch_cuda()
+    d, n, B = 3, 5, 24
+    F = workloads.draw_F(np.random.default_rng(47), B, d, 0.1)
+    mesh = rve.Mesh(d, n, rve.two_phase_lame(10.0), radius=0.3)
+    t = rve.autotune(mesh, torch.tensor(F.reshape(-1), device="cuda"))
+    try:
+        print("tuned:", t, flush=True)
+        assert t["leaf"] in (8, 27, 64) and t["slots"] in (512, 1024) and t["ms"] > 0
+        out = run_gpu(d, np.full(B, n), np.full(B, 0.3), np.full(B, 10.0), F)
+        compare(d, np.full(B, n), np.full(B, 0.3), np.full(B, 10.0), F, out, idx=range(0, B, 3))
+    finally:
+        rve.tuning_reset(d, n)
+
+
 @pytest.mark.parametrize("n,threads", [(8, 512), (32, 256)])
 def test_workgroup_size_choice_matches_oracle(n, threads):
     """Either workgroup size runs every mesh whose fronts fit LDS: eight waves on a
