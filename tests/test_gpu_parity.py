@@ -283,6 +283,24 @@ def test_autotuned_plan_matches_oracle_3d():
         rve.tuning_reset(d, n)
 
 
+@pytest.mark.parametrize("n", [16, 32])
+def test_eight_wave_fp32_solver_matches_oracle(n):
+    """The eight-wave solver with FP32 factors (which the size rule never picks:
+    FP32 fronts leave room for two four-wave workgroups per CU, but the autotuner
+    may) meets the FP32 + refinement bar."""
+    torch_cuda()
+    d, B = 2, 48
+    F = workloads.draw_F(np.random.default_rng(53 + n), B, d, 0.15)
+    rve.tuning_set(d, n, threads=512)
+    print(f"case 2d n={n} B={B} threads=512 fp32ir", flush=True)
+    try:
+        out = run_gpu(d, np.full(B, n), np.full(B, 0.3), np.full(B, 10.0), F,
+                      opts=rve.default_opts(precision=rve.PREC_FP32_IR))
+        compare_loose_iters(d, np.full(B, n), np.full(B, 0.3), np.full(B, 10.0), F, out, idx=range(0, B, 4))
+    finally:
+        rve.tuning_reset(d, n)
+
+
 @pytest.mark.parametrize("n,threads", [(8, 512), (32, 256)])
 def test_workgroup_size_choice_matches_oracle(n, threads):
     """Either workgroup size runs every mesh whose fronts fit LDS: eight waves on a
