@@ -12,8 +12,8 @@ from paper_1908_08292_amd import api, rve, workloads  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 
-def _run(wl, static, w0=None):
-    batch, meshes = api.build_batch(2, wl.n, wl.radius, wl.ratio)
+def _run(wl, static, w0=None, d=2, opts=None):
+    batch, meshes = api.build_batch(d, wl.n, wl.radius, wl.ratio)
     s = api.Solver(batch)
     s.set_F(wl.F)
     if w0 is not None:
@@ -23,7 +23,7 @@ def _run(wl, static, w0=None):
     s.A.fill_(7.0)
     s.status.fill_(9)
     s.iters.fill_(-1)
-    batch.solve(s.F, s.P, s.A, s.w, s.status, s.iters, static=static)
+    batch.solve(s.F, s.P, s.A, s.w, s.status, s.iters, opts=opts, static=static)
     torch.cuda.synchronize()
     out = s.results()
     out["w"] = s.w.cpu().numpy()
@@ -52,6 +52,17 @@ def test_static_matches_allocating_entry_point_twice():
     got2 = _run(small, static=True, w0=w0)
     assert np.all(ref2["status"] == 0)
     _same(got2, ref2)
+
+
+def test_static_matches_allocating_entry_point_3d_fp32():
+    """The same on global-front plans (3D 6^3 and 8^3) with FP32 factors."""
+    print("[no_alloc] 3D: 8 RVEs of 6^3 / 8^3, FP32 factors", flush=True)
+    wl = workloads.rve3d(8, sizes=(6, 8), seed=2026)
+    o = rve.default_opts(precision=rve.PREC_FP32_IR)
+    ref = _run(wl, static=False, d=3, opts=o)
+    got = _run(wl, static=True, d=3, opts=o)
+    assert np.all(ref["status"] == 0)
+    _same(got, ref)
 
 
 def test_static_rejects_a_slot_larger_than_the_array():
