@@ -1374,8 +1374,8 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
     const DevPlan& pl = *c.plan;
     constexpr int NEN = 1 << D;
     const int lane = threadIdx.x & 63;
-    const DevFront fr = pl.fronts[s];
-    const int m = fr.m, p = fr.p, mu = m - p;
+    const DevFront fr = pl.fronts[uni(s)];  // (uniform per wave: scalar loads)
+    const int m = uni(fr.m), p = uni(fr.p), mu = m - p;
     const int32_t* rows = pl.rows + fr.rows_off;
     T* Lg = reinterpret_cast<T*>(c.L + fr.L_off);
     double* Dg = c.L + fr.D_off;
@@ -1563,8 +1563,8 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
     const DevPlan& pl = *c.plan;
     const int lane = threadIdx.x & 63;
     PROF_T0();
-    const DevFront fr = pl.fronts[s];
-    const int m = fr.m, p = fr.p, mu = m - p;
+    const DevFront fr = pl.fronts[uni(s)];  // (uniform per wave: scalar loads)
+    const int m = uni(fr.m), p = uni(fr.p), mu = m - p;
     const int32_t* rows = pl.rows + fr.rows_off;
     T* Lg = reinterpret_cast<T*>(c.L + fr.L_off);
     double* Dg = c.L + fr.D_off;
@@ -1732,7 +1732,7 @@ template <int D, int NRHS, typename T>
 __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* rl, int wave_slice) {
     constexpr int nrhs = NRHS;
     const DevPlan& pl = *c.plan;
-    const int tid = threadIdx.x, wave = tid >> 6;
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     PROF_T0();
     // small subtrees: one front per wave, all fronts of one height at a time
     for (int h = 0; h < pl.nwave_h; ++h) {
@@ -1777,8 +1777,8 @@ template <int D, int NRHS, typename T>
 __device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
     const DevPlan& pl = *c.plan;
     const int lane = threadIdx.x & 63;
-    const DevFront fr = pl.fronts[s];
-    const int m = fr.m, p = fr.p, mu = m - p;
+    const DevFront fr = pl.fronts[uni(s)];  // (uniform per wave: scalar loads)
+    const int m = uni(fr.m), p = uni(fr.p), mu = m - p;
     const int32_t* rows = pl.rows + fr.rows_off;
     const T* Lg = reinterpret_cast<const T*>(c.L + fr.L_off);
     const double* Dg = c.L + fr.D_off;
@@ -1839,8 +1839,8 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
     const DevPlan& pl = *c.plan;
     const int lane = threadIdx.x & 63;
     constexpr int NPART = (NRHS == 1) ? 3 : 1;
-    const DevFront fr = pl.fronts[s];
-    const int m = fr.m, p = fr.p;
+    const DevFront fr = pl.fronts[uni(s)];  // (uniform per wave: scalar loads)
+    const int m = uni(fr.m), p = uni(fr.p);
     const int32_t* rows = pl.rows + fr.rows_off;
     const T* Lg = reinterpret_cast<const T*>(c.L + fr.L_off);
     const double* Dg = c.L + fr.D_off;
@@ -1976,7 +1976,7 @@ template <int D, int NRHS, typename T>
 __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* rl, double* x, int front_elems,
                                          int wave_slice) {
     const DevPlan& pl = *c.plan;
-    const int tid = threadIdx.x, wave = tid >> 6;
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     zero_pinned<D>(c, x, NRHS);
     // large fronts (the top of the tree) in the plan's steps, then the small
     // subtrees wave by wave
