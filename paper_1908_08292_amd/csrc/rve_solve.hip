@@ -1428,24 +1428,25 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
 #pragma unroll
             for (int q = 0; q < NRHS; ++q) yv[q] = rl[q * m + min(r, m - 1)];
             const double d0 = (double)D0[min(r, m - 1)];
+            T mypiv = T(1);  // the pivot of this lane's row, tested after the block
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 if (j < kb) {
                     const T piv = readlane_t(row[j], K + j);
                     const T rp = recip_t(piv);
-                    if (r == K + j && (!(fabs((double)piv) > 1e-14 * fabs(d0)) || !isfinite((double)piv))) sm.flag = 2;
+                    mypiv = r == K + j ? piv : mypiv;
                     const bool below = act && r > K + j;
                     const T l = below ? row[j] * rp : T(0);
                     const T lpv = l * piv;
-                    // unconditional updates: l = 0 off the rows below the pivot, and
-                    // the only other entries touched, row[cc] with K + cc > r, lie
-                    // above the diagonal and are neither stored nor read
+                    // unconditional updates, past the block bound too (lane K + cc
+                    // <= 63 since K <= 48): l = 0 off the rows below the pivot, and
+                    // the only other entries touched, row[cc] with K + cc > r or
+                    // cc >= kb, lie above the diagonal or outside the block and are
+                    // neither stored nor read as a pivot
 #pragma unroll
                     for (int cc = j + 1; cc < 16; ++cc) {
-                        if (cc < kb) {
-                            const T lc = readlane_t(l, K + cc);
-                            row[cc] -= lpv * lc;
-                        }
+                        const T lc = readlane_t(l, K + cc);
+                        row[cc] -= lpv * lc;
                     }
 #pragma unroll
                     for (int q = 0; q < NRHS; ++q) {
@@ -1455,6 +1456,9 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
                     if (below) row[j] = l;
                 }
             }
+            if (r >= K && r < K + kb &&
+                (!(fabs((double)mypiv) > 1e-14 * fabs(d0)) || !isfinite((double)mypiv)))
+                sm.flag = 2;
 #pragma unroll
             for (int cc = 0; cc < 16; ++cc)
                 if (act && cc < kb && K + cc <= r) F[cpk(K + cc, m) + r - K - cc] = row[cc];
