@@ -160,6 +160,17 @@ typedef struct {
  * w_state); its status is RVE_S_NOCONV.  The alternating two-level Newton of
  * Sec. 5.2 (one micro update per macro iteration) relies on it. */
 #define RVE_FLAG_OUTPUTS_AT_CAP 1
+/* The condensation of Sec. 3.3 (A = <A> - Y^T K^-1 Y at the converged state w)
+ * by default reuses the last Newton factorization on 2D meshes whose fronts fit
+ * LDS: when the quadratic convergence model (r_next = r^3 / r_prev^2) predicts
+ * that the next Newton state converges, that factorization (of the tangent K' at the state one Newton step
+ * before w) also takes the d^2 columns Y' of its state; X = K'^-1 Y' is then
+ * one backward substitution, and A = <A> - Y^T X - X^T (Y - K X) with Y, K of w
+ * is exact up to (X - X*)^T K (X - X*), second order in the last Newton step
+ * (X is refined while ||Y - K X||_F > 1e-4 ||Y||_F).  Where the prediction
+ * missed, and on other meshes, a factorization at w is made.  With this flag the
+ * condensation always factorizes at w (the direct Schur form). */
+#define RVE_FLAG_DIRECT_TANGENT 2
 
 /* rtol 1e-10, atol -1 (default), max_iter 25, FP64, det_backtrack 8, flags 0 */
 void rve_opts_default(rve_opts* o);

@@ -181,7 +181,9 @@ int plan_device(PlanEntry* e) {
     for (const FrontHost& fr : P.fronts) scratch = std::max<int64_t>(scratch, (int64_t)fr.m * (P.d * P.d + 3));
     e->front_elems[0] = std::max<int64_t>(mm * (mm + 1) / 2, scratch);
     e->front_elems[1] = std::max<int64_t>(mm * (mm + 1) / 2, 2 * scratch);
-    e->rl_elems = mm * (P.d * P.d + 1);  // rhs rows, then the original diagonal
+    // rhs rows (d^2 + 1 in 2D: the Newton residual beside the condensation's
+    // columns, see rve_solve_kernel), then the original diagonal
+    e->rl_elems = mm * (P.d * P.d + (P.d == 2 ? 2 : 1));
     const int64_t need = std::max<int64_t>(e->front_elems[0] + e->rl_elems, NWAVE_ * P.wave_slice) *
                          (int64_t)sizeof(double);
     e->lds_bytes = need;
@@ -493,7 +495,7 @@ int rve_batch_create(const rve_mesh* meshes, int64_t B, rve_batch* out) {
     L.w = o; o += rnd(nn * d);
     L.wt = o; o += rnd(nn * d);
     L.R = o; o += rnd(nn * d);
-    L.rhs = o; o += rnd(nn * d * d2);
+    L.rhs = o; o += rnd(nn * d * (d2 + 1));
     L.x = o; o += rnd(nn * d);
     L.fe = o; o += rnd(ne * nd);
     L.ke = o; o += rnd(ne * nd * nd);
@@ -632,6 +634,7 @@ static int solve_batch_impl(rve_batch b, const int32_t* subset, const int32_t* s
     // refinement sweep bought 2e-12 for 12 % of the batch time)
     a.ir_max = 2;
     a.ir_max_tan = 0;
+    a.reuse_tan = (A != nullptr && !(o.flags & RVE_FLAG_DIRECT_TANGENT)) ? 1 : 0;
     a.ir_eta = 1e-2;
     a.ir_eta_tan = 0.0;
     hipError_t e = wide ? nt512::launch_rve_solve(a, nslots, dyn, fp32, (hipStream_t)hip_stream)

@@ -540,11 +540,13 @@ __device__ void residual_act(const RveCtx& c, const double* b, double* out) {
     }
 }
 
-// node gather of element vectors: out[(v*D+i)*nc + col] = sum_a src[e_a(v)][(a*D+i)*nc + col]
+// node gather of element vectors: out[(v*D+i)*ldo + q0 + col] = sum_a src[e_a(v)][(a*D+i)*nc + col]
+// (ldo = nc, q0 = 0 by default)
 template <int D>
-__device__ void node_gather(const RveCtx& c, const double* src, int nc, double* out, double sign) {
+__device__ void node_gather(const RveCtx& c, const double* src, int nc, double* out, double sign, int ldo = 0,
+                            int q0 = 0) {
     constexpr int NEN = 1 << D, ND = NEN * D;
-    const int tot = c.nn * D * nc;
+    const int tot = c.nn * D * nc, ld = ldo > 0 ? ldo : nc;
     for (int t = threadIdx.x; t < tot; t += NT) {
         int col = t % nc, vi = t / nc, v = vi / D, i = vi % D;
         double s = 0;
@@ -553,17 +555,20 @@ __device__ void node_gather(const RveCtx& c, const double* src, int nc, double* 
             int e = element_of_node(D, c.n, v, a);
             s += src[((int64_t)e * ND + a * D + i) * nc + col];
         }
-        out[t] = sign * s;
+        out[(int64_t)vi * ld + q0 + col] = sign * s;
     }
 }
 
 // The element tangents a factorization with NRHS right-hand sides reads: the
-// Newton factorizations (one rhs) read them in the factor type (FP32 for FP32
-// factors), the condensation factorizations (d^2 rhs) in FP64.  (The global
-// path factors the condensation in FP64 and passes NRHS = 1 with T = double.)
-template <int NRHS, typename T>
-__device__ inline const typename std::conditional<NRHS == 1, T, double>::type* ke_of(const RveCtx& c) {
-    return reinterpret_cast<const typename std::conditional<NRHS == 1, T, double>::type*>(c.ke);
+// Newton factorizations (one rhs, or d^2 + 1 with the condensation's columns)
+// read them in the factor type (FP32 for FP32 factors), the condensation
+// factorizations at the converged state (d^2 rhs) in FP64.  (The global path
+// factors the condensation in FP64 and passes NRHS = 1 with T = double.)
+template <int D, int NRHS, typename T>
+using KeType = typename std::conditional<NRHS != D * D, T, double>::type;
+template <int D, int NRHS, typename T>
+__device__ inline const KeType<D, NRHS, T>* ke_of(const RveCtx& c) {
+    return reinterpret_cast<const KeType<D, NRHS, T>*>(c.ke);
 }
 
 // ---------------------------------------------------------------- LDS fronts
@@ -969,7 +974,7 @@ __device__ __attribute__((noinline)) void factorize_glb(const RveCtx& c, Smem& s
             double v = 0;
 #pragma unroll
             for (int q = 0; q < NEN; ++q) {
-                const double kv = (double)ke_of<1, T>(c)[((int64_t)cbs[q].elem * ND + cbs[q].lb * D + k) * ND +
+                const double kv = (double)ke_of<D, 1, T>(c)[((int64_t)cbs[q].elem * ND + cbs[q].lb * D + k) * ND +
                                                          cbs[q].la * D + l];
                 v += (q < kp.c_count) ? kv : 0.0;
             }
@@ -1388,7 +1393,7 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
     }
     __builtin_amdgcn_wave_barrier();
     T* const D0 = rl + m * NRHS;
-    gather_original<NEN>(pl, ke_of<NRHS, T>(c), fr.asm_begin, fr.asm_end, lane, 64, F, m, D0);
+    gather_original<NEN>(pl, ke_of<D, NRHS, T>(c), fr.asm_begin, fr.asm_end, lane, 64, F, m, D0);
     __builtin_amdgcn_wave_barrier();
     for (int q = fr.child_begin; q < fr.child_end; ++q) {
         const DevFront ch = pl.fronts[pl.children[q]];
@@ -1582,7 +1587,7 @@ __device__ inline void wg_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl, i
     __syncthreads();
     // original entries: one gather level, every source load in flight at once
     T* const D0 = rl + m * nrhs;  // original diagonal, after the rhs rows
-    gather_original<NEN>(pl, ke_of<NRHS, T>(c), fr.asm_begin, fr.asm_end, gt, GT, F, m, D0);
+    gather_original<NEN>(pl, ke_of<D, NRHS, T>(c), fr.asm_begin, fr.asm_end, gt, GT, F, m, D0);
     __syncthreads();
     for (int q = fr.child_begin; q < fr.child_end; ++q) {
         const DevFront ch = pl.fronts[pl.children[q]];
@@ -1778,7 +1783,7 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* r
 // rows' solution values are loaded one per lane and broadcast by readlane, and
 // the pivot triangle is swept from the last pivot (no barrier)
 template <int D, int NRHS, typename T>
-__device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
+__device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x, int yq0) {
     const DevPlan& pl = *c.plan;
     const int lane = threadIdx.x & 63;
     const DevFront fr = pl.fronts[uni(s)];  // (uniform per wave: scalar loads)
@@ -1786,7 +1791,7 @@ __device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
     const int32_t* rows = pl.rows + fr.rows_off;
     const T* Lg = reinterpret_cast<const T*>(c.L + fr.L_off);
     const double* Dg = c.L + fr.D_off;
-    const double* yg = c.L + fr.y_off;
+    const double* yg = c.L + fr.y_off + (int64_t)yq0 * p;
     const int lp = cpk(p, m);
     copy_in(S, Lg, lp, lane, 64);
     double v[NRHS], xs[NRHS];
@@ -1839,7 +1844,8 @@ __device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
 // solution scattered to x.  Fronts sharing a step have equal pivot counts, so
 // both halves pass the same barriers.
 template <int D, int NRHS, typename T>
-__device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, double* x, int gt, int GT, int gw) {
+__device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, double* x, int gt, int GT, int gw,
+                                    int yq0) {
     const DevPlan& pl = *c.plan;
     const int lane = threadIdx.x & 63;
     constexpr int NPART = (NRHS == 1) ? 3 : 1;
@@ -1848,7 +1854,7 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
     const int32_t* rows = pl.rows + fr.rows_off;
     const T* Lg = reinterpret_cast<const T*>(c.L + fr.L_off);
     const double* Dg = c.L + fr.D_off;
-    const double* yg = c.L + fr.y_off;
+    const double* yg = c.L + fr.y_off + (int64_t)yq0 * p;
     const int lp = cpk(p, m);
     // (FP64 panels are always staged: one address space for the reads)
     const T* Lp = Lg;
@@ -1972,13 +1978,13 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
 }
 
 // backward substitution L^T x = D^-1 y with NRHS columns; y is each front's
-// stored forward-substituted rhs, x (node-major [dof][NRHS], FP64) receives the
-// solution.  The workgroup fronts in the plan's steps, in reverse (wg_backsolve;
+// stored forward-substituted rhs from its column yq0 on, x (node-major
+// [dof][NRHS], FP64) receives the solution.  The workgroup fronts in the plan's steps, in reverse (wg_backsolve;
 // panels staged in LDS, for FP32 when they fit beside the FP64 scratch), then
 // the small subtrees one front per wave, parents first.
 template <int D, int NRHS, typename T>
 __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* rl, double* x, int front_elems,
-                                         int wave_slice) {
+                                         int wave_slice, int yq0 = 0) {
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     zero_pinned<D>(c, x, NRHS);
@@ -2014,14 +2020,14 @@ __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* r
                 vb = reinterpret_cast<double*>(base);
                 Ls = (nf > 1 || vneed + lp <= front_elems) ? base + vneed : nullptr;
             }
-            wg_backsolve<D, NRHS, T>(c, e[k], Ls, vb, x, tid - g * GT, GT, wave - g * NW);
+            wg_backsolve<D, NRHS, T>(c, e[k], Ls, vb, x, tid - g * GT, GT, wave - g * NW, yq0);
         }
     }
     // small subtrees: one front per wave, parents (greater height) first
     for (int h = pl.nwave_h - 1; h >= 0; --h) {
         T* S = F + (int64_t)wave * wave_slice;
         for (int k = pl.wave_hbeg[h] + wave; k < pl.wave_hbeg[h + 1]; k += NWAVE)
-            backsolve_wave_front<D, NRHS, T>(c, pl.wave_list[k], S, x);
+            backsolve_wave_front<D, NRHS, T>(c, pl.wave_list[k], S, x, yq0);
         __syncthreads();
     }
 }
@@ -2326,7 +2332,15 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
         int status = 0, it = 0;
         bool capped = false, restarted = false;
         if (!finite_in) status = 4;
-        double r0 = 0.0;
+        double r0 = 0.0, rprev = 0.0;
+        // tangent from the last Newton factorization (2D LDS plans): when the
+        // quadratic model r_next ~ r^3 / r_prev^2 puts the next residual within
+        // the tolerance, the factorization also forward-substitutes the d^2
+        // columns Y of the current state (rhs [dof][1 + d^2], R first); if the
+        // next state converges, X ~ K^-1 Y is one backward substitution away
+        constexpr int NSPEC = D2 + 1;
+        const bool spec_on = D == 2 && NSPEC <= kMaxNrhs && a.reuse_tan && c.plan->lds_ok;
+        bool spec = false;  // the last factorization carries the Y columns
         PROF_T0();
         while (status == 0) {
             PROF_RESET();
@@ -2359,10 +2373,36 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                 else status = 1;
                 break;
             }
-            for (int t = threadIdx.x; t < ndof; t += NT) c.rhs[t] = -c.R[t];
-            __syncthreads();
-            if (c.plan->lds_ok) factorize_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
-            else factorize_glb<D, T>(c, sm, 1, dynF);
+            spec = spec_on && it >= 1 && rn * rn * rn <= (a.rtol * r0 + sm.atol) * rprev * rprev;
+            rprev = rn;
+            if constexpr (NSPEC <= kMaxNrhs) {
+                if (spec) {
+                    // Y rows of this state: element pass mode 2 with the FP64
+                    // tangent rows off (the factor-type tangents stay in place)
+                    RveCtx cy = c;
+                    cy.ke32 = 0;
+                    double dP[D2], dA[D2 * D2];
+#pragma unroll
+                    for (int q = 0; q < D2; ++q) dP[q] = 0;
+#pragma unroll
+                    for (int q = 0; q < D2 * D2; ++q) dA[q] = 0;
+                    element_pass<D>(cy, sm, c.w, 2, dP, dA);
+                    __syncthreads();
+                    node_gather<D>(c, c.re, D2, c.rhs, 1.0, NSPEC, 1);
+                    for (int t = threadIdx.x; t < ndof; t += NT) c.rhs[(int64_t)t * NSPEC] = -c.R[t];
+                    __syncthreads();
+                    factorize_lds<D, NSPEC, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
+                    // the refinement below reads the Newton rhs as one column
+                    for (int t = threadIdx.x; t < ndof; t += NT) c.rhs[t] = -c.R[t];
+                    __syncthreads();
+                }
+            }
+            if (!spec) {
+                for (int t = threadIdx.x; t < ndof; t += NT) c.rhs[t] = -c.R[t];
+                __syncthreads();
+                if (c.plan->lds_ok) factorize_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
+                else factorize_glb<D, T>(c, sm, 1, dynF);
+            }
             if (sm.flag) { status = 3; break; }
             PROF_RESET();
             if (c.plan->lds_ok) backsolve_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, c.x, a.lds_front, a.wave_slice);
@@ -2431,11 +2471,18 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                 __syncthreads();
                 node_gather<D>(c, c.re, D2, c.rhs, 1.0);
                 __syncthreads();
-                // the condensation factorization: FP64 (direct Schur form below, no
+                // the condensation: with the Y columns in the last Newton
+                // factorization (state w_prev, one Newton step before w), X from
+                // those factors and the stationary form below, refined while
+                // ||Y - K X||_F > 1e-4 ||Y||_F (at most twice); otherwise a
+                // factorization at w: FP64 (direct Schur form below, no
                 // refinement) for global-front plans and for LDS plans whose FP64
-                // front region keeps the occupancy; otherwise in the factor type
-                const bool tan64 = !IR || !c.plan->lds_ok || a.tan64;
-                if (!c.plan->lds_ok)
+                // front region keeps the occupancy, else in the factor type
+                const bool stale = spec && !capped;
+                const bool tan64 = !stale && (!IR || !c.plan->lds_ok || a.tan64);
+                if (stale)
+                    ;
+                else if (!c.plan->lds_ok)
                     factorize_glb<D, double>(c, sm, D2, dynRaw);
                 else if (IR && a.tan64)
                     factorize_lds<D, D2, double>(c, sm, dynRaw, dynRaw + a.lds_front64, a.wave_slice);
@@ -2444,16 +2491,31 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                 if (sm.flag) {
                     status = 3;
                 } else if (!tan64) {
-                    // X ~ K^-1 Y from the FP32 factors, refined ir_max_tan times against
-                    // the FP64 tangent; then the stationary (second-order) form
+                    // X ~ K^-1 Y from the factors (FP32, or of the previous state),
+                    // refined against the FP64 tangent of w; then the stationary
+                    // (second-order) form
                     //   Abar = <A> - Y^T X - X^T r,  r = Y - K X,
                     // whose error is (X - X*)^T K (X - X*) (energy-norm error squared)
                     double* X = c.re;  // element Y no longer needed: [dof][D2]
-                    backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front, a.wave_slice);
+                    backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front, a.wave_slice,
+                                            stale ? 1 : 0);
+                    const int max_ref = stale ? 2 : a.ir_max_tan;
                     for (int ref = 0;; ++ref) {
                         residual_ke<D, D2>(c, c.rhs, X, ir1);
                         __syncthreads();
-                        if (ref == a.ir_max_tan) break;
+                        if (ref == max_ref) break;
+                        if (stale) {
+                            double nr[2] = {0.0, 0.0};
+                            for (int t = threadIdx.x; t < ndof * D2; t += NT) {
+                                if (is_pinned(*c.plan, t / D2 / D)) continue;
+                                nr[0] += ir1[t] * ir1[t];
+                                nr[1] += c.rhs[t] * c.rhs[t];
+                            }
+                            block_sum<2>(nr, sm);
+                            const bool done = !(sm.outv[0] > 1e-8 * sm.outv[1]);
+                            __syncthreads();
+                            if (done) break;
+                        }
                         forward_lds<D, D2, T>(c, sm, dynF, ir1, a.lds_front);
                         backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front, a.wave_slice);
                         for (int t = threadIdx.x; t < ndof * D2; t += NT) X[t] += ir2[t];

@@ -68,6 +68,7 @@ struct SolveArgs {
     int32_t ir_max_tan;          // refinement sweeps of the tangent solves
     int32_t tan64;               // FP32 factors: the condensation factorization of LDS plans in FP64
     int32_t lds_front64;         // FP64 elements of the front region for that factorization
+    int32_t reuse_tan;           // 2D LDS plans: the condensation from the last Newton factorization
     double ir_eta;               // stop refining when ||b - K x|| <= ir_eta ||R||
     double ir_eta_tan;           // same for the d^2 tangent columns (Frobenius)
 };

@@ -21,6 +21,7 @@ PREC_FP64, PREC_FP32_IR = 0, 1
 LAW_NEOHOOKE, LAW_SVK, LAW_LINEAR = 0, 1, 2
 BC_PERIODIC, BC_LINEAR = 0, 1
 ELEM_Q1, ELEM_P1 = 0, 1
+FLAG_OUTPUTS_AT_CAP, FLAG_DIRECT_TANGENT = 1, 2
 
 
 class RveError(RuntimeError):

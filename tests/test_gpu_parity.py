@@ -316,3 +316,30 @@ def test_workgroup_size_choice_matches_oracle(n, threads):
         compare(d, np.full(B, n), np.full(B, 0.3), np.full(B, 10.0), F, out, idx=range(0, B, 4))
     finally:
         rve.tuning_reset(d, n)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+@pytest.mark.parametrize("n", [4, 16, 32])
+def test_condensation_from_last_newton_factorization(n, prec):
+    """By default the condensation reuses the last Newton factorization (the Y
+    columns of that state forward-substituted with the residual) and takes the
+    stationary form at the converged state; RVE_FLAG_DIRECT_TANGENT factorizes at
+    the converged state.  The Newton iterates are the same arithmetic either way
+    (P and the counts bitwise equal), both tangents meet the oracle bar, and they
+    agree to second order in the last Newton step."""
+    torch_cuda()
+    d, B = 2, 48
+    wl = workloads.rve2d(B, n=n, seed=4100 + n)
+    p = rve.PREC_FP32_IR if prec == "fp32ir" else rve.PREC_FP64
+    print(f"case 2d n={n} B={B} {prec}: reused vs direct condensation", flush=True)
+    reuse = run_gpu(d, wl.n, wl.radius, wl.ratio, wl.F, opts=rve.default_opts(precision=p))
+    direct = run_gpu(d, wl.n, wl.radius, wl.ratio, wl.F,
+                     opts=rve.default_opts(precision=p, flags=rve.FLAG_DIRECT_TANGENT))
+    assert np.all(reuse["status"] == 0) and np.all(direct["status"] == 0)
+    assert np.array_equal(reuse["P"], direct["P"])
+    assert np.array_equal(reuse["iters"], direct["iters"])
+    dA = max(rel(reuse["A"][b], direct["A"][b], 1e-300) for b in range(B))
+    print(f"  max rel difference of A (reused vs direct) {dA:.2e}", flush=True)
+    assert dA <= 1e-8
+    (compare if prec == "fp64" else compare_loose_iters)(d, wl.n, wl.radius, wl.ratio, wl.F, reuse,
+                                                         idx=range(0, B, 6))
