@@ -76,19 +76,22 @@ def make_workload(name):
 def algorithmic_flops(rve, d, n_arr, iters):
     """LDL^T factorizations and triangular solves (2 nnz(L) flops per sweep per
     right-hand side), counted from the symbolic plan of each RVE's mesh size.
-    3D: iters + 1 factorizations per RVE (one at the converged state), forward and
-    backward per Newton step, forward with d^2 columns for the condensation.  2D
-    (fronts in LDS): iters factorizations, the last one with the d^2 condensation
-    columns forward-substituted beside the residual, then their backward sweep
-    (a missed convergence prediction adds a factorization that is not counted)."""
+    The condensation reuses the last Newton factorization (2D, and 3D plans with
+    fronts in global memory): iters factorizations, the last one with the d^2
+    condensation columns forward-substituted beside the residual, then their
+    backward sweep (a missed convergence prediction adds a factorization that is
+    not counted).  3D plans with fronts in LDS: iters + 1 factorizations (one at
+    the converged state, with the d^2 columns forward-substituted)."""
     total = 0.0
     cache = {}
     for n, it in zip(n_arr, iters):
         n = int(n)
         if n not in cache:
-            cache[n] = rve.plan_info(d, n)
-        pi = cache[n]
-        if d == 2:
+            sch = rve.plan_schedule(d, n)
+            lds = bool(sch["wave"].any()) or len(sch["steps"]) > 0
+            cache[n] = (rve.plan_info(d, n), d == 2 or not lds)
+        pi, reuse = cache[n]
+        if reuse:
             total += it * pi["factor_flops"] + it * 4.0 * pi["nnz_L"] + 4.0 * d * d * pi["nnz_L"]
         else:
             total += (it + 1) * pi["factor_flops"] + it * 4.0 * pi["nnz_L"] + 2.0 * d * d * pi["nnz_L"]

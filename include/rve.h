@@ -161,14 +161,15 @@ typedef struct {
  * Sec. 5.2 (one micro update per macro iteration) relies on it. */
 #define RVE_FLAG_OUTPUTS_AT_CAP 1
 /* The condensation of Sec. 3.3 (A = <A> - Y^T K^-1 Y at the converged state w)
- * by default reuses the last Newton factorization on 2D meshes whose fronts fit
- * LDS: when the quadratic convergence model (r_next = r^3 / r_prev^2) predicts
- * that the next Newton state converges, that factorization (of the tangent K' at the state one Newton step
- * before w) also takes the d^2 columns Y' of its state; X = K'^-1 Y' is then
- * one backward substitution, and A = <A> - Y^T X - X^T (Y - K X) with Y, K of w
- * is exact up to (X - X*)^T K (X - X*), second order in the last Newton step
- * (X is refined while ||Y - K X||_F > 1e-4 ||Y||_F).  Where the prediction
- * missed, and on other meshes, a factorization at w is made.  With this flag the
+ * by default reuses the last Newton factorization (2D meshes, and 3D meshes
+ * whose fronts live in global memory): when the quadratic convergence model
+ * r_next = r^3 / r_prev^2 predicts that the next Newton state converges, that
+ * factorization (of the tangent K' one Newton step before w) also takes the d^2
+ * columns Y' of its state.  X = K'^-1 Y' is then one backward substitution, and
+ * A = <A> - Y^T X - X^T (Y - K X) with Y, K of w is exact up to
+ * (X - X*)^T K (X - X*), second order in the last Newton step (X is refined
+ * while ||Y - K X||_F > 1e-4 ||Y||_F).  Where the prediction missed, and on 3D
+ * meshes whose fronts fit LDS, a factorization at w is made.  With this flag the
  * condensation always factorizes at w (the direct Schur form). */
 #define RVE_FLAG_DIRECT_TANGENT 2
 

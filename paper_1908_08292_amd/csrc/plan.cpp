@@ -413,8 +413,12 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
         // the front region: the packed fronts with their rhs rows and diagonals,
         // and in the backward substitution the staged panels with their FP64
         // scratch (d^2 m + 3 p doubles, i.e. twice as many FP32 elements).
-        const int64_t mm = P.max_m, region = mm * (mm + 1) / 2 + mm * (d * d + 1);
-        auto fneed = [&](const FrontHost& X) { return (int64_t)X.m * (X.m + 1) / 2 + (int64_t)X.m * (d * d + 1); };
+        // (rhs rows: d^2 + 1 columns in 2D, where the last Newton factorization
+        // carries the condensation's columns beside the residual; then the
+        // original diagonal)
+        const int64_t rr = d * d + (d == 2 ? 2 : 1);
+        const int64_t mm = P.max_m, region = mm * (mm + 1) / 2 + mm * rr;
+        auto fneed = [&](const FrontHost& X) { return (int64_t)X.m * (X.m + 1) / 2 + (int64_t)X.m * rr; };
         auto bneed = [&](const FrontHost& X) {
             return (int64_t)X.p * X.m - (int64_t)X.p * (X.p - 1) / 2 + 2 * ((int64_t)d * d * X.m + 3 * (int64_t)X.p) + 1;
         };

@@ -14,7 +14,7 @@
 
 namespace fehmm {
 
-constexpr int kMaxNrhs = 9;  // d^2 right-hand sides of the tangent condensation (3D)
+constexpr int kMaxNrhs = 10;  // the Newton residual beside the d^2 columns of the condensation (3D)
 
 struct FrontHost {
     int m = 0, p = 0;           // dofs in the front, pivot dofs (leading)

@@ -1205,7 +1205,7 @@ __device__ __attribute__((noinline)) void forward_glb(const RveCtx& c, Smem& sm,
 // triangle with readlane broadcasts, all threads fold the block into the
 // earlier pivots.
 template <int D, int NRHS, typename T>
-__device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& sm, double* xo) {
+__device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& sm, double* xo, int yq0 = 0) {
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     zero_pinned<D>(c, xo, NRHS);
@@ -1218,7 +1218,7 @@ __device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& s
         const int32_t* rows = uni(pl.rows + fr.rows_off);
         const T* Fp = reinterpret_cast<const T*>(cL + uni(fr.L_off));
         const T* Dg = reinterpret_cast<const T*>(cL + uni(fr.D_off));
-        double* y = cL + uni(fr.y_off);
+        double* y = cL + uni(fr.y_off) + (int64_t)uni(yq0) * p;
         for (int j = tid; j < p; j += NT) {
             const double rd = 1.0 / (double)Dg[j];
             double v[NRHS];
@@ -2333,13 +2333,14 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
         bool capped = false, restarted = false;
         if (!finite_in) status = 4;
         double r0 = 0.0, rprev = 0.0;
-        // tangent from the last Newton factorization (2D LDS plans): when the
+        // tangent from the last Newton factorization (LDS plans in 2D, global-
+        // front plans in either dimension): when the
         // quadratic model r_next ~ r^3 / r_prev^2 puts the next residual within
         // the tolerance, the factorization also forward-substitutes the d^2
         // columns Y of the current state (rhs [dof][1 + d^2], R first); if the
         // next state converges, X ~ K^-1 Y is one backward substitution away
         constexpr int NSPEC = D2 + 1;
-        const bool spec_on = D == 2 && NSPEC <= kMaxNrhs && a.reuse_tan && c.plan->lds_ok;
+        const bool spec_on = NSPEC <= kMaxNrhs && a.reuse_tan && (D == 2 || !c.plan->lds_ok);
         bool spec = false;  // the last factorization carries the Y columns
         PROF_T0();
         while (status == 0) {
@@ -2391,7 +2392,8 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                     node_gather<D>(c, c.re, D2, c.rhs, 1.0, NSPEC, 1);
                     for (int t = threadIdx.x; t < ndof; t += NT) c.rhs[(int64_t)t * NSPEC] = -c.R[t];
                     __syncthreads();
-                    factorize_lds<D, NSPEC, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
+                    if (!c.plan->lds_ok) factorize_glb<D, T>(c, sm, NSPEC, dynF);
+                    else if constexpr (D == 2) factorize_lds<D, NSPEC, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
                     // the refinement below reads the Newton rhs as one column
                     for (int t = threadIdx.x; t < ndof; t += NT) c.rhs[t] = -c.R[t];
                     __syncthreads();
@@ -2497,8 +2499,11 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                     //   Abar = <A> - Y^T X - X^T r,  r = Y - K X,
                     // whose error is (X - X*)^T K (X - X*) (energy-norm error squared)
                     double* X = c.re;  // element Y no longer needed: [dof][D2]
-                    backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front, a.wave_slice,
-                                            stale ? 1 : 0);
+                    if (c.plan->lds_ok)
+                        backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front, a.wave_slice,
+                                                stale ? 1 : 0);
+                    else
+                        backsolve_glb<D, D2, T>(c, sm, X, 1);  // (global-front plans reach here only stale)
                     const int max_ref = stale ? 2 : a.ir_max_tan;
                     for (int ref = 0;; ++ref) {
                         residual_ke<D, D2>(c, c.rhs, X, ir1);
@@ -2516,8 +2521,13 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                             __syncthreads();
                             if (done) break;
                         }
-                        forward_lds<D, D2, T>(c, sm, dynF, ir1, a.lds_front);
-                        backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front, a.wave_slice);
+                        if (c.plan->lds_ok) {
+                            forward_lds<D, D2, T>(c, sm, dynF, ir1, a.lds_front);
+                            backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front, a.wave_slice);
+                        } else {
+                            forward_glb<D, D2, T>(c, sm, ir1);
+                            backsolve_glb<D, D2, T>(c, sm, ir2);
+                        }
                         for (int t = threadIdx.x; t < ndof * D2; t += NT) X[t] += ir2[t];
                         __syncthreads();
                     }

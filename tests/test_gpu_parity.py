@@ -343,3 +343,24 @@ def test_condensation_from_last_newton_factorization(n, prec):
     assert dA <= 1e-8
     (compare if prec == "fp64" else compare_loose_iters)(d, wl.n, wl.radius, wl.ratio, wl.F, reuse,
                                                          idx=range(0, B, 6))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_condensation_from_last_newton_factorization_3d(prec):
+    """The same reuse on 3D plans whose fronts live in global memory (n = 5, 6, 8
+    in one batch; n = 4 fits LDS and takes the factorization at the converged
+    state)."""
+    torch_cuda()
+    wl = workloads.rve3d(8, sizes=(4, 5, 6, 8), seed=4200)
+    p = rve.PREC_FP32_IR if prec == "fp32ir" else rve.PREC_FP64
+    print(f"case 3d n={list(wl.n)} {prec}: reused vs direct condensation", flush=True)
+    reuse = run_gpu(3, wl.n, wl.radius, wl.ratio, wl.F, opts=rve.default_opts(precision=p))
+    direct = run_gpu(3, wl.n, wl.radius, wl.ratio, wl.F,
+                     opts=rve.default_opts(precision=p, flags=rve.FLAG_DIRECT_TANGENT))
+    assert np.all(reuse["status"] == 0) and np.all(direct["status"] == 0)
+    assert np.array_equal(reuse["P"], direct["P"])
+    assert np.array_equal(reuse["iters"], direct["iters"])
+    dA = max(rel(reuse["A"][b], direct["A"][b], 1e-300) for b in range(len(wl.F)))
+    print(f"  max rel difference of A (reused vs direct) {dA:.2e}", flush=True)
+    assert dA <= 1e-8
+    (compare if prec == "fp64" else compare_loose_iters)(3, wl.n, wl.radius, wl.ratio, wl.F, reuse)
