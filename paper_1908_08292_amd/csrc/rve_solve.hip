@@ -1107,15 +1107,22 @@ __device__ __attribute__((noinline)) void factorize_glb(const RveCtx& c, Smem& s
                     }
                 }
                 __syncthreads();
-                // (d) rhs of the rows below: b_i -= sum_c L(i, K + c) y(K + c)
-                for (int t = tid; t < (m - R0) * nrhs; t += NT) {
-                    const int i = R0 + t % (m - R0), q = t / (m - R0);
-                    double acc = 0.0;
+                // (d) rhs of the rows below: b_i -= sum_c L(i, K + c) y(K + c),
+                //     one row per thread for every column (the row's 16 L entries
+                //     read once)
+                for (int i = R0 + tid; i < m; i += NT) {
+                    double lk[16];
 #pragma unroll
-                    for (int cc = 0; cc < 16; ++cc)
-                        if (cc < kb) acc += (double)Fp[(int64_t)(K + cc) * m + i] * y[(int64_t)q * p + K + cc];
-                    if (i < p) y[(int64_t)q * p + i] -= acc;
-                    else rus[(int64_t)q * mu + (i - p)] -= acc;
+                    for (int cc = 0; cc < 16; ++cc) lk[cc] = cc < kb ? (double)Fp[(int64_t)(K + cc) * m + i] : 0.0;
+                    for (int q = 0; q < nrhs; ++q) {
+                        const double* yq = y + (int64_t)q * p + K;
+                        double acc = 0.0;
+#pragma unroll
+                        for (int cc = 0; cc < 16; ++cc)
+                            if (cc < kb) acc += lk[cc] * yq[cc];
+                        if (i < p) y[(int64_t)q * p + i] -= acc;
+                        else rus[(int64_t)q * mu + (i - p)] -= acc;
+                    }
                 }
                 __syncthreads();
                 PROF_MARK(PH_TRSM);
