@@ -414,13 +414,14 @@ PlanHost build_plan(int d, int n, const PlanParams& prm) {
         // and in the backward substitution the staged panels with their FP64
         // scratch (d^2 m + 3 p doubles, i.e. twice as many FP32 elements).
         // (rhs rows: d^2 + 1 columns in 2D, where the last Newton factorization
-        // carries the condensation's columns beside the residual; then the
-        // original diagonal)
+        // and its backward substitution carry the condensation's columns beside
+        // the residual; then the original diagonal)
         const int64_t rr = d * d + (d == 2 ? 2 : 1);
         const int64_t mm = P.max_m, region = mm * (mm + 1) / 2 + mm * rr;
         auto fneed = [&](const FrontHost& X) { return (int64_t)X.m * (X.m + 1) / 2 + (int64_t)X.m * rr; };
+        const int64_t bc = d * d + (d == 2 ? 1 : 0);  // backward-substituted columns
         auto bneed = [&](const FrontHost& X) {
-            return (int64_t)X.p * X.m - (int64_t)X.p * (X.p - 1) / 2 + 2 * ((int64_t)d * d * X.m + 3 * (int64_t)X.p) + 1;
+            return (int64_t)X.p * X.m - (int64_t)X.p * (X.p - 1) / 2 + 2 * (bc * X.m + 3 * (int64_t)X.p) + 1;
         };
         int hmax = 0;
         for (const FrontHost& F : P.fronts) hmax = std::max(hmax, F.height);

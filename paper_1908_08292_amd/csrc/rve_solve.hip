@@ -526,17 +526,17 @@ __device__ inline void element_pass(const RveCtx& c, Smem& sm, const double* w, 
     }
 }
 
-// out = b - K x on the free dofs (0 on the pinned ones), from the element
+// out = sb * b - K x on the free dofs (0 on the pinned ones), from the element
 // products k_e x_e that element pass mode 3 left in the force slots
 template <int D>
-__device__ void residual_act(const RveCtx& c, const double* b, double* out) {
+__device__ void residual_act(const RveCtx& c, const double* b, double sb, double* out) {
     constexpr int NEN = 1 << D, ND = NEN * D;
     for (int vi = threadIdx.x; vi < c.nn * D; vi += NT) {
         const int v = vi / D, i = vi % D;
         double s = 0.0;
 #pragma unroll
         for (int a = 0; a < NEN; ++a) s += c.fe[(int64_t)element_of_node(D, c.n, v, a) * ND + a * D + i];
-        out[vi] = is_pinned(*c.plan, v) ? 0.0 : b[vi] - s;
+        out[vi] = is_pinned(*c.plan, v) ? 0.0 : sb * b[vi] - s;
     }
 }
 
@@ -1212,7 +1212,7 @@ __device__ __attribute__((noinline)) void forward_glb(const RveCtx& c, Smem& sm,
 // triangle with readlane broadcasts, all threads fold the block into the
 // earlier pivots.
 template <int D, int NRHS, typename T>
-__device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& sm, double* xo, int yq0 = 0) {
+__device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& sm, double* xo) {
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     zero_pinned<D>(c, xo, NRHS);
@@ -1225,7 +1225,7 @@ __device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& s
         const int32_t* rows = uni(pl.rows + fr.rows_off);
         const T* Fp = reinterpret_cast<const T*>(cL + uni(fr.L_off));
         const T* Dg = reinterpret_cast<const T*>(cL + uni(fr.D_off));
-        double* y = cL + uni(fr.y_off) + (int64_t)uni(yq0) * p;
+        double* y = cL + uni(fr.y_off);
         for (int j = tid; j < p; j += NT) {
             const double rd = 1.0 / (double)Dg[j];
             double v[NRHS];
@@ -1790,7 +1790,7 @@ __device__ __noinline__ void factorize_lds(const RveCtx& c, Smem& sm, T* F, T* r
 // rows' solution values are loaded one per lane and broadcast by readlane, and
 // the pivot triangle is swept from the last pivot (no barrier)
 template <int D, int NRHS, typename T>
-__device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x, int yq0) {
+__device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x) {
     const DevPlan& pl = *c.plan;
     const int lane = threadIdx.x & 63;
     const DevFront fr = pl.fronts[uni(s)];  // (uniform per wave: scalar loads)
@@ -1798,7 +1798,7 @@ __device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x, in
     const int32_t* rows = pl.rows + fr.rows_off;
     const T* Lg = reinterpret_cast<const T*>(c.L + fr.L_off);
     const double* Dg = c.L + fr.D_off;
-    const double* yg = c.L + fr.y_off + (int64_t)yq0 * p;
+    const double* yg = c.L + fr.y_off;
     const int lp = cpk(p, m);
     copy_in(S, Lg, lp, lane, 64);
     double v[NRHS], xs[NRHS];
@@ -1851,8 +1851,7 @@ __device__ void backsolve_wave_front(const RveCtx& c, int s, T* S, double* x, in
 // solution scattered to x.  Fronts sharing a step have equal pivot counts, so
 // both halves pass the same barriers.
 template <int D, int NRHS, typename T>
-__device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, double* x, int gt, int GT, int gw,
-                                    int yq0) {
+__device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, double* x, int gt, int GT, int gw) {
     const DevPlan& pl = *c.plan;
     const int lane = threadIdx.x & 63;
     constexpr int NPART = (NRHS == 1) ? 3 : 1;
@@ -1861,7 +1860,7 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
     const int32_t* rows = pl.rows + fr.rows_off;
     const T* Lg = reinterpret_cast<const T*>(c.L + fr.L_off);
     const double* Dg = c.L + fr.D_off;
-    const double* yg = c.L + fr.y_off + (int64_t)yq0 * p;
+    const double* yg = c.L + fr.y_off;
     const int lp = cpk(p, m);
     // (FP64 panels are always staged: one address space for the reads)
     const T* Lp = Lg;
@@ -1985,13 +1984,13 @@ __device__ inline void wg_backsolve(const RveCtx& c, int s, T* Ls, double* vb, d
 }
 
 // backward substitution L^T x = D^-1 y with NRHS columns; y is each front's
-// stored forward-substituted rhs from its column yq0 on, x (node-major
-// [dof][NRHS], FP64) receives the solution.  The workgroup fronts in the plan's steps, in reverse (wg_backsolve;
+// stored forward-substituted rhs, x (node-major [dof][NRHS], FP64) receives the
+// solution.  The workgroup fronts in the plan's steps, in reverse (wg_backsolve;
 // panels staged in LDS, for FP32 when they fit beside the FP64 scratch), then
 // the small subtrees one front per wave, parents first.
 template <int D, int NRHS, typename T>
 __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* rl, double* x, int front_elems,
-                                         int wave_slice, int yq0 = 0) {
+                                         int wave_slice) {
     const DevPlan& pl = *c.plan;
     const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     zero_pinned<D>(c, x, NRHS);
@@ -2027,14 +2026,14 @@ __device__ __noinline__ void backsolve_lds(const RveCtx& c, Smem& sm, T* F, T* r
                 vb = reinterpret_cast<double*>(base);
                 Ls = (nf > 1 || vneed + lp <= front_elems) ? base + vneed : nullptr;
             }
-            wg_backsolve<D, NRHS, T>(c, e[k], Ls, vb, x, tid - g * GT, GT, wave - g * NW, yq0);
+            wg_backsolve<D, NRHS, T>(c, e[k], Ls, vb, x, tid - g * GT, GT, wave - g * NW);
         }
     }
     // small subtrees: one front per wave, parents (greater height) first
     for (int h = pl.nwave_h - 1; h >= 0; --h) {
         T* S = F + (int64_t)wave * wave_slice;
         for (int k = pl.wave_hbeg[h] + wave; k < pl.wave_hbeg[h + 1]; k += NWAVE)
-            backsolve_wave_front<D, NRHS, T>(c, pl.wave_list[k], S, x, yq0);
+            backsolve_wave_front<D, NRHS, T>(c, pl.wave_list[k], S, x);
         __syncthreads();
     }
 }
@@ -2401,9 +2400,6 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                     __syncthreads();
                     if (!c.plan->lds_ok) factorize_glb<D, T>(c, sm, NSPEC, dynF);
                     else if constexpr (D == 2) factorize_lds<D, NSPEC, T>(c, sm, dynF, dynF + a.lds_front, a.wave_slice);
-                    // the refinement below reads the Newton rhs as one column
-                    for (int t = threadIdx.x; t < ndof; t += NT) c.rhs[t] = -c.R[t];
-                    __syncthreads();
                 }
             }
             if (!spec) {
@@ -2414,8 +2410,22 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
             }
             if (sm.flag) { status = 3; break; }
             PROF_RESET();
-            if (c.plan->lds_ok) backsolve_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, c.x, a.lds_front, a.wave_slice);
-            else backsolve_glb<D, 1, T>(c, sm, c.x);
+            if constexpr (NSPEC <= kMaxNrhs) {
+                if (spec) {
+                    // every column in one backward sweep, into the rhs buffer
+                    // ([dof][1 + d^2]): the Newton step, then X' = K'^-1 Y', which
+                    // stays there for the condensation if the next state converges
+                    if (!c.plan->lds_ok) backsolve_glb<D, NSPEC, T>(c, sm, c.rhs);
+                    else if constexpr (D == 2)
+                        backsolve_lds<D, NSPEC, T>(c, sm, dynF, dynF + a.lds_front, c.rhs, a.lds_front, a.wave_slice);
+                    for (int t = threadIdx.x; t < ndof; t += NT) c.x[t] = c.rhs[(int64_t)t * NSPEC];
+                    __syncthreads();
+                }
+            }
+            if (!spec) {
+                if (c.plan->lds_ok) backsolve_lds<D, 1, T>(c, sm, dynF, dynF + a.lds_front, c.x, a.lds_front, a.wave_slice);
+                else backsolve_glb<D, 1, T>(c, sm, c.x);
+            }
             PROF_MARK(PH_BACK);
             if constexpr (IR) {
                 // refinement against the FP64 tangent: dx = K32^-1 (b - K64 x), with
@@ -2423,7 +2433,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                 for (int ref = 0; ref < a.ir_max; ++ref) {
                     element_pass<D>(c, sm, c.w, 3, nullptr, nullptr, c.x);
                     __syncthreads();
-                    residual_act<D>(c, c.rhs, ir1);
+                    residual_act<D>(c, c.R, -1.0, ir1);  // b = -R
                     __syncthreads();
                     const double rl2 = sqrt(free_norm2<D>(c, sm, ir1));
                     if (!(rl2 > a.ir_eta * rn)) break;
@@ -2478,17 +2488,29 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                 block_sum<D2 * D2>(accA, sm);
                 double Aavg = threadIdx.x < D2 * D2 ? sm.outv[threadIdx.x] : 0.0;
                 __syncthreads();
-                node_gather<D>(c, c.re, D2, c.rhs, 1.0);
-                __syncthreads();
                 // the condensation: with the Y columns in the last Newton
                 // factorization (state w_prev, one Newton step before w), X from
-                // those factors and the stationary form below, refined while
-                // ||Y - K X||_F > 1e-4 ||Y||_F (at most twice); otherwise a
-                // factorization at w: FP64 (direct Schur form below, no
-                // refinement) for global-front plans and for LDS plans whose FP64
-                // front region keeps the occupancy, else in the factor type
+                // the last Newton solve (still in the rhs buffer) and the
+                // stationary form below, refined while ||Y - K X||_F >
+                // 1e-4 ||Y||_F (at most twice); otherwise a factorization at w:
+                // FP64 (direct Schur form below, no refinement) for global-front
+                // plans and for LDS plans whose FP64 front region keeps the
+                // occupancy, else in the factor type
                 const bool stale = spec && !capped;
                 const bool tan64 = !stale && (!IR || !c.plan->lds_ok || a.tan64);
+                // Y of w: into the rhs buffer for a factorization at w, else
+                // beside X (ir2), X then moved into the element-Y slots
+                double* const Y = stale ? ir2 : c.rhs;
+                double* const X = c.re;  // [dof][D2] once the element Y rows are gathered
+                node_gather<D>(c, c.re, D2, Y, 1.0);
+                __syncthreads();
+                if constexpr (NSPEC <= kMaxNrhs) {
+                    if (stale) {
+                        for (int t = threadIdx.x; t < ndof * D2; t += NT)
+                            X[t] = c.rhs[(int64_t)(t / D2) * NSPEC + 1 + t % D2];
+                        __syncthreads();
+                    }
+                }
                 if (stale)
                     ;
                 else if (!c.plan->lds_ok)
@@ -2505,15 +2527,12 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                     // (second-order) form
                     //   Abar = <A> - Y^T X - X^T r,  r = Y - K X,
                     // whose error is (X - X*)^T K (X - X*) (energy-norm error squared)
-                    double* X = c.re;  // element Y no longer needed: [dof][D2]
-                    if (c.plan->lds_ok)
-                        backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front, a.wave_slice,
-                                                stale ? 1 : 0);
-                    else
-                        backsolve_glb<D, D2, T>(c, sm, X, 1);  // (global-front plans reach here only stale)
+                    if (!stale) backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, X, a.lds_front, a.wave_slice);
+                    // refinement corrections: ir2 unless it holds Y
+                    double* const corr = stale ? c.rhs : ir2;
                     const int max_ref = stale ? 2 : a.ir_max_tan;
                     for (int ref = 0;; ++ref) {
-                        residual_ke<D, D2>(c, c.rhs, X, ir1);
+                        residual_ke<D, D2>(c, Y, X, ir1);
                         __syncthreads();
                         if (ref == max_ref) break;
                         if (stale) {
@@ -2521,7 +2540,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                             for (int t = threadIdx.x; t < ndof * D2; t += NT) {
                                 if (is_pinned(*c.plan, t / D2 / D)) continue;
                                 nr[0] += ir1[t] * ir1[t];
-                                nr[1] += c.rhs[t] * c.rhs[t];
+                                nr[1] += Y[t] * Y[t];
                             }
                             block_sum<2>(nr, sm);
                             const bool done = !(sm.outv[0] > 1e-8 * sm.outv[1]);
@@ -2530,12 +2549,12 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                         }
                         if (c.plan->lds_ok) {
                             forward_lds<D, D2, T>(c, sm, dynF, ir1, a.lds_front);
-                            backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, ir2, a.lds_front, a.wave_slice);
+                            backsolve_lds<D, D2, T>(c, sm, dynF, dynF + a.lds_front, corr, a.lds_front, a.wave_slice);
                         } else {
                             forward_glb<D, D2, T>(c, sm, ir1);
-                            backsolve_glb<D, D2, T>(c, sm, ir2);
+                            backsolve_glb<D, D2, T>(c, sm, corr);
                         }
-                        for (int t = threadIdx.x; t < ndof * D2; t += NT) X[t] += ir2[t];
+                        for (int t = threadIdx.x; t < ndof * D2; t += NT) X[t] += corr[t];
                         __syncthreads();
                     }
                     double acc[D2 * D2];
@@ -2547,7 +2566,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
                         for (int g = 0; g < D2; ++g)
 #pragma unroll
                             for (int h2 = 0; h2 < D2; ++h2)
-                                acc[g * D2 + h2] += c.rhs[t * D2 + g] * X[t * D2 + h2] + X[t * D2 + g] * ir1[t * D2 + h2];
+                                acc[g * D2 + h2] += Y[t * D2 + g] * X[t * D2 + h2] + X[t * D2 + g] * ir1[t * D2 + h2];
                     }
                     block_sum<D2 * D2>(acc, sm);
                     if (threadIdx.x < D2 * D2) Aout[threadIdx.x] = Aavg - sm.outv[threadIdx.x];
