@@ -218,8 +218,8 @@ int rve_solve_batch_sync(rve_batch b, const double* F, double* P, double* A, dou
  * and one slot per persistent workgroup) lives in a static device array of
  * RVE_STATIC_SCRATCH_BYTES instead of the batch's own slots, so the call makes
  * no hipMalloc, hipFree or other allocating call.  The number of persistent
- * workgroups is min(the batch's slots, what fits the array): 1424 for 2D 8 x 8,
- * 236 for 16 x 16, 44 for 32 x 32 (rve_solve_batch: up to 1024), so batches of
+ * workgroups is min(the batch's slots, what fits the array): 1398 for 2D 8 x 8,
+ * 232 for 16 x 16, 43 for 32 x 32 (rve_solve_batch: up to 1024), so batches of
  * large RVEs take longer; 3D: 19 (8^3), 4 (12^3), 1 (16^3).
  * Each device holds its own copy of the array from the first call on it until
  * the process ends (the first call on a device also looks its address up).

@@ -1300,28 +1300,27 @@ __device__ __attribute__((noinline)) void backsolve_glb(const RveCtx& c, Smem& s
 
 
 // Original entries of an LDS front from the element matrices (one gather level)
-// and the extend-add of a child's packed update matrix: four (gather) or eight
-// (extend-add) strides of the list per pass, every index load first, then every
-// value load (clamped addresses, zeros selected), then the stores, so a pass
-// costs one or two memory round trips for all its strides.  first / stride: the
-// caller's lane (wave-level) or thread (workgroup-level) numbering.  D0 (LDS)
-// receives the original diagonal of the pivot columns, the scale of the
-// vanishing-pivot test.
-template <int NEN, typename KT, typename T>
+// and the extend-add of a child's packed update matrix: U strides of the list
+// per pass, every index load first, then every value load (clamped addresses,
+// zeros selected), then the stores, so a pass costs one or two memory round
+// trips for all its strides.  first / stride: the caller's lane (wave-level) or
+// thread (workgroup-level) numbering.  D0 (LDS) receives the original diagonal
+// of the pivot columns, the scale of the vanishing-pivot test.
+template <int NEN, int U = 4, typename KT, typename T>
 __device__ inline void gather_original(const DevPlan& pl, const KT* ke, int a0, int a1, int first, int stride,
                                        T* F, int m, T* D0) {
-    for (int t0 = a0 + first; t0 < a1; t0 += 4 * stride) {
-        int rc[4], src[4][NEN];
+    for (int t0 = a0 + first; t0 < a1; t0 += U * stride) {
+        int rc[U], src[U][NEN];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int t = min(t0 + u * stride, a1 - 1);
             rc[u] = pl.asm_rc[t];
 #pragma unroll
             for (int q = 0; q < NEN; ++q) src[u][q] = pl.asm_src[(int64_t)t * NEN + q];
         }
-        double v[4];
+        double v[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             v[u] = 0.0;
 #pragma unroll
             for (int q = 0; q < NEN; ++q) {
@@ -1330,7 +1329,7 @@ __device__ inline void gather_original(const DevPlan& pl, const KT* ke, int a0, 
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             if (t0 + u * stride < a1) {
                 const int r = rc[u] >> 16, col = rc[u] & 0xffff;
                 F[cpk(col, m) + r - col] = v[u];
@@ -1352,9 +1351,8 @@ __device__ inline void copy_in(T* dst, const T* src, int n, int first, int strid
             if (t0 + u * stride < n) dst[t0 + u * stride] = v[u];
     }
 }
-template <typename T>
+template <int U = 8, typename T>
 __device__ inline void extend_add_packed(const int32_t* ea, const T* Uc, int nu, int first, int stride, T* F) {
-    constexpr int U = 8;
     for (int t0 = first; t0 < nu; t0 += U * stride) {
         int e[U];
         T v[U];
@@ -1393,28 +1391,41 @@ __device__ void wave_front(const RveCtx& c, Smem& sm, int s, T* F, T* rl) {
     double* Dg = c.L + fr.D_off;
     double* yg = c.L + fr.y_off;
     const int tot = cpk(m, m);
-    for (int t = lane; t < tot; t += 64) F[t] = 0.0;
-    for (int t = lane; t < m * NRHS; t += 64) {
-        const int i = t % m, col = t / m;
-        rl[t] = (i < p) ? c.rhs[(int64_t)rows[i] * NRHS + col] : 0.0;
+    // the rhs rows (lane = row, m <= 64) are loaded first and stored after the
+    // gather, so their two round trips overlap the gather's; the gather takes
+    // eight strides per pass (one pass for the usual front), and a child's rhs
+    // rows travel with its update matrix, sixteen strides per pass
+    T rv[NRHS];
+    {
+        const int ri = rows[min(lane, m - 1)];  // (the value is used on the pivot rows only)
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) rv[q] = lane < p ? (T)c.rhs[(int64_t)ri * NRHS + q] : T(0);
     }
+    for (int t = lane; t < tot; t += 64) F[t] = 0.0;
     __builtin_amdgcn_wave_barrier();
     T* const D0 = rl + m * NRHS;
-    gather_original<NEN>(pl, ke_of<D, NRHS, T>(c), fr.asm_begin, fr.asm_end, lane, 64, F, m, D0);
+    gather_original<NEN, 8>(pl, ke_of<D, NRHS, T>(c), fr.asm_begin, fr.asm_end, lane, 64, F, m, D0);
+    if (lane < m)
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) rl[q * m + lane] = rv[q];
     __builtin_amdgcn_wave_barrier();
     for (int q = fr.child_begin; q < fr.child_end; ++q) {
         const DevFront ch = pl.fronts[pl.children[q]];
-        const int mc = ch.m - ch.p;
+        const int mc = ch.m - ch.p;  // < 64: the child is a wave front too
         const int32_t* rel = pl.relind + ch.relind_off;
         const T* Uc = reinterpret_cast<const T*>(c.U + ch.U_off);
         const int nu = cpk(mc, mc);
         const T* ruc = Uc + nu;
         const int32_t* ea = pl.ea_dst + ch.ea_off;
-        extend_add_packed(ea, Uc, nu, lane, 64, F);
-        for (int t = lane; t < mc * NRHS; t += 64) {
-            const int i = t % mc, col = t / mc;
-            rl[col * m + rel[i]] += ruc[(int64_t)col * mc + i];
-        }
+        const int li = max(min(lane, mc - 1), 0);
+        const int ci = mc > 0 ? rel[li] : 0;
+        T cr[NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) cr[k] = mc > 0 ? ruc[(int64_t)k * mc + li] : T(0);
+        extend_add_packed<16>(ea, Uc, nu, lane, 64, F);
+        if (lane < mc)
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) rl[k * m + ci] += cr[k];
         __builtin_amdgcn_wave_barrier();
     }
     for (int K = 0; K < p; K += 16) {
