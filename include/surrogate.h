@@ -103,7 +103,7 @@ int rve_surrogate_train(rve_surrogate h, const double* F, const double* P, const
 
 /* Calibrates the indicator at one precision from n judged points (P from
  * rve_solve_batch): relative stress error |P_s - P|_F / |P|_F on a grid of
- * 8^3 cells over the bounding box of the points' x, each cell reporting 1.5
+ * 8^3 cells over the bounding box of the points' x, each cell reporting 2
  * times the largest error found in it and its 26 neighbours (+inf with fewer
  * than 2 points in the cell).  Host-blocking. */
 int rve_surrogate_calibrate(rve_surrogate h, const double* F, const double* P, int64_t n, int32_t precision,

@@ -79,7 +79,10 @@ def fit_surrogate(n=16, radius=0.25, ratio=10.0, n_train=200000, n_calib=20000, 
     sol.set_F(F)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    sol.solve()
+    # training tangents from the direct Schur form at the converged state (exact
+    # to rounding; the default reuse of the last Newton factorization is exact
+    # to second order in the last Newton step, about 1e-11 here)
+    sol.solve(opts=rve.default_opts(flags=rve.FLAG_DIRECT_TANGENT))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ok = sol.status == 0

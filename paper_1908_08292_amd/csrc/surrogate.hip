@@ -49,7 +49,7 @@ constexpr int OFF_W1 = 0, OFF_B1 = 384, OFF_W2 = 512, OFF_B2 = 512 + 16384;
 constexpr int OFF_W3 = OFF_B2 + 128, OFF_B3 = OFF_W3 + 16384, OFF_W4 = OFF_B3 + 128;
 static_assert(OFF_W4 + 128 == NPARAM, "parameter layout");
 constexpr int GRID = 8;                // indicator cells per input axis
-constexpr double kIndicatorMargin = 1.5;  // indicator = margin x the largest calibration error nearby
+constexpr double kIndicatorMargin = 2.0;  // indicator = margin x the largest calibration error nearby
 constexpr int TRAIN_PTS = 15;          // data points per training tile (+ the origin)
 
 enum { MODE_EVAL = 0, MODE_TRAIN = 1 };
