@@ -261,6 +261,37 @@ __device__ inline void load_wl(const RveCtx& c, const double* w, int e, double* 
         for (int i = 0; i < D; ++i) wl[b * D + i] = w[nodes[b] * D + i];
 }
 
+// Mode 4 (2D): one work item's share of the condensation in the stationary
+// form, sum over the element rows t of X_t^T y_t + y_t^T X_t - X_t^T (k_t X_e)
+// (the assembled Y^T X + X^T Y - X^T K X), with X [dof][ldx] at xv (zero on the
+// pinned dofs) and the FP64 tangent and Y rows of the state, into acc.
+template <int D, int RPI>
+__device__ inline void cond_item(int row0, const double (&kr)[RPI][(1 << D) * D], const double (&yr)[RPI][D * D],
+                                 const double* xv, int ldx, const int* nodes, double* acc) {
+    constexpr int NEN = 1 << D, ND = NEN * D, D2 = D * D;
+#pragma unroll
+    for (int r = 0; r < RPI; ++r) {
+        const int row = row0 + r;
+        const double* xr = xv + ((int64_t)nodes[row / D] * D + row % D) * ldx;
+        double x[D2], kx[D2];
+#pragma unroll
+        for (int g = 0; g < D2; ++g) {
+            x[g] = xr[g];
+            kx[g] = 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < ND; ++q) {
+            const double* xq = xv + ((int64_t)nodes[q / D] * D + q % D) * ldx;
+#pragma unroll
+            for (int h = 0; h < D2; ++h) kx[h] += kr[r][q] * xq[h];
+        }
+#pragma unroll
+        for (int g = 0; g < D2; ++g)
+#pragma unroll
+            for (int h = 0; h < D2; ++h) acc[g * D2 + h] += x[g] * yr[r][h] + yr[r][g] * x[h] - x[g] * kx[h];
+    }
+}
+
 // Outputs of an element pass work item (element e, rows row0 .. row0 + RPI - 1):
 // mode 0 the internal forces and tangent rows (FP32 when c.ke32, the factors'
 // input); mode 2 the Y rows and, when c.ke32, the FP64 tangent rows at the
@@ -322,10 +353,14 @@ __device__ inline void element_store(const RveCtx& c, int e, int row0, int mode,
 //     Y_(a,i),(kL) = sum dN_a,J A_iJkL w|J|.
 template <int D, int NPT>
 __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP,
-                                              double* accA, const double* xv) {
+                                              double* accA, const double* xv, int ldx) {
     constexpr int NEN = 1 << D, ND = NEN * D, D2 = D * D, RPI = (D == 2) ? 2 : 1;
     const int nitems = c.ne * NEN * (D / RPI);
     const double wJ = sm.wJ;
+    constexpr int NCOND = D == 2 ? 16 : 1;  // mode 4 (2D): the condensation's share of this thread
+    double accC[NCOND];
+#pragma unroll
+    for (int q = 0; q < NCOND; ++q) accC[q] = 0.0;
     for (int it = threadIdx.x; it < nitems; it += NT) {
         int e, a, i0;
         if (D == 2) { e = it / NEN; a = it % NEN; i0 = 0; }
@@ -355,7 +390,7 @@ __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const d
             if (mode == 1) continue;
             double Pg[D2], Ag[D2 * D2];
             law_PA<D>(c.law, lam, mu, F, Pg, Ag);
-            if (mode == 2 && a == 0 && i0 == 0) {
+            if ((mode == 2 || mode == 4) && a == 0 && i0 == 0) {
 #pragma unroll
                 for (int q = 0; q < D2; ++q) accP[q] += Pg[q] * wJ;
 #pragma unroll
@@ -371,7 +406,7 @@ __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const d
                     for (int Jj = 0; Jj < D; ++Jj) f += Pg[i * D + Jj] * dNa[Jj];
                     fr[r] += f * wJ;
                 }
-                if (mode == 0 || mode == 3 || (mode == 2 && c.ke32)) {
+                if (mode == 0 || mode == 3 || mode == 4 || (mode == 2 && c.ke32)) {
 #pragma unroll
                     for (int b = 0; b < NEN; ++b) {
                         const double* dNb = &sm.dN[(gp * 8 + b) * 3];
@@ -386,7 +421,7 @@ __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const d
                         }
                     }
                 }
-                if (mode == 2) {
+                if (mode == 2 || mode == 4) {
 #pragma unroll
                     for (int k = 0; k < D; ++k)
 #pragma unroll
@@ -399,20 +434,36 @@ __device__ __noinline__ void element_pass_law(const RveCtx& c, Smem& sm, const d
                 }
             }
         }
+        if constexpr (D == 2) {
+            if (mode == 4) {
+                cond_item<D, RPI>(a * D + i0, kr, yr, xv, ldx, nodes, accC);
+                continue;
+            }
+        }
         element_store<D, RPI>(c, e, a * D + i0, mode, fr, kr, yr, xv, nodes);
     }
+    if constexpr (D == 2)
+        if (mode == 4)
+#pragma unroll
+            for (int q = 0; q < NCOND; ++q) accA[q] -= accC[q];
 }
 
 // Element pass of the neo-Hookean law.  mode 0: residual + tangent rows
 // (Newton); mode 1: J > 0 check only (on w); mode 2: final outputs (Pbar, <A>,
 // Y rows); mode 3: the FP64 tangent applied to xv, matrix-free (refinement of
-// FP32 solves).  Work item = (e, a) in 2D (rows i = 0,1), (e, a, i) in 3D.
+// FP32 solves); mode 4 (2D): Pbar and <A> minus the condensation in the
+// stationary form with X at xv (cond_item), nothing stored.  Work item = (e, a)
+// in 2D (rows i = 0,1), (e, a, i) in 3D.
 template <int D, int NPT>
 __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP,
-                                             double* accA, const double* xv) {
+                                             double* accA, const double* xv, int ldx) {
     constexpr int NEN = 1 << D, ND = NEN * D, RPI = (D == 2) ? 2 : 1;
     const int nitems = c.ne * NEN * (D / RPI);
     const double wJ = sm.wJ;
+    constexpr int NCOND = D == 2 ? 16 : 1;  // mode 4 (2D): the condensation's share of this thread
+    double accC[NCOND];
+#pragma unroll
+    for (int q = 0; q < NCOND; ++q) accC[q] = 0.0;
     for (int it = threadIdx.x; it < nitems; it += NT) {
         int e, a, i0;
         if (D == 2) { e = it / NEN; a = it % NEN; i0 = 0; }
@@ -441,7 +492,7 @@ __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const do
             if (!(J > 0.0)) { sm.flag = 1; continue; }
             if (mode == 1) continue;
             const double c1 = mu - 0.5 * lam * (J * J - 1.0), c2 = lam * J * J;
-            if (mode == 2 && a == 0 && i0 == 0) {
+            if ((mode == 2 || mode == 4) && a == 0 && i0 == 0) {
 #pragma unroll
                 for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -486,7 +537,7 @@ __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const do
                     for (int Jj = 0; Jj < D; ++Jj) FdN += F[i * D + Jj] * dNa[Jj];
                     fr[r] += (mu * FdN - c1 * ga[i]) * wJ;
                 }
-                if (mode == 0 || mode == 3 || (mode == 2 && c.ke32)) {
+                if (mode == 0 || mode == 3 || mode == 4 || (mode == 2 && c.ke32)) {
 #pragma unroll
                     for (int b = 0; b < NEN; ++b) {
                         double dab = 0.0;
@@ -497,7 +548,7 @@ __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const do
                             kr[r][b * D + k] += ((i == k ? mu * dab : 0.0) + c1 * ga[k] * g[b][i] + c2 * ga[i] * g[b][k]) * wJ;
                     }
                 }
-                if (mode == 2) {
+                if (mode == 2 || mode == 4) {
 #pragma unroll
                     for (int k = 0; k < D; ++k)
 #pragma unroll
@@ -507,22 +558,32 @@ __device__ __noinline__ void element_pass_nh(const RveCtx& c, Smem& sm, const do
                 }
             }
         }
+        if constexpr (D == 2) {
+            if (mode == 4) {
+                cond_item<D, RPI>(a * D + i0, kr, yr, xv, ldx, nodes, accC);
+                continue;
+            }
+        }
         element_store<D, RPI>(c, e, a * D + i0, mode, fr, kr, yr, xv, nodes);
     }
+    if constexpr (D == 2)
+        if (mode == 4)
+#pragma unroll
+            for (int q = 0; q < NCOND; ++q) accA[q] -= accC[q];
 }
 
 // the element pass of the RVE's law (neo-Hookean closed forms, or the generic
 // path) and element kind (2^d Gauss points of Q1 / hex8, or d! P1 simplices)
 template <int D>
 __device__ inline void element_pass(const RveCtx& c, Smem& sm, const double* w, int mode, double* accP, double* accA,
-                                    const double* xv = nullptr) {
+                                    const double* xv = nullptr, int ldx = 0) {
     constexpr int NQ1 = 1 << D, NP1 = D == 2 ? 2 : 6;
     if (c.elem == 0) {
-        if (c.law != 0) element_pass_law<D, NQ1>(c, sm, w, mode, accP, accA, xv);
-        else element_pass_nh<D, NQ1>(c, sm, w, mode, accP, accA, xv);
+        if (c.law != 0) element_pass_law<D, NQ1>(c, sm, w, mode, accP, accA, xv, ldx);
+        else element_pass_nh<D, NQ1>(c, sm, w, mode, accP, accA, xv, ldx);
     } else {
-        if (c.law != 0) element_pass_law<D, NP1>(c, sm, w, mode, accP, accA, xv);
-        else element_pass_nh<D, NP1>(c, sm, w, mode, accP, accA, xv);
+        if (c.law != 0) element_pass_law<D, NP1>(c, sm, w, mode, accP, accA, xv, ldx);
+        else element_pass_nh<D, NP1>(c, sm, w, mode, accP, accA, xv, ldx);
     }
 }
 
@@ -2485,29 +2546,37 @@ __global__ __launch_bounds__(NT, 512 / NT) void rve_solve_kernel(SolveArgs a) {
         double* Pout = a.P + (int64_t)rve * D2;
         double* Aout = a.A ? a.A + (int64_t)rve * D2 * D2 : nullptr;
         if (status == 0) {
+            // the condensation from X = K'^-1 Y', solved with the last Newton step
+            // (still in the rhs buffer, columns 1..d^2): used where the last
+            // factorized residual was within 1e-4 of the initial one, so the
+            // stationary form's error (second order in that step) stays far
+            // below the tangent's tolerance; in 2D the element pass adds it to
+            // the average tangent itself (mode 4)
+            const bool stale = Aout && spec && !capped && rprev <= 1e-4 * r0;
+            const bool stale2 = stale && D == 2;
             double accP[D2], accA[D2 * D2];
 #pragma unroll
             for (int q = 0; q < D2; ++q) accP[q] = 0;
 #pragma unroll
             for (int q = 0; q < D2 * D2; ++q) accA[q] = 0;
-            element_pass<D>(c, sm, c.w, 2, accP, accA);
+            element_pass<D>(c, sm, c.w, stale2 ? 4 : 2, accP, accA, stale2 ? c.rhs + 1 : nullptr, NSPEC);
             __syncthreads();
             block_sum<D2>(accP, sm);
             if (threadIdx.x < D2) Pout[threadIdx.x] = sm.outv[threadIdx.x];
             __syncthreads();
-            if (Aout) {
+            if (Aout && stale2) {
+                block_sum<D2 * D2>(accA, sm);
+                if (threadIdx.x < D2 * D2) Aout[threadIdx.x] = sm.outv[threadIdx.x];
+                __syncthreads();
+            } else if (Aout) {
                 block_sum<D2 * D2>(accA, sm);
                 double Aavg = threadIdx.x < D2 * D2 ? sm.outv[threadIdx.x] : 0.0;
                 __syncthreads();
-                // the condensation: with the Y columns in the last Newton
-                // factorization (state w_prev, one Newton step before w), X from
-                // the last Newton solve (still in the rhs buffer) and the
-                // stationary form below, refined while ||Y - K X||_F >
-                // 1e-4 ||Y||_F (at most twice); otherwise a factorization at w:
-                // FP64 (direct Schur form below, no refinement) for global-front
-                // plans and for LDS plans whose FP64 front region keeps the
-                // occupancy, else in the factor type
-                const bool stale = spec && !capped;
+                // otherwise (3D) the stationary form assembled below, refined
+                // while ||Y - K X||_F > 1e-4 ||Y||_F (at most twice), or a
+                // factorization at w: FP64 (direct Schur form below, no
+                // refinement) for global-front plans and for LDS plans whose
+                // FP64 front region keeps the occupancy, else in the factor type
                 const bool tan64 = !stale && (!IR || !c.plan->lds_ok || a.tan64);
                 // Y of w: into the rhs buffer for a factorization at w, else
                 // beside X (ir2), X then moved into the element-Y slots
