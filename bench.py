@@ -547,7 +547,9 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(meta["workload"], head),
                      "kernel": f"rve_solve_kernel<{d}>", "flops_per_launch": flops,
-                     "flops_counted": "LDL^T factorizations + triangular solves from the symbolic plan"},
+                     "flops_counted": "LDL^T factorizations + triangular solves from the symbolic plan: one "
+                                      "factorization per Newton step (the condensation reuses the last one), "
+                                      "none at the converged state"},
     }
     if "fp32ir" in timed and head != "fp32ir":
         t = timed["fp32ir"]
