@@ -394,3 +394,26 @@ def test_condensation_reuse_guard_at_loose_tolerance(prec):
         mu_max = oracle.two_phase_lame(wl.ratio[b])[:, 1].max()
         assert rel(reuse["P"][b], ref["P"], 1e-12 * mu_max) <= (P_TOL if prec == "fp64" else 1e-6)
         assert rel(reuse["A"][b], ref["A"], 1e-12 * mu_max) <= A_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_parity_2d_global_fronts(prec):
+    """2D meshes from 36 x 36 on have fronts beyond the LDS (largest 210 rows at
+    36, 234 at 40) and take the global-front path, with the condensation reused
+    from the last Newton factorization by default: parity with the oracle, and
+    agreement with the factorization at the converged state."""
+    torch_cuda()
+    d, B = 2, 6
+    wl = workloads.rve2d(B, seed=4400)
+    wl.n[:] = [36, 40, 36, 40, 36, 40]
+    assert not rve.plan_schedule(2, 36)["wave"].any() and len(rve.plan_schedule(2, 40)["steps"]) == 0
+    p = rve.PREC_FP32_IR if prec == "fp32ir" else rve.PREC_FP64
+    print(f"case 2d n={list(wl.n)} {prec}: global fronts", flush=True)
+    reuse = run_gpu(d, wl.n, wl.radius, wl.ratio, wl.F, opts=rve.default_opts(precision=p))
+    direct = run_gpu(d, wl.n, wl.radius, wl.ratio, wl.F,
+                     opts=rve.default_opts(precision=p, flags=rve.FLAG_DIRECT_TANGENT))
+    assert np.all(reuse["status"] == 0) and np.all(direct["status"] == 0)
+    dA = max(rel(reuse["A"][b], direct["A"][b], 1e-300) for b in range(B))
+    print(f"  max rel difference of A (reused vs direct) {dA:.2e}", flush=True)
+    assert dA <= 1e-8
+    (compare if prec == "fp64" else compare_loose_iters)(d, wl.n, wl.radius, wl.ratio, wl.F, reuse)
